@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the ISM hot path on one MI355X.
+
+One step = one ``ism_simulate`` call over the whole workload (host planning,
+axis tables, shell enumeration + windowed-sinc accumulation, ordered partial
+reduction), with positions, output and workspace already resident in HBM.
+Prints one JSON line: image-source sinc taps/s (G/s) with RIRs/s, the roofline
+of the tap-accumulation kernel (timed live with HIP events around each of its
+launches) and the FP64 CPU oracle's rate on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "image-source sinc taps/s (G/s) + RIRs/s, FP32 vs FP16; p50/p99 serving latency"
+FLOP_PER_TAP = 18          # frozen accounting of one windowed-sinc tap
+FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 FLOP/clk)
+
+
+class _HipEvents:
+    """hipEvent_t handles from the HIP runtime torch already loaded."""
+
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        ev = ctypes.c_void_p()
+        if self.hip.hipEventCreate(ctypes.byref(ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return ev.value
+
+    def elapsed_ms(self, a, b) -> float:
+        ms = ctypes.c_float()
+        if self.hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a), ctypes.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def destroy(self, ev):
+        self.hip.hipEventDestroy(ctypes.c_void_p(ev))
+
+
+def cpu_baseline(w, n_rcv_sample: int):
+    """FP64 oracle on the first ``n_rcv_sample`` receivers of the workload (full RIRs)."""
+    from oracle import oracle as orc
+
+    orc.build()
+    beta = orc.beta_from_t60(w.room, w.t60)
+    if w.beta_jitter is not None:
+        beta = np.minimum(beta * np.asarray(w.beta_jitter), 0.999)
+    n = orc.n_img_for_time(w.room, w.c, w.t_max)
+    args = (w.room, beta, n, w.c, w.fs, w.t_max, w.t_w)
+    rcv = w.rcv[:n_rcv_sample]
+    threads = max(1, min(os.cpu_count() or 1, 16, rcv.shape[0] * w.src.shape[0]))
+    taps = orc.count_taps(*args, w.src, rcv)
+    t0 = time.perf_counter()
+    orc.rir(*args, w.src, rcv, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": taps / dt / 1e9, "unit": "G taps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{w.src.shape[0]} source x {rcv.shape[0]} receivers of the workload, full RIRs "
+                      f"({taps} taps, {dt:.2f} s wall, {threads} threads)",
+            "rirs_per_s": rcv.shape[0] * w.src.shape[0] / dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="room_32_receivers",
+                    choices=["room_32_receivers", "single_rir", "large_room_uca"])
+    ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the ISM path here does not "
+              "shard across GPUs.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1810_11359_amd import ism, workloads
+
+    w = workloads.WORKLOADS[args.workload](0)
+    room = ism.room_for(w)
+    sim = ism.Simulator(room, w.src, w.rcv)
+    n_rir = sim.n_src * sim.n_rcv
+    taps = ism.count_taps(room, w.src, w.rcv)
+    hip = _HipEvents()
+    ev_a = [hip.create() for _ in range(args.steps)]
+    ev_b = [hip.create() for _ in range(args.steps)]
+
+    for _ in range(args.warmup):
+        sim.run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        sim.run(ev_start=ev_a[i], ev_stop=ev_b[i])
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = e0.elapsed_time(e1)
+    kern_ms = [hip.elapsed_ms(a, b) for a, b in zip(ev_a, ev_b)]
+    for ev in ev_a + ev_b:
+        hip.destroy(ev)
+
+    ms_step = ms_total / args.steps
+    value = taps / (ms_step / 1e3) / 1e9
+    kmean = float(np.mean(kern_ms))
+    achieved = FLOP_PER_TAP * taps / (kmean / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "G taps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "room_m": list(map(float, w.room)), "t60_s": w.t60, "fs": w.fs,
+                   "t_w_s": w.t_w, "n_src": int(sim.n_src), "n_rcv": int(sim.n_rcv), "n_samples": room.n_samples,
+                   "n_img": list(room.n_img), "taps_per_step": int(taps), "parallelism": "single GPU"},
+        "rirs_per_s": n_rir / (ms_step / 1e3),
+        "wall_s_timed": wall,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                     "kernel": "accumulate_kernel", "kernel_ms_mean": kmean,
+                     "kernel_ms_p50": float(np.median(kern_ms)), "flop_per_tap": FLOP_PER_TAP},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, sim.n_rcv))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,144 @@
+/*
+ * ism.h - C ABI of the MI355X (gfx950) Image Source Method library (libism.so).
+ *
+ * The library computes room impulse responses (RIRs) of a shoebox room with the
+ * Image Source Method of Allen and Berkley as restated in the gpuRIR paper
+ * (Diaz-Guerra et al.), Sec. 2.1: for every (source, receiver) pair it sums,
+ * over the lattice of image sources, a Hann-windowed sinc (Sec. 2.2, Eq. (6))
+ * of amplitude beta_n / (4 pi d_n) (Eq. (4)) delayed by d_n / c (Eq. (3)).
+ *
+ * Conventions shared by every entry point:
+ *  - Plain C types only. "host" pointers are CPU memory, "device" pointers are
+ *    memory of the current HIP device. The caller owns every buffer; the
+ *    library allocates nothing in the simulate calls and keeps no global
+ *    mutable state, so calls are reentrant.
+ *  - Every call returns an int status: ISM_OK (0) or a negative ISM_E_* code.
+ *    All argument checks run before any launch; a call that fails them leaves
+ *    every output untouched. No C++ exception crosses this boundary.
+ *  - GPU calls are asynchronous on the given HIP stream (NULL = the default
+ *    stream). A launch failure is reported as ISM_E_DEVICE.
+ */
+#ifndef ISM_H
+#define ISM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISM_ABI_VERSION 1
+
+enum {
+  ISM_OK = 0,
+  ISM_E_INVALID_ARG = -1,    /* null pointer, non-positive size, NaN, ...          */
+  ISM_E_INFEASIBLE_T60 = -2, /* Sabine's formula needs an absorption above 1       */
+  ISM_E_OUT_OF_ROOM = -3,    /* a position not strictly inside the room            */
+  ISM_E_WORKSPACE = -4,      /* workspace missing or smaller than required         */
+  ISM_E_DEVICE = -5,         /* HIP launch or runtime error                        */
+  ISM_E_TOO_LARGE = -6,      /* problem exceeds a documented limit (see below)     */
+  ISM_E_UNSUPPORTED = -7     /* valid request this build does not implement        */
+};
+
+/* Arithmetic used for the windowed-sinc taps. Geometry, delays and the
+ * accumulation are FP32 in every mode. */
+typedef enum { ISM_FP32 = 0, ISM_FP16 = 1, ISM_BF16 = 2 } ism_precision;
+
+/* One shoebox room and its simulation parameters (Sec. 2.1, Sec. 4). */
+typedef struct {
+  double room[3];  /* Lx, Ly, Lz [m], > 0                                            */
+  double beta[6];  /* reflection coefficients in [-1, 1], order x0, x1, y0, y1, z0, z1;
+                      x0 is the wall in the plane x = 0, x1 the wall in x = Lx       */
+  int n_img[3];    /* images per dimension N_a >= 1; lattice index n_a runs over
+                      ceil(-N_a/2) <= n_a < ceil(N_a/2) (Sec. 2.1)                  */
+  double c;        /* speed of sound [m/s], > 0                                     */
+  double fs;       /* sampling rate [Hz], > 0                                       */
+  double t_max;    /* RIR length [s], > 0; nS = ism_n_samples(t_max, fs)            */
+  double t_w;      /* Hann window length T_w of Eq. (6) [s], > 0; W = t_w*fs samples,
+                      cut-off frequency fs/2                                        */
+} ism_room;
+
+/* Limits of this build (ISM_E_TOO_LARGE beyond them). */
+#define ISM_MAX_SAMPLES (256 * 1024) /* nS per RIR                                     */
+#define ISM_MAX_N_IMG 2048           /* N_a per axis                                   */
+#define ISM_MAX_PAIRS (1 << 22)      /* n_src * n_rcv per call                         */
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char *ism_status_string(int status);
+
+/* ISM_ABI_VERSION of the loaded library. */
+int ism_abi_version(void);
+
+/* ---- Host helpers (Sec. 4: helper functions of the library) ---------------- */
+
+/* Uniform reflection coefficient for all six walls giving reverberation time
+ * t60 by Sabine's formula (Sec. 2.2, Eq. (7)) with alpha = 1 - beta^2:
+ * beta = sqrt(1 - 0.161 V / (S t60)). beta_out: host [6].
+ * ISM_E_INFEASIBLE_T60 when 0.161 V / (S t60) > 1. */
+int ism_beta_from_t60(const double room[3], double t60, double beta_out[6]);
+
+/* Images per dimension so that no image closer than c*t is left out of the
+ * lattice: N_a = 4 ceil(c t / (2 L_a)) + 2. n_out: host [3]. */
+int ism_n_img_for_time(const double room[3], double c, double t, int n_out[3]);
+
+/* Time at which the exponential energy decay of reverberation time t60
+ * reaches att_db decibels of attenuation: t60 * att_db / 60. */
+int ism_time_for_attenuation(double t60, double att_db, double *t_out);
+
+/* Samples per RIR: ceil(t_max*fs), snapped to the nearest integer when t_max*fs
+ * lies within 1e-9 (relative) of it. Returns -1 for invalid input. */
+int64_t ism_n_samples(double t_max, double fs);
+
+/* ---- Validation -------------------------------------------------------------- */
+
+/* Checks every field of *room (finite, positive sizes, |beta| <= 1, limits). */
+int ism_check_room(const ism_room *room);
+
+/* Checks host positions src [n_src][3], rcv [n_rcv][3] (float32): each strictly
+ * inside the room (0 < p_a < L_a) -> else ISM_E_OUT_OF_ROOM; a source equal to
+ * a receiver -> ISM_E_INVALID_ARG (its direct path has zero length). */
+int ism_check_positions(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv);
+
+/* ---- Work measure -------------------------------------------------------------- */
+
+/* Exact number of window taps the simulation evaluates, summed over all pairs:
+ * sum over (src, rcv, lattice image) of #{k in [0, nS) : |k - x| < W/2},
+ * x = d fs / c, computed on the host in double precision from host positions. */
+int ism_count_taps(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                   int64_t *taps_out);
+
+/* ---- GPU simulation -------------------------------------------------------------- */
+
+/* Device workspace (bytes) that ism_simulate needs for this room, pair count
+ * and precision. The size depends only on these arguments. */
+int ism_workspace_size(const ism_room *room, int n_src, int n_rcv, int precision, size_t *bytes);
+
+/* RIRs of every (source, receiver) pair of one room.
+ *   src   device float32 [n_src][3], rcv device float32 [n_rcv][3] (positions [m]);
+ *   out   device float32 [n_src][n_rcv][nS], row-major, fully overwritten;
+ *   ws    device workspace of at least ism_workspace_size() bytes (contents
+ *         need not be initialised; overwritten);
+ *   stream  hipStream_t or NULL.
+ * Positions live on the device, so they are checked on the device: a pair whose
+ * source or receiver is not strictly inside the room, or whose source equals
+ * its receiver, gets an RIR filled with NaN (call ism_check_positions on a host
+ * copy to get a status instead). Taps are summed in FP64 and rounded to FP32
+ * once, so repeated calls agree to within one FP32 rounding of each sample.
+ * Asynchronous; out and ws must stay valid until the stream reaches it. */
+int ism_simulate(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                 int precision, float *out, void *ws, size_t ws_bytes, void *stream);
+
+/* ism_simulate, plus per-kernel timing: records the caller's HIP events
+ * ev_start immediately before and ev_stop immediately after the tap
+ * accumulation kernel (the dominant kernel), on the same stream. Either event
+ * may be NULL. The events are caller-owned (hipEventCreate); the library only
+ * records them. Same arguments, checks and results as ism_simulate. */
+int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                       int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
+                       void *ev_stop);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

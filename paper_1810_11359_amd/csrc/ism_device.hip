@@ -1,0 +1,508 @@
+// HIP kernels of the Image Source Method for gfx950 (MI355X).
+//
+// Three kernels per call:
+//   tables_kernel      per (RIR, axis, lattice index): displacement of the image
+//                      coordinate from the receiver in samples (float-float) and
+//                      the axis factor of the reflection gain (Sec. 2.1, Eq. (1)
+//                      and the gain rule below it). Also flags invalid pairs.
+//   accumulate_kernel  per work item (RIR, output tile, slab of the image shell):
+//                      enumerates exactly the lattice images whose window can
+//                      reach the tile, computes each image's delay and amplitude
+//                      (Eq. (2)-(4)) and adds its Hann-windowed-sinc taps (Eq. (6))
+//                      into an LDS tile with FP64 LDS atomics (Eq. (5)).
+//   reduce_kernel      sums, in a fixed order, the partial tiles of tiles that
+//                      were split over several work items.
+//
+// Arithmetic is FP32 only; delays use error-free transformations so that the
+// fractional delay keeps ~1e-7 sample accuracy at 1e5-sample distances.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "ism_internal.h"
+
+namespace ism {
+
+// ---------------------------------------------------------------------------
+// Float-float building blocks (Dekker / Knuth error-free transformations).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void fast_two_sum(float a, float b, float &s, float &e) {  // |a| >= |b|
+  s = a + b;
+  e = b - (s - a);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float &p, float &e) {
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+__device__ __forceinline__ void ff_mul(float ah, float al, float bh, float bl, float &ch, float &cl) {
+  float p, e;
+  two_prod(ah, bh, p, e);
+  e = __builtin_fmaf(ah, bl, e);
+  e = __builtin_fmaf(al, bh, e);
+  fast_two_sum(p, e, ch, cl);
+}
+// b^e for e >= 0 by binary powering in float-float (0^0 = 1).
+__device__ float ff_pow(float b, int e) {
+  float rh = 1.0f, rl = 0.0f, bh = b, bl = 0.0f;
+  while (e > 0) {
+    if (e & 1) ff_mul(rh, rl, bh, bl, rh, rl);
+    e >>= 1;
+    if (e) ff_mul(bh, bl, bh, bl, bh, bl);
+  }
+  return rh + rl;
+}
+// a^2 of a float-float value, as float-float.
+__device__ __forceinline__ void ff_sq(float h, float l, float &sh, float &sl) {
+  two_prod(h, h, sh, sl);
+  sl = __builtin_fmaf(2.0f * h, l, sl);
+}
+// (ah, al) - (bh, bl), renormalised.
+__device__ __forceinline__ void ff_sub(float ah, float al, float bh, float bl, float &ch, float &cl) {
+  float s, e;
+  two_sum(ah, -bh, s, e);
+  e += al - bl;
+  fast_two_sum(s, e, ch, cl);
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time constants of the tap loop (evaluated in double by the compiler).
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr double cx_sin(double x) {  // |x| <= pi: Taylor series to double accuracy
+  double term = x, sum = x;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+// For an even integer window of WT samples and fractional delay f in (0, 1),
+// the taps of one image are j = JLO .. JLO + WT - 1 (JLO = 1 - WT/2) relative to
+// k0 = floor(x). With v = j - f:
+//   sin(pi v) = sigma_j sin(pi f),            sigma_j = (-1)^(j+1)
+//   1 + cos(2 pi v / W) = 1 + cos(th_j) cos(phi) + sin(th_j) sin(phi),
+//                         th_j = 2 pi j / W, phi = 2 pi f / W,
+// so tap_j = [C/2 + (C/2 cos phi) cos th_j + (C/2 sin phi) sin th_j] / (sigma_j (j - f))
+// with C = A sin(pi f) / pi. Only sigma_j, sigma_j j, cos th_j, sin th_j depend on j.
+template <int WT>
+struct TapConsts {
+  float sig[WT], sig_j[WT], cth[WT], sth[WT];
+};
+template <int WT>
+constexpr TapConsts<WT> make_tap_consts() {
+  TapConsts<WT> t{};
+  for (int jj = 0; jj < WT; ++jj) {
+    const int j = jj + 1 - WT / 2;
+    const double sg = (j % 2 == 0) ? -1.0 : 1.0;
+    const double th = 2.0 * kPi * j / WT;  // in (-pi, pi]
+    t.sig[jj] = (float)sg;
+    t.sig_j[jj] = (float)(sg * j);
+    t.cth[jj] = (float)cx_cos(th);
+    t.sth[jj] = (float)cx_sin(th);
+  }
+  return t;
+}
+
+// sin(pi h) / pi for h in [0, 1/2]: Taylor series of sin to the h^13 term
+// (truncation < 2e-10 at h = 1/2), Horner in h^2.
+__device__ __forceinline__ float sinpi_over_pi(float h) {
+  constexpr float c1 = (float)(-kPi * kPi / 6.0);
+  constexpr float c2 = (float)(kPi * kPi * kPi * kPi / 120.0);
+  constexpr float c3 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi / 5040.0);
+  constexpr float c4 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 362880.0);
+  constexpr float c5 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 39916800.0);
+  constexpr float c6 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 6227020800.0);
+  const float u = h * h;
+  float p = __builtin_fmaf(u, c6, c5);
+  p = __builtin_fmaf(u, p, c4);
+  p = __builtin_fmaf(u, p, c3);
+  p = __builtin_fmaf(u, p, c2);
+  p = __builtin_fmaf(u, p, c1);
+  p = __builtin_fmaf(u, p, 1.0f);
+  return h * p;
+}
+// cos and sin of a small angle |phi| <= 0.2 (Taylor, truncation < 3e-12).
+__device__ __forceinline__ void small_sincos(float phi, float &s, float &c) {
+  const float u = phi * phi;
+  float pc = __builtin_fmaf(u, (float)(1.0 / 40320.0), (float)(-1.0 / 720.0));
+  pc = __builtin_fmaf(u, pc, (float)(1.0 / 24.0));
+  pc = __builtin_fmaf(u, pc, -0.5f);
+  c = __builtin_fmaf(u, pc, 1.0f);
+  float ps = __builtin_fmaf(u, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
+  ps = __builtin_fmaf(u, ps, (float)(1.0 / 120.0));
+  ps = __builtin_fmaf(u, ps, (float)(-1.0 / 6.0));
+  s = __builtin_fmaf(phi * u, ps, phi);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: per-RIR axis tables.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void tables_kernel(RoomArgs ra, const float *__restrict__ src,
+                                                     const float *__restrict__ rcv, AxisEntry *__restrict__ tab,
+                                                     int *__restrict__ valid, int n_rir) {
+  const int64_t total = (int64_t)n_rir * ra.n_tab;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+       gid += (int64_t)gridDim.x * blockDim.x) {
+    const int rir = (int)(gid / ra.n_tab);
+    const int e = (int)(gid % ra.n_tab);
+    const int si = rir / ra.n_rcv, ri = rir % ra.n_rcv;
+    const int a = e < ra.off[1] ? 0 : (e < ra.off[2] ? 1 : 2);
+    const int n = ra.lo[a] + (e - ra.off[a]);
+    const float s = src[3 * si + a], r = rcv[3 * ri + a];
+    // Eq. (1): even n -> n L + s, odd n -> (n + 1) L - s.
+    const bool odd = (n & 1) != 0;
+    const float m = (float)(odd ? n + 1 : n);
+    float p, pe;
+    two_prod(m, ra.L_hi[a], p, pe);
+    pe = __builtin_fmaf(m, ra.L_lo[a], pe);
+    float t, te;
+    two_sum(odd ? -s : s, -r, t, te);  // exact
+    float u, ue;
+    two_sum(p, t, u, ue);
+    ue += pe + te;
+    fast_two_sum(u, ue, u, ue);
+    // times fs / c: displacement in samples
+    float v, ve;
+    two_prod(u, ra.q_hi, v, ve);
+    ve = __builtin_fmaf(u, ra.q_lo, ve);
+    ve = __builtin_fmaf(ue, ra.q_hi, ve);
+    fast_two_sum(v, ve, v, ve);
+    // Gain factor: the path from image n crosses |floor(n/2)| copies of the wall
+    // at 0 and |ceil(n/2)| copies of the wall at L along this axis.
+    const int e0 = abs(n >> 1), e1 = abs((n + 1) >> 1);
+    const float g = ff_pow(ra.beta[2 * a], e0) * ff_pow(ra.beta[2 * a + 1], e1);
+    tab[gid] = AxisEntry{v, ve, g, 0.0f};
+    if (e == 0) {
+      bool ok = true, same = true;
+      for (int b = 0; b < 3; ++b) {
+        const float sb = src[3 * si + b], rb = rcv[3 * ri + b];
+        ok = ok && sb > 0.0f && (sb - ra.L_hi[b]) < ra.L_lo[b] && rb > 0.0f && (rb - ra.L_hi[b]) < ra.L_lo[b];
+        same = same && (sb == rb);
+      }
+      valid[rir] = (ok && !same) ? 1 : 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// Smallest i in [0, n] with t[i].d_hi >= b (t[].d_hi is strictly increasing).
+__device__ __forceinline__ int first_ge(const AxisEntry *__restrict__ t, int n, float b) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (t[mid].d_hi < b) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2: enumeration of the image shell of one tile + windowed-sinc taps.
+// ---------------------------------------------------------------------------
+constexpr int QCAP = 512;  // per-wave queue of candidate images
+
+template <int WT, int NW>
+__global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
+                                                             const AxisEntry *__restrict__ tab_all,
+                                                             const int *__restrict__ valid, float *__restrict__ out,
+                                                             float *__restrict__ part) {
+  constexpr int JLO = 1 - WT / 2;
+  constexpr int JHI = WT / 2;
+  constexpr int MARGIN = WT;
+  constexpr int ACC = TILE + 2 * MARGIN;
+  constexpr TapConsts<WT> K = make_tap_consts<WT>();
+
+  __shared__ double acc[ACC];
+  __shared__ uint32_t queue[NW][QCAP];
+  __shared__ float col_sh[NW][64], col_sl[NW][64], col_g[NW][64];
+  __shared__ int nx_pref[NW][64], nx_nylo[NW][64];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+
+  // ---- work item -> (tile, rir, chunk)
+  const uint32_t item = blockIdx.x;
+  int pos = 0;
+  {
+    int lo = 0, hi = pa.n_tiles;  // largest pos with first_item[pos] <= item
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pa.first_item[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    pos = lo;
+  }
+  const int tile = pa.n_tiles - 1 - pos;
+  const int C = pa.chunks[tile];
+  const uint32_t rel = item - pa.first_item[pos];
+  const int rir = (int)(rel / (uint32_t)C);
+  const int c = (int)(rel % (uint32_t)C);
+  const int T0 = tile * TILE;
+  const int T1 = min(T0 + TILE, ra.n_samples);
+  float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + T0 : part + (size_t)item * TILE;
+
+  if (!valid[rir]) {
+    for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) dst[k] = __builtin_nanf("");
+    return;
+  }
+  const AxisEntry *__restrict__ tab = tab_all + (size_t)rir * ra.n_tab;
+  const AxisEntry *__restrict__ tx = tab + ra.off[0];
+  const AxisEntry *__restrict__ ty = tab + ra.off[1];
+  const AxisEntry *__restrict__ tz = tab + ra.off[2];
+
+  for (int i = threadIdx.x; i < ACC; i += NW * 64) acc[i] = 0.0;
+
+  // Images whose window reaches the tile have delay x in (T0 - W/2, T1 - 1 + W/2);
+  // the enumeration bounds are widened by one sample on each side and every
+  // candidate is then filtered exactly on its integer delay.
+  const float R1 = (float)(T1 - 1) + ra.half_w + 2.0f;
+  const float R0 = (float)T0 - ra.half_w - 2.0f;
+  float r1h, r1l, r0h = 0.0f, r0l = 0.0f;
+  two_prod(R1, R1, r1h, r1l);
+  if (R0 > 0.0f) two_prod(R0, R0, r0h, r0l);
+
+  // Slab of the shell along the x displacement owned by this chunk.
+  float dlo = -INFINITY, dhi = INFINITY;
+  if (c > 0) dlo = -R1 + (2.0f * R1) * ((float)c / (float)C);
+  if (c < C - 1) dhi = -R1 + (2.0f * R1) * ((float)(c + 1) / (float)C);
+  const int nx_a = max(first_ge(tx, ra.N[0], dlo), first_ge(tx, ra.N[0], -R1));
+  const int nx_b = min(first_ge(tx, ra.N[0], dhi), first_ge(tx, ra.N[0], R1));
+  __syncthreads();
+
+  for (int nx0 = nx_a; nx0 < nx_b; nx0 += 64) {
+    // lanes = x indices: y range of the columns that reach the outer sphere
+    const int nxi = nx0 + lane;
+    int ny_lo = 0, ny_cnt = 0;
+    if (nxi < nx_b) {
+      const AxisEntry ex = tx[nxi];
+      float qh, ql, rh, rl;
+      ff_sq(ex.d_hi, ex.d_lo, qh, ql);
+      ff_sub(r1h, r1l, qh, ql, rh, rl);
+      if (rh > 0.0f) {
+        const float R = __builtin_sqrtf(rh) + 1.0f;
+        ny_lo = first_ge(ty, ra.N[1], -R);
+        ny_cnt = first_ge(ty, ra.N[1], R) - ny_lo;
+      }
+    }
+    const int incl_y = wave_incl_scan(ny_cnt);
+    const int ncols = __builtin_amdgcn_readlane(incl_y, 63);
+    nx_pref[wave][lane] = incl_y - ny_cnt;
+    nx_nylo[wave][lane] = ny_lo;
+    wave_sync();
+
+    for (int cb = wave; cb * 64 < ncols; cb += NW) {
+      // lanes = columns (nx, ny): z ranges of the shell
+      const int g = cb * 64 + lane;
+      int z1 = 0, n1 = 0, z2 = 0, n2 = 0;
+      if (g < ncols) {
+        int i = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+          if (i + step < 64 && nx_pref[wave][i + step] <= g) i += step;
+        const AxisEntry ex = tx[nx0 + i];
+        const AxisEntry ey = ty[nx_nylo[wave][i] + (g - nx_pref[wave][i])];
+        float ah, al, bh, bl, sh, sl;
+        ff_sq(ex.d_hi, ex.d_lo, ah, al);
+        ff_sq(ey.d_hi, ey.d_lo, bh, bl);
+        two_sum(ah, bh, sh, sl);
+        sl += al + bl;
+        fast_two_sum(sh, sl, sh, sl);
+        col_sh[wave][lane] = sh;
+        col_sl[wave][lane] = sl;
+        col_g[wave][lane] = ex.gain * ey.gain;
+        float rh, rl;
+        ff_sub(r1h, r1l, sh, sl, rh, rl);
+        if (rh > 0.0f) {
+          const float zmax = __builtin_sqrtf(rh) + 1.0f;
+          float zmin = 0.0f;
+          if (R0 > 0.0f) {
+            float hh, hl;
+            ff_sub(r0h, r0l, sh, sl, hh, hl);
+            if (hh > 0.0f) zmin = fmaxf(__builtin_sqrtf(hh) - 1.0f, 0.0f);
+          }
+          if (zmin > 0.0f) {
+            z1 = first_ge(tz, ra.N[2], -zmax);
+            n1 = first_ge(tz, ra.N[2], -zmin) - z1;
+            z2 = first_ge(tz, ra.N[2], zmin);
+            n2 = first_ge(tz, ra.N[2], zmax) - z2;
+          } else {
+            z1 = first_ge(tz, ra.N[2], -zmax);
+            n1 = first_ge(tz, ra.N[2], zmax) - z1;
+          }
+        }
+      }
+      const int cnt = n1 + n2;
+      const int incl = wave_incl_scan(cnt);
+      const int total = __builtin_amdgcn_readlane(incl, 63);
+      const int excl = incl - cnt;
+
+      for (int q0 = 0; q0 < total; q0 += QCAP) {
+        // lanes write their candidates with wave-wide index in [q0, q0 + QCAP)
+        const int i_lo = max(0, q0 - excl), i_hi = min(cnt, q0 + QCAP - excl);
+        for (int i = i_lo; i < i_hi; ++i) {
+          const int nz = (i < n1) ? z1 + i : z2 + (i - n1);
+          queue[wave][excl + i - q0] = ((uint32_t)lane << 16) | (uint32_t)nz;
+        }
+        wave_sync();
+        const int qn = min(QCAP, total - q0);
+        for (int b0 = 0; b0 < qn; b0 += 64) {
+          // lanes = images
+          bool keep = false;
+          float f = 0.0f, C2 = 0.0f, CP = 0.0f, CQ = 0.0f;
+          int base = 0;
+          if (b0 + lane < qn) {
+            const uint32_t ent = queue[wave][b0 + lane];
+            const int cl = (int)(ent >> 16);
+            const int nz = (int)(ent & 0xffffu);
+            const AxisEntry ez = tz[nz];
+            float ph, pl, s, se, Sh, Sl;
+            ff_sq(ez.d_hi, ez.d_lo, ph, pl);
+            two_sum(col_sh[wave][cl], ph, s, se);
+            se += col_sl[wave][cl] + pl;
+            fast_two_sum(s, se, Sh, Sl);
+            // x = sqrt(S) in samples (Eq. (2)-(3)): one Newton correction in float-float
+            const float x0 = __builtin_amdgcn_sqrtf(Sh);
+            const float rx = __builtin_amdgcn_rcpf(x0);
+            const float xl = (__builtin_fmaf(-x0, x0, Sh) + Sl) * (0.5f * rx);
+            float kf = floorf(x0);
+            f = (x0 - kf) + xl;
+            if (f < 0.0f) {
+              f += 1.0f;
+              kf -= 1.0f;
+            }
+            if (f >= 1.0f) {
+              f -= 1.0f;
+              kf += 1.0f;
+            }
+            const int k0 = (int)kf;
+            base = k0 + JLO - T0 + MARGIN;
+            keep = (x0 < 1.0e9f) && (k0 + JHI >= T0) && (k0 + JLO <= T1 - 1) && base >= 0 && base + WT <= ACC;
+            // Eq. (4) amplitude and the per-image factors of the taps
+            const float A = col_g[wave][cl] * ez.gain * ra.kappa * rx;
+            f = fmaxf(f, 0x1p-100f);
+            const float Cc = A * sinpi_over_pi(fminf(f, 1.0f - f));
+            float sp, cp;
+            small_sincos(f * ra.two_pi_over_w, sp, cp);
+            C2 = 0.5f * Cc;
+            CP = C2 * cp;
+            CQ = C2 * sp;
+          }
+          if (keep) {
+            double *a = acc + base;
+#pragma unroll
+            for (int jj = 0; jj < WT; ++jj) {
+              const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
+              const float r = __builtin_amdgcn_rcpf(u);
+              float w = __builtin_fmaf(K.cth[jj], CP, C2);
+              w = __builtin_fmaf(K.sth[jj], CQ, w);
+              __hip_atomic_fetch_add(a + jj, (double)(w * r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+        }
+        wave_sync();
+      }
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) dst[k] = (float)acc[MARGIN + k];
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 3: ordered sum of the partial tiles of split tiles.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, const uint16_t *multi_unused,
+                                                     const float *__restrict__ part, float *__restrict__ out,
+                                                     int n_multi_rows) {
+  (void)multi_unused;
+  (void)n_multi_rows;
+  // blockIdx.y = dispatch position of the tile, blockIdx.x = rir
+  const int pos = blockIdx.y;
+  const int tile = pa.n_tiles - 1 - pos;
+  const int C = pa.chunks[tile];
+  if (C <= 1) return;
+  const int rir = blockIdx.x;
+  const int T0 = tile * TILE;
+  const int T1 = min(T0 + TILE, ra.n_samples);
+  const size_t first = (size_t)pa.first_item[pos] + (size_t)rir * C;
+  for (int k = threadIdx.x; k < T1 - T0; k += blockDim.x) {
+    float v = 0.0f;
+    for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
+    out[(size_t)rir * ra.n_samples + T0 + k] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (called from ism_host.cpp).
+// ---------------------------------------------------------------------------
+int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, int *valid, int n_rir,
+                  hipStream_t st) {
+  const int64_t total = (int64_t)n_rir * ra.n_tab;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(tables_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ra, src, rcv, tab, valid, n_rir);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int WT>
+static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
+                        const int *valid, float *out, float *part, hipStream_t st) {
+  constexpr int NW = 4;
+  hipLaunchKernelGGL((accumulate_kernel<WT, NW>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, valid, out,
+                     part);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt == 128; }
+
+int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
+                      const int *valid, float *out, float *part, hipStream_t st) {
+  switch (wt) {
+    case 32: return launch_acc_w<32>(ra, pa, n_items, tab, valid, out, part, st);
+    case 64: return launch_acc_w<64>(ra, pa, n_items, tab, valid, out, part, st);
+    case 96: return launch_acc_w<96>(ra, pa, n_items, tab, valid, out, part, st);
+    case 128: return launch_acc_w<128>(ra, pa, n_items, tab, valid, out, part, st);
+    default: return -2;
+  }
+}
+
+int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)n_rir, (unsigned)pa.n_tiles), dim3(256), 0, st, ra, pa,
+                     (const uint16_t *)nullptr, part, out, 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ism

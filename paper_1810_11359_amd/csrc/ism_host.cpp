@@ -1,0 +1,315 @@
+// C ABI of libism.so (declared in include/ism.h): argument checks, FP64 host
+// planning, workspace layout and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "ism.h"
+#include "ism_internal.h"
+
+namespace ism {
+int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, int *valid, int n_rir,
+                  hipStream_t st);
+int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
+                      const int *valid, float *out, float *part, hipStream_t st);
+int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
+                  hipStream_t st);
+bool supported_window(int wt);
+}  // namespace ism
+
+using namespace ism;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int lattice_lo(int N) { return -(N / 2); }       // ceil(-N/2)
+int lattice_hi(int N) { return (N + 1) / 2; }    // ceil(N/2), exclusive
+
+void split(double v, float &hi, float &lo) {
+  hi = (float)v;
+  lo = (float)(v - (double)hi);
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Window length W = t_w * fs in samples when it is an even integer (within
+// 1e-9 relative); 0 otherwise.
+int even_window(const ism_room &r) {
+  const double W = r.t_w * r.fs;
+  const double k = std::nearbyint(W);
+  if (std::fabs(W - k) > 1e-9 * W) return 0;
+  const long iw = (long)k;
+  if (iw < 2 || (iw & 1)) return 0;
+  return (int)iw;
+}
+
+struct Plan {
+  RoomArgs ra;
+  PlanArgs pa;
+  int wt;
+  int n_rir;
+  uint32_t n_items;
+  bool any_split;
+  size_t off_valid, off_tab, off_part, ws_bytes;
+};
+
+int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
+  int st = ism_check_room(r);
+  if (st != ISM_OK) return st;
+  if (n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
+  if ((int64_t)n_src * n_rcv > ISM_MAX_PAIRS) return ISM_E_TOO_LARGE;
+  if (precision != ISM_FP32) return precision == ISM_FP16 || precision == ISM_BF16 ? ISM_E_UNSUPPORTED : ISM_E_INVALID_ARG;
+  p.wt = even_window(*r);
+  if (p.wt == 0 || !supported_window(p.wt)) return ISM_E_UNSUPPORTED;
+  const int64_t nS = ism_n_samples(r->t_max, r->fs);
+  const double W = (double)p.wt;
+  const double q = r->fs / r->c;
+
+  RoomArgs &ra = p.ra;
+  std::memset(&ra, 0, sizeof(ra));
+  int off = 0;
+  for (int a = 0; a < 3; ++a) {
+    split(r->room[a], ra.L_hi[a], ra.L_lo[a]);
+    ra.lo[a] = lattice_lo(r->n_img[a]);
+    ra.N[a] = r->n_img[a];
+    ra.off[a] = off;
+    off += r->n_img[a];
+  }
+  for (int i = 0; i < 6; ++i) ra.beta[i] = (float)r->beta[i];
+  ra.n_tab = off;
+  split(q, ra.q_hi, ra.q_lo);
+  ra.kappa = (float)(r->fs / (4.0 * kPi * r->c));
+  ra.two_pi_over_w = (float)(2.0 * kPi / W);
+  ra.half_w = (float)(W / 2.0);
+  ra.n_samples = (int)nS;
+  ra.n_src = n_src;
+  ra.n_rcv = n_rcv;
+
+  // Work split: estimated taps of a tile's image shell from the shell volume
+  // over the image density 1 / (Lx Ly Lz) (one image per mirrored room copy).
+  p.n_rir = n_src * n_rcv;
+  PlanArgs &pa = p.pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.n_tiles = (int)((nS + TILE - 1) / TILE);
+  pa.n_rir = p.n_rir;
+  const double cell = r->room[0] * r->room[1] * r->room[2] * q * q * q;
+  const double lattice = (double)r->n_img[0] * r->n_img[1] * r->n_img[2];
+  double target = 2.5e5;
+  if (const char *e = std::getenv("ISM_TARGET_TAPS")) target = std::max(1e3, std::atof(e));
+  p.any_split = false;
+  for (int t = 0; t < pa.n_tiles; ++t) {
+    const double T0 = (double)t * TILE, T1 = std::min((double)(t + 1) * TILE, (double)nS);
+    const double x1 = T1 + W / 2.0, x0 = std::max(T0 - W / 2.0, 0.0);
+    const double imgs = std::min(4.0 / 3.0 * kPi * (x1 * x1 * x1 - x0 * x0 * x0) / cell, lattice);
+    const double taps = imgs * W;
+    int ch = (int)std::ceil(taps / target);
+    ch = std::max(1, std::min(ch, MAX_CHUNKS));
+    pa.chunks[t] = (uint8_t)ch;
+    if (ch > 1) p.any_split = true;
+  }
+  uint64_t acc = 0;
+  for (int pos = 0; pos < pa.n_tiles; ++pos) {
+    pa.first_item[pos] = (uint32_t)acc;
+    acc += (uint64_t)p.n_rir * pa.chunks[pa.n_tiles - 1 - pos];
+    if (acc > 0x7fffffffULL) return ISM_E_TOO_LARGE;
+  }
+  pa.first_item[pa.n_tiles] = (uint32_t)acc;
+  p.n_items = (uint32_t)acc;
+
+  p.off_valid = 0;
+  p.off_tab = align_up(sizeof(int) * (size_t)p.n_rir);
+  p.off_part = align_up(p.off_tab + sizeof(AxisEntry) * (size_t)p.n_rir * ra.n_tab);
+  p.ws_bytes = p.off_part + (p.any_split ? sizeof(float) * (size_t)p.n_items * TILE : 0);
+  return ISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ism_status_string(int status) {
+  switch (status) {
+    case ISM_OK: return "ok";
+    case ISM_E_INVALID_ARG: return "invalid argument";
+    case ISM_E_INFEASIBLE_T60: return "T60 infeasible by Sabine's formula (absorption > 1)";
+    case ISM_E_OUT_OF_ROOM: return "position not strictly inside the room";
+    case ISM_E_WORKSPACE: return "workspace missing or too small";
+    case ISM_E_DEVICE: return "HIP device error";
+    case ISM_E_TOO_LARGE: return "problem exceeds a library limit";
+    case ISM_E_UNSUPPORTED: return "request not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+int ism_abi_version(void) { return ISM_ABI_VERSION; }
+
+int ism_beta_from_t60(const double room[3], double t60, double beta_out[6]) {
+  if (!room || !beta_out) return ISM_E_INVALID_ARG;
+  if (!finite_pos(room[0]) || !finite_pos(room[1]) || !finite_pos(room[2]) || !finite_pos(t60)) return ISM_E_INVALID_ARG;
+  const double V = room[0] * room[1] * room[2];
+  const double S = 2.0 * (room[0] * room[1] + room[0] * room[2] + room[1] * room[2]);
+  const double alpha = 0.161 * V / (S * t60);  // Eq. (7) with one alpha for all walls
+  if (alpha > 1.0) return ISM_E_INFEASIBLE_T60;
+  const double b = std::sqrt(1.0 - alpha);  // alpha = 1 - beta^2
+  for (int i = 0; i < 6; ++i) beta_out[i] = b;
+  return ISM_OK;
+}
+
+int ism_n_img_for_time(const double room[3], double c, double t, int n_out[3]) {
+  if (!room || !n_out) return ISM_E_INVALID_ARG;
+  if (!finite_pos(c) || !finite_pos(t)) return ISM_E_INVALID_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (!finite_pos(room[a])) return ISM_E_INVALID_ARG;
+    const double k = std::ceil(c * t / (2.0 * room[a]));
+    if (k > (ISM_MAX_N_IMG - 2) / 4) return ISM_E_TOO_LARGE;
+    n_out[a] = 4 * (int)k + 2;
+  }
+  return ISM_OK;
+}
+
+int ism_time_for_attenuation(double t60, double att_db, double *t_out) {
+  if (!t_out || !finite_pos(t60) || !std::isfinite(att_db) || att_db < 0.0) return ISM_E_INVALID_ARG;
+  *t_out = t60 * att_db / 60.0;
+  return ISM_OK;
+}
+
+int64_t ism_n_samples(double t_max, double fs) {
+  if (!finite_pos(t_max) || !finite_pos(fs)) return -1;
+  const double v = t_max * fs;
+  if (v > 9.0e15) return -1;
+  const double r = std::nearbyint(v);
+  if (std::fabs(v - r) <= 1e-9 * v) return (int64_t)r;
+  return (int64_t)std::ceil(v);
+}
+
+int ism_check_room(const ism_room *r) {
+  if (!r) return ISM_E_INVALID_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (!finite_pos(r->room[a])) return ISM_E_INVALID_ARG;
+    if (r->n_img[a] < 1) return ISM_E_INVALID_ARG;
+    if (r->n_img[a] > ISM_MAX_N_IMG) return ISM_E_TOO_LARGE;
+  }
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(r->beta[i]) || std::fabs(r->beta[i]) > 1.0) return ISM_E_INVALID_ARG;
+  if (!finite_pos(r->c) || !finite_pos(r->fs) || !finite_pos(r->t_max) || !finite_pos(r->t_w)) return ISM_E_INVALID_ARG;
+  const int64_t nS = ism_n_samples(r->t_max, r->fs);
+  if (nS < 1) return ISM_E_INVALID_ARG;
+  if (nS > ISM_MAX_SAMPLES) return ISM_E_TOO_LARGE;
+  return ISM_OK;
+}
+
+int ism_check_positions(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv) {
+  int st = ism_check_room(room);
+  if (st != ISM_OK) return st;
+  if (!src || !rcv || n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
+  auto inside = [&](const float *p) {
+    for (int a = 0; a < 3; ++a)
+      if (!(std::isfinite(p[a]) && p[a] > 0.0f && (double)p[a] < room->room[a])) return false;
+    return true;
+  };
+  for (int i = 0; i < n_src; ++i)
+    if (!inside(src + 3 * i)) return ISM_E_OUT_OF_ROOM;
+  for (int i = 0; i < n_rcv; ++i)
+    if (!inside(rcv + 3 * i)) return ISM_E_OUT_OF_ROOM;
+  for (int i = 0; i < n_src; ++i)
+    for (int j = 0; j < n_rcv; ++j)
+      if (src[3 * i] == rcv[3 * j] && src[3 * i + 1] == rcv[3 * j + 1] && src[3 * i + 2] == rcv[3 * j + 2])
+        return ISM_E_INVALID_ARG;
+  return ISM_OK;
+}
+
+int ism_count_taps(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                   int64_t *taps_out) {
+  if (!taps_out) return ISM_E_INVALID_ARG;
+  int st = ism_check_room(room);
+  if (st != ISM_OK) return st;
+  if (!src || !rcv || n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
+  const double W = room->t_w * room->fs, hw = W / 2.0;
+  const double q = room->fs / room->c;
+  const int64_t nS = ism_n_samples(room->t_max, room->fs);
+  const int n_pairs = n_src * n_rcv;
+  std::atomic<int> next{0};
+  std::atomic<int64_t> total{0};
+  auto worker = [&]() {
+    for (;;) {
+      const int pidx = next.fetch_add(1);
+      if (pidx >= n_pairs) return;
+      const float *s = src + 3 * (pidx / n_rcv);
+      const float *r = rcv + 3 * (pidx % n_rcv);
+      // per-axis squared displacements (samples^2) of every lattice index
+      std::vector<double> d2[3];
+      for (int a = 0; a < 3; ++a) {
+        for (int n = lattice_lo(room->n_img[a]); n < lattice_hi(room->n_img[a]); ++n) {
+          const double coord = (n % 2 == 0) ? n * room->room[a] + s[a] : (n + 1) * room->room[a] - s[a];
+          const double dd = (coord - r[a]) * q;
+          d2[a].push_back(dd * dd);
+        }
+      }
+      int64_t cnt = 0;
+      for (double dx : d2[0])
+        for (double dy : d2[1])
+          for (double dz : d2[2]) {
+            const double x = std::sqrt(dx + dy + dz);
+            int64_t first = (int64_t)std::floor(x - hw) + 1;
+            int64_t last = (int64_t)std::ceil(x + hw) - 1;
+            if (first < 0) first = 0;
+            if (last > nS - 1) last = nS - 1;
+            if (last >= first) cnt += last - first + 1;
+          }
+      total.fetch_add(cnt);
+    }
+  };
+  const unsigned hc = std::max(1u, std::min(std::thread::hardware_concurrency(), (unsigned)n_pairs));
+  std::vector<std::thread> th;
+  for (unsigned i = 1; i < hc; ++i) th.emplace_back(worker);
+  worker();
+  for (auto &t : th) t.join();
+  *taps_out = total.load();
+  return ISM_OK;
+}
+
+int ism_workspace_size(const ism_room *room, int n_src, int n_rcv, int precision, size_t *bytes) {
+  if (!bytes) return ISM_E_INVALID_ARG;
+  Plan p;
+  const int st = make_plan(room, n_src, n_rcv, precision, p);
+  if (st != ISM_OK) return st;
+  *bytes = p.ws_bytes;
+  return ISM_OK;
+}
+
+int ism_simulate(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv, int precision,
+                 float *out, void *ws, size_t ws_bytes, void *stream) {
+  return ism_simulate_timed(room, src, n_src, rcv, n_rcv, precision, out, ws, ws_bytes, stream, nullptr, nullptr);
+}
+
+int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                       int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
+                       void *ev_stop) {
+  Plan p;
+  const int st = make_plan(room, n_src, n_rcv, precision, p);
+  if (st != ISM_OK) return st;
+  if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
+  if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  int *valid = (int *)(w + p.off_valid);
+  AxisEntry *tab = (AxisEntry *)(w + p.off_tab);
+  float *part = p.any_split ? (float *)(w + p.off_part) : nullptr;
+  if (launch_tables(p.ra, src, rcv, tab, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
+  if (ev_start && hipEventRecord((hipEvent_t)ev_start, s) != hipSuccess) return ISM_E_DEVICE;
+  if (launch_accumulate(p.wt, p.ra, p.pa, p.n_items, tab, valid, out, part, s) != 0) return ISM_E_DEVICE;
+  if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
+  if (p.any_split && launch_reduce(p.ra, p.pa, p.n_rir, part, out, s) != 0) return ISM_E_DEVICE;
+  return ISM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Internal types shared by the host planner (ism_host.cpp) and the HIP kernels
+// (ism_device.hip). Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+namespace ism {
+
+// Output tile handled by one work item: TILE consecutive samples of one RIR.
+constexpr int TILE = 1024;
+// Most tiles per RIR (ISM_MAX_SAMPLES / TILE).
+constexpr int MAX_TILES = 256;
+// Work items per tile are capped so the per-tile chunk count fits a byte.
+constexpr int MAX_CHUNKS = 255;
+
+// Per-call room constants, passed by value as a kernel argument. Lengths are in
+// metres, delays in samples. Float-float pairs (hi, lo) carry double-precision
+// host values into FP32-only device arithmetic.
+struct RoomArgs {
+  float L_hi[3], L_lo[3];  // room size
+  float beta[6];           // x0, x1, y0, y1, z0, z1
+  int lo[3];               // first lattice index ceil(-N/2) per axis
+  int N[3];                // lattice size per axis
+  int off[3];              // offset of each axis in the per-RIR table
+  int n_tab;               // Nx + Ny + Nz
+  float q_hi, q_lo;        // fs / c [samples per metre]
+  float kappa;             // fs / (4 pi c): A = gain * kappa / x with x in samples
+  float two_pi_over_w;     // 2 pi / W
+  float half_w;            // W / 2
+  int n_samples;           // nS
+  int n_src, n_rcv;
+};
+
+// Work decomposition of one call. Items are ordered by tile (last tile first,
+// where the images are densest), then by RIR, then by chunk. Tile t owns
+// samples [t*TILE, min((t+1)*TILE, nS)); its image shell is split into
+// chunks[t] slabs along the x displacement.
+struct PlanArgs {
+  int n_tiles;
+  int n_rir;
+  uint32_t first_item[MAX_TILES + 1];  // index of the first item of tile t (dispatch order)
+  uint8_t chunks[MAX_TILES];           // chunks per tile
+};
+
+// Per-RIR table entry for one lattice index of one axis: displacement from
+// the receiver to the image coordinate in samples (float-float) and the axis
+// factor of the reflection gain.
+struct AxisEntry {
+  float d_hi, d_lo, gain, pad;
+};
+
+}  // namespace ism

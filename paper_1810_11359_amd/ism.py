@@ -1,0 +1,233 @@
+"""Thin ctypes binding of libism.so (include/ism.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of the library. PyTorch provides device memory and the stream. The
+library must be built (``python -m paper_1810_11359_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libism.so")
+
+ISM_OK = 0
+ISM_E_INVALID_ARG = -1
+ISM_E_INFEASIBLE_T60 = -2
+ISM_E_OUT_OF_ROOM = -3
+ISM_E_WORKSPACE = -4
+ISM_E_DEVICE = -5
+ISM_E_TOO_LARGE = -6
+ISM_E_UNSUPPORTED = -7
+
+PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2}
+
+# Every symbol include/ism.h declares.
+EXPORTS = (
+    "ism_status_string", "ism_abi_version", "ism_beta_from_t60", "ism_n_img_for_time",
+    "ism_time_for_attenuation", "ism_n_samples", "ism_check_room", "ism_check_positions",
+    "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed",
+)
+
+
+class IsmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+        self.status = status
+
+
+class _Room(ctypes.Structure):
+    _fields_ = [("room", ctypes.c_double * 3), ("beta", ctypes.c_double * 6), ("n_img", ctypes.c_int * 3),
+                ("c", ctypes.c_double), ("fs", ctypes.c_double), ("t_max", ctypes.c_double),
+                ("t_w", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libism.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -m paper_1810_11359_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        dp, ip, fp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p
+        rp = ctypes.POINTER(_Room)
+        L.ism_status_string.restype = ctypes.c_char_p
+        L.ism_status_string.argtypes = [ctypes.c_int]
+        L.ism_abi_version.restype = ctypes.c_int
+        L.ism_abi_version.argtypes = []
+        L.ism_beta_from_t60.restype = ctypes.c_int
+        L.ism_beta_from_t60.argtypes = [dp, ctypes.c_double, dp]
+        L.ism_n_img_for_time.restype = ctypes.c_int
+        L.ism_n_img_for_time.argtypes = [dp, ctypes.c_double, ctypes.c_double, ip]
+        L.ism_time_for_attenuation.restype = ctypes.c_int
+        L.ism_time_for_attenuation.argtypes = [ctypes.c_double, ctypes.c_double, dp]
+        L.ism_n_samples.restype = ctypes.c_int64
+        L.ism_n_samples.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.ism_check_room.restype = ctypes.c_int
+        L.ism_check_room.argtypes = [rp]
+        L.ism_check_positions.restype = ctypes.c_int
+        L.ism_check_positions.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int]
+        L.ism_count_taps.restype = ctypes.c_int
+        L.ism_count_taps.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.ism_workspace_size.restype = ctypes.c_int
+        L.ism_workspace_size.argtypes = [rp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.ism_simulate.restype = ctypes.c_int
+        L.ism_simulate.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t, fp]
+        L.ism_simulate_timed.restype = ctypes.c_int
+        L.ism_simulate_timed.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
+                                         fp, fp, fp]
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().ism_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != ISM_OK:
+        raise IsmError(status, where)
+
+
+@dataclass
+class Room:
+    """One shoebox room (fields as in ``ism_room`` of include/ism.h)."""
+    room: Sequence[float]
+    beta: Sequence[float]
+    n_img: Sequence[int]
+    c: float = 343.0
+    fs: float = 16000.0
+    t_max: float = 0.5
+    t_w: float = 0.004
+
+    def _c(self) -> _Room:
+        r = _Room()
+        for i in range(3):
+            r.room[i] = float(self.room[i])
+            r.n_img[i] = int(self.n_img[i])
+        for i in range(6):
+            r.beta[i] = float(self.beta[i])
+        r.c, r.fs, r.t_max, r.t_w = float(self.c), float(self.fs), float(self.t_max), float(self.t_w)
+        return r
+
+    @property
+    def n_samples(self) -> int:
+        return n_samples(self.t_max, self.fs)
+
+
+def beta_from_t60(room: Sequence[float], t60: float) -> np.ndarray:
+    L = (ctypes.c_double * 3)(*[float(v) for v in room])
+    out = (ctypes.c_double * 6)()
+    _check(lib().ism_beta_from_t60(L, float(t60), out), "ism_beta_from_t60")
+    return np.array(out[:])
+
+
+def n_img_for_time(room: Sequence[float], c: float, t: float) -> tuple:
+    L = (ctypes.c_double * 3)(*[float(v) for v in room])
+    n = (ctypes.c_int * 3)()
+    _check(lib().ism_n_img_for_time(L, float(c), float(t), n), "ism_n_img_for_time")
+    return (n[0], n[1], n[2])
+
+
+def time_for_attenuation(t60: float, att_db: float) -> float:
+    t = ctypes.c_double()
+    _check(lib().ism_time_for_attenuation(float(t60), float(att_db), ctypes.byref(t)), "ism_time_for_attenuation")
+    return t.value
+
+
+def n_samples(t_max: float, fs: float) -> int:
+    v = int(lib().ism_n_samples(float(t_max), float(fs)))
+    if v < 0:
+        raise IsmError(ISM_E_INVALID_ARG, "ism_n_samples")
+    return v
+
+
+def _host_pos(p) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(p, dtype=np.float32).reshape(-1, 3))
+
+
+def check_positions(room: Room, src, rcv) -> None:
+    s, r = _host_pos(src), _host_pos(rcv)
+    rc = room._c()
+    _check(lib().ism_check_positions(ctypes.byref(rc), s.ctypes.data, s.shape[0], r.ctypes.data, r.shape[0]),
+           "ism_check_positions")
+
+
+def count_taps(room: Room, src, rcv) -> int:
+    s, r = _host_pos(src), _host_pos(rcv)
+    rc = room._c()
+    out = ctypes.c_int64()
+    _check(lib().ism_count_taps(ctypes.byref(rc), s.ctypes.data, s.shape[0], r.ctypes.data, r.shape[0],
+                                ctypes.byref(out)), "ism_count_taps")
+    return out.value
+
+
+def workspace_size(room: Room, n_src: int, n_rcv: int, precision: str = "fp32") -> int:
+    rc = room._c()
+    out = ctypes.c_size_t()
+    _check(lib().ism_workspace_size(ctypes.byref(rc), int(n_src), int(n_rcv), PRECISIONS[precision],
+                                    ctypes.byref(out)), "ism_workspace_size")
+    return out.value
+
+
+class Simulator:
+    """Reusable device state for repeated ``ism_simulate`` calls on one room shape.
+
+    Holds the device positions, output tensor and workspace so a timed loop
+    launches kernels only.
+    """
+
+    def __init__(self, room: Room, src, rcv, precision: str = "fp32", device: str = "cuda", check: bool = True):
+        import torch
+
+        self.torch = torch
+        self.room = room
+        self._room_c = room._c()
+        s, r = _host_pos(src), _host_pos(rcv)
+        if check:
+            check_positions(room, s, r)
+        self.precision = PRECISIONS[precision]
+        self.src = torch.from_numpy(s).to(device)
+        self.rcv = torch.from_numpy(r).to(device)
+        self.n_src, self.n_rcv = s.shape[0], r.shape[0]
+        self.out = torch.empty((self.n_src, self.n_rcv, room.n_samples), dtype=torch.float32, device=device)
+        nbytes = workspace_size(room, self.n_src, self.n_rcv, precision)
+        self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        self.ws_bytes = nbytes
+
+    def run(self, stream=None, ev_start=None, ev_stop=None):
+        """Launch one simulation on ``stream`` (default: torch's current stream); returns the output tensor.
+
+        ``ev_start``/``ev_stop`` are optional raw hipEvent_t handles recorded around the tap kernel."""
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        _check(lib().ism_simulate_timed(ctypes.byref(self._room_c), self.src.data_ptr(), self.n_src,
+                                        self.rcv.data_ptr(), self.n_rcv, self.precision, self.out.data_ptr(),
+                                        self.ws.data_ptr(), self.ws_bytes, st.cuda_stream, ev_start, ev_stop),
+               "ism_simulate_timed")
+        return self.out
+
+
+def simulate(room: Room, src, rcv, precision: str = "fp32", device: str = "cuda"):
+    """RIRs [n_src, n_rcv, nS] (float32, on ``device``) of every source/receiver pair."""
+    return Simulator(room, src, rcv, precision, device).run()
+
+
+def room_for(w) -> Room:
+    """Room of a ``workloads.Workload`` built with this library's helpers: Sabine
+    beta for the workload's T60 (times its per-wall jitter, capped at 0.999) and
+    the lattice that keeps every image closer than c * T_max."""
+    beta = beta_from_t60(w.room, w.t60)
+    if w.beta_jitter is not None:
+        beta = np.minimum(beta * np.asarray(w.beta_jitter), 0.999)
+    n = n_img_for_time(w.room, w.c, w.t_max)
+    return Room(list(map(float, w.room)), list(map(float, beta)), n, w.c, w.fs, w.t_max, w.t_w)

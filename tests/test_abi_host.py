@@ -1,0 +1,139 @@
+"""CPU tests of the C ABI: the library loads and exports every declared symbol,
+host helpers agree with the oracle, and argument checks return the documented
+status codes. No GPU compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1810_11359_amd import ism, workloads
+
+from .helpers import oracle_room_args
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "ism.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ism_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = _declared_functions()
+    assert set(declared) == set(ism.EXPORTS)
+    lib = ism.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.ism_abi_version() == 1
+
+
+def test_status_strings():
+    for st in range(0, -8, -1):
+        assert ism.status_string(st) and ism.status_string(st) != "unknown status"
+    assert ism.status_string(-99) == "unknown status"
+
+
+def test_helpers_match_oracle(oracle_mod):
+    rng = np.random.default_rng(0)
+    for _ in range(30):
+        L = rng.uniform(2.0, 10.0, 3)
+        t60 = rng.uniform(0.3, 2.0)
+        try:
+            ob = oracle_mod.beta_from_t60(L, t60)
+        except ValueError:
+            with pytest.raises(ism.IsmError) as e:
+                ism.beta_from_t60(L, t60)
+            assert e.value.status == ism.ISM_E_INFEASIBLE_T60
+            continue
+        np.testing.assert_array_equal(ism.beta_from_t60(L, t60), ob)
+        assert ism.n_img_for_time(L, 343.0, t60) == oracle_mod.n_img_for_time(L, 343.0, t60)
+        assert ism.time_for_attenuation(t60, 20.0) == oracle_mod.time_for_attenuation(t60, 20.0)
+    for t, fs in [(0.7, 16000), (0.3, 16000), (2.0, 48000), (0.123456, 44100), (1e-4, 8000)]:
+        assert ism.n_samples(t, fs) == oracle_mod.n_samples(t, fs)
+
+
+def test_count_taps_matches_oracle(oracle_mod):
+    w = workloads.single_rir(3)
+    L, beta, n, c, fs, t_max, t_w = oracle_room_args(oracle_mod, w)
+    room = ism.room_for(w)
+    assert tuple(room.n_img) == tuple(n)
+    assert ism.count_taps(room, w.src, w.rcv) == oracle_mod.count_taps(L, beta, n, c, fs, t_max, t_w, w.src, w.rcv)
+    # a second geometry with several pairs and a short RIR
+    room2 = ism.Room([3.3, 2.7, 2.9], [0.7] * 6, (9, 10, 7), 343.0, 16000.0, 0.05, 0.004)
+    src = np.array([[1.0, 1.1, 1.2], [2.0, 0.5, 2.5]], dtype=np.float32)
+    rcv = np.array([[0.6, 2.0, 1.0]], dtype=np.float32)
+    assert ism.count_taps(room2, src, rcv) == oracle_mod.count_taps(room2.room, room2.beta, room2.n_img, 343.0, 16000.0,
+                                                                    0.05, 0.004, src, rcv)
+
+
+def _room(**kw):
+    base = dict(room=[4.0, 5.0, 3.0], beta=[0.9] * 6, n_img=(10, 10, 10), c=343.0, fs=16000.0, t_max=0.1, t_w=0.004)
+    base.update(kw)
+    return ism.Room(**base)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(room=[0.0, 5.0, 3.0]), ism.ISM_E_INVALID_ARG),
+    (dict(room=[float("nan"), 5.0, 3.0]), ism.ISM_E_INVALID_ARG),
+    (dict(beta=[1.5] + [0.9] * 5), ism.ISM_E_INVALID_ARG),
+    (dict(n_img=(0, 10, 10)), ism.ISM_E_INVALID_ARG),
+    (dict(n_img=(5000, 10, 10)), ism.ISM_E_TOO_LARGE),
+    (dict(c=-1.0), ism.ISM_E_INVALID_ARG),
+    (dict(fs=0.0), ism.ISM_E_INVALID_ARG),
+    (dict(t_w=0.0), ism.ISM_E_INVALID_ARG),
+    (dict(t_max=100.0), ism.ISM_E_TOO_LARGE),
+])
+def test_room_checks(kw, status):
+    r = _room(**kw)
+    assert ism.lib().ism_check_room(ctypes.byref(r._c())) == status
+    with pytest.raises(ism.IsmError) as e:
+        ism.workspace_size(r, 1, 1)
+    assert e.value.status == status
+
+
+def test_room_ok_and_workspace():
+    r = _room()
+    assert ism.lib().ism_check_room(ctypes.byref(r._c())) == ism.ISM_OK
+    assert ism.workspace_size(r, 2, 3) > 0
+    with pytest.raises(ism.IsmError) as e:
+        ism.workspace_size(r, 0, 3)
+    assert e.value.status == ism.ISM_E_INVALID_ARG
+
+
+def test_unsupported_requests():
+    with pytest.raises(ism.IsmError) as e:
+        ism.workspace_size(_room(t_w=0.0041), 1, 1)  # W = 65.6 samples
+    assert e.value.status == ism.ISM_E_UNSUPPORTED
+    with pytest.raises(ism.IsmError) as e:
+        ism.workspace_size(_room(), 1, 1, precision="fp16")
+    assert e.value.status == ism.ISM_E_UNSUPPORTED
+
+
+def test_position_checks():
+    r = _room()
+    ok = np.array([[1.0, 1.0, 1.0]], dtype=np.float32)
+    ism.check_positions(r, ok, [[2.0, 2.0, 2.0]])
+    for bad in ([[0.0, 1.0, 1.0]], [[4.0, 1.0, 1.0]], [[1.0, 5.5, 1.0]], [[1.0, 1.0, float("nan")]]):
+        with pytest.raises(ism.IsmError) as e:
+            ism.check_positions(r, ok, bad)
+        assert e.value.status == ism.ISM_E_OUT_OF_ROOM
+    with pytest.raises(ism.IsmError) as e:
+        ism.check_positions(r, ok, ok)
+    assert e.value.status == ism.ISM_E_INVALID_ARG
+
+
+def test_simulate_rejects_bad_arguments_before_launch():
+    # Every check runs on the host before any launch, so this is safe without a GPU.
+    r = _room()
+    rc = r._c()
+    L = ism.lib()
+    fake = ctypes.c_void_p(0x1000)
+    need = ism.workspace_size(r, 1, 1)
+    assert L.ism_simulate(ctypes.byref(rc), None, 1, fake, 1, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
+    assert L.ism_simulate(ctypes.byref(rc), fake, 1, fake, 1, 0, fake, None, need, None) == ism.ISM_E_WORKSPACE
+    assert L.ism_simulate(ctypes.byref(rc), fake, 1, fake, 1, 0, fake, fake, need - 1, None) == ism.ISM_E_WORKSPACE
+    assert L.ism_simulate(ctypes.byref(rc), fake, 0, fake, 1, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
+    assert L.ism_simulate(ctypes.byref(rc), fake, 1, fake, 1, 7, fake, fake, need, None) == ism.ISM_E_INVALID_ARG

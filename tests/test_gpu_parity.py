@@ -1,0 +1,158 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance: max |h_gpu - h_oracle| / max |h_oracle| <= 1e-5 per RIR for FP32
+taps. Full RIRs at sizes the oracle finishes in seconds (several 1024-sample
+tiles plus a ragged last tile); at the full workload sizes the oracle computes
+sampled receivers or sampled time windows.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_11359_amd import ism, workloads
+
+from .helpers import oracle_room_args, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ism.lib()
+    return torch
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_rir(room, src, rcv):
+    import torch
+
+    out = ism.simulate(room, src, rcv)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _oracle_rir(oracle_mod, room, src, rcv, k_begin=0, k_end=None):
+    return oracle_mod.rir(room.room, room.beta, room.n_img, room.c, room.fs, room.t_max, room.t_w, src, rcv,
+                          k_begin=k_begin, k_end=k_end)
+
+
+def test_single_rir_workload(oracle_mod):
+    w = workloads.single_rir(0)
+    room = ism.room_for(w)
+    assert tuple(room.n_img) == tuple(oracle_room_args(oracle_mod, w)[2])
+    _say(f"single_rir n_img={room.n_img} nS={room.n_samples}")
+    got = _gpu_rir(room, w.src, w.rcv)
+    ref = oracle_mod.rir(*oracle_room_args(oracle_mod, w), w.src, w.rcv)
+    assert got.shape == ref.shape == (1, 1, 4800)
+    err = rel_err(got, ref)
+    print("rel err", err)
+    assert np.all(err <= TOL_FP32)
+
+
+def test_exact_integer_delay():
+    room = ism.Room([4.0, 3.0, 3.0], [0.0] * 6, (6, 6, 6), 256.0, 16384.0, 0.015625, 0.00390625)
+    _say("integer delay")
+    h = _gpu_rir(room, [[0.75, 1.0, 1.0]], [[2.75, 1.0, 1.0]])[0, 0]
+    assert abs(h[128] - 1.0 / (8.0 * np.pi)) <= 1e-6 / (8.0 * np.pi)
+    assert np.max(np.abs(np.delete(h, 128))) <= 1e-6 * h[128]
+
+
+CASES = [
+    # (name, room, beta, n_img, fs, t_max, t_w, src, rcv)
+    ("short_path_free_field", [4.0, 5.0, 3.0], [0.0] * 6, (6, 6, 6), 16000.0, 0.05, 0.004,
+     [[1.2, 2.0, 1.5]], [[1.4, 2.1, 1.3]]),
+    ("signed_beta_odd_n_w32", [3.1, 2.6, 2.9], [-0.9, 0.8, 0.7, -0.85, 0.95, -0.6], (7, 9, 11), 8000.0, 0.19, 0.004,
+     [[0.4, 1.7, 2.2]], [[2.7, 0.5, 0.9], [1.5, 1.3, 1.45]]),
+    ("even_n_w64_ragged", [5.3, 3.7, 2.4], [0.92, 0.88, 0.9, 0.91, 0.7, 0.95], (26, 34, 50), 16000.0, 0.21, 0.004,
+     [[1.0, 1.0, 1.0], [4.1, 2.9, 1.9]], [[2.5, 1.8, 0.6], [0.7, 3.3, 2.0], [5.0, 0.3, 2.2]]),
+    ("w96_48k", [4.4, 3.1, 2.7], [0.9] * 6, (30, 42, 46), 48000.0, 0.085, 0.002,
+     [[1.3, 0.9, 1.1]], [[3.0, 2.2, 2.0]]),
+    ("w128_32k_wall_grazing", [2.2, 2.9, 2.1], [0.97] * 6, (34, 26, 34), 32000.0, 0.08, 0.004,
+     [[0.01, 1.4, 2.09]], [[2.19, 0.02, 1.0]]),
+    ("asymmetric_small_n", [6.0, 4.0, 3.0], [0.8, 0.6, 0.9, 0.5, 0.7, 0.4], (3, 1, 5), 16000.0, 0.3, 0.004,
+     [[2.0, 1.0, 1.0]], [[4.0, 3.0, 2.0]]),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_small_rooms_full_rir(oracle_mod, case):
+    name, L, beta, n, fs, t_max, t_w, src, rcv = case
+    room = ism.Room(L, beta, n, 343.0, fs, t_max, t_w)
+    _say(f"{name} nS={room.n_samples}")
+    got = _gpu_rir(room, src, rcv)
+    ref = _oracle_rir(oracle_mod, room, src, rcv)
+    err = rel_err(got, ref)
+    print(name, "rel err", err)
+    assert np.all(err <= TOL_FP32)
+
+
+def test_room_32_receivers_sampled(oracle_mod):
+    w = workloads.room_32_receivers(0)
+    room = ism.room_for(w)
+    _say(f"room_32_receivers n_img={room.n_img}")
+    got = _gpu_rir(room, w.src, w.rcv)
+    assert got.shape == (1, 32, 11200)
+    pick = [0, 7, 19, 31]
+    ref = oracle_mod.rir(*oracle_room_args(oracle_mod, w), w.src, w.rcv[pick])
+    err = rel_err(got[:, pick], ref)
+    print("rel err", err)
+    assert np.all(err <= TOL_FP32)
+    assert np.all(np.isfinite(got))
+
+
+def test_large_room_uca_sampled_windows(oracle_mod):
+    w = workloads.large_room_uca(0)
+    room = ism.room_for(w)
+    _say(f"large_room_uca n_img={room.n_img}")
+    got = _gpu_rir(room, w.src, w.rcv)
+    assert got.shape == (1, 64, 96000)
+    assert np.all(np.isfinite(got))
+    pick = [0, 33]
+    args = oracle_room_args(oracle_mod, w)
+    peak = np.max(np.abs(got[0, pick]), axis=-1)  # direct path lies in the first window
+    for k0, k1 in [(0, 1500), (47000, 48200), (94800, 96000)]:
+        ref = oracle_mod.rir(*args, w.src, w.rcv[pick], k_begin=k0, k_end=k1)
+        err = np.max(np.abs(got[0, pick, k0:k1] - ref[0]), axis=-1) / peak
+        print("window", k0, k1, "rel err", err)
+        assert np.all(err <= TOL_FP32)
+
+
+def test_invalid_pair_gives_nan():
+    import torch
+
+    room = ism.Room([4.0, 5.0, 3.0], [0.9] * 6, (10, 10, 10), 343.0, 16000.0, 0.05, 0.004)
+    src = np.array([[1.0, 1.0, 1.0]], dtype=np.float32)
+    rcv = np.array([[2.0, 2.0, 2.0], [1.0, 1.0, 1.0], [3.0, 4.0, 2.5], [5.0, 1.0, 1.0]], dtype=np.float32)
+    sim = ism.Simulator(room, src, rcv, check=False)
+    _say("invalid pairs")
+    out = sim.run()
+    torch.cuda.synchronize()
+    h = out.cpu().numpy()
+    assert np.all(np.isfinite(h[0, 0])) and np.all(np.isfinite(h[0, 2]))
+    assert np.all(np.isnan(h[0, 1])) and np.all(np.isnan(h[0, 3]))
+
+
+def test_repeatable_and_split_invariant(monkeypatch):
+    import torch
+
+    w = workloads.room_32_receivers(1)
+    room = ism.room_for(w)
+    _say("repeatability")
+    a = _gpu_rir(room, w.src, w.rcv[:8])
+    b = _gpu_rir(room, w.src, w.rcv[:8])
+    peak = np.max(np.abs(a), axis=-1)
+    assert np.all(np.max(np.abs(a - b), axis=-1) <= 1e-7 * peak)
+    monkeypatch.setenv("ISM_TARGET_TAPS", "20000")  # many more work items per tile
+    c = _gpu_rir(room, w.src, w.rcv[:8])
+    assert np.all(np.max(np.abs(a - c), axis=-1) <= 2e-7 * peak)
