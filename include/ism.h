@@ -123,8 +123,8 @@ int ism_workspace_size(const ism_room *room, int n_src, int n_rcv, int precision
  * Positions live on the device, so they are checked on the device: a pair whose
  * source or receiver is not strictly inside the room, or whose source equals
  * its receiver, gets an RIR filled with NaN (call ism_check_positions on a host
- * copy to get a status instead). Taps are summed in FP64 and rounded to FP32
- * once, so repeated calls agree to within one FP32 rounding of each sample.
+ * copy to get a status instead). The summation order is fixed, so repeated
+ * calls with the same arguments give bitwise identical results.
  * Asynchronous; out and ws must stay valid until the stream reaches it. */
 int ism_simulate(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
                  int precision, float *out, void *ws, size_t ws_bytes, void *stream);

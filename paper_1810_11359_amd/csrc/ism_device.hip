@@ -9,7 +9,7 @@
 //                      enumerates exactly the lattice images whose window can
 //                      reach the tile, computes each image's delay and amplitude
 //                      (Eq. (2)-(4)) and adds its Hann-windowed-sinc taps (Eq. (6))
-//                      into an LDS tile with FP64 LDS atomics (Eq. (5)).
+//                      into wave-private FP32 LDS tiles (Eq. (5)).
 //   reduce_kernel      sums, in a fixed order, the partial tiles of tiles that
 //                      were split over several work items.
 //
@@ -155,7 +155,8 @@ __device__ __forceinline__ void small_sincos(float phi, float &s, float &c) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void tables_kernel(RoomArgs ra, const float *__restrict__ src,
                                                      const float *__restrict__ rcv, AxisEntry *__restrict__ tab,
-                                                     int *__restrict__ valid, int n_rir) {
+                                                     AxisOrigin *__restrict__ origin, int *__restrict__ valid,
+                                                     int n_rir) {
   const int64_t total = (int64_t)n_rir * ra.n_tab;
   for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
        gid += (int64_t)gridDim.x * blockDim.x) {
@@ -190,12 +191,16 @@ __global__ __launch_bounds__(256) void tables_kernel(RoomArgs ra, const float *_
     tab[gid] = AxisEntry{v, ve, g, 0.0f};
     if (e == 0) {
       bool ok = true, same = true;
+      AxisOrigin o;
       for (int b = 0; b < 3; ++b) {
         const float sb = src[3 * si + b], rb = rcv[3 * ri + b];
         ok = ok && sb > 0.0f && (sb - ra.L_hi[b]) < ra.L_lo[b] && rb > 0.0f && (rb - ra.L_hi[b]) < ra.L_lo[b];
         same = same && (sb == rb);
+        o.e_even[b] = (sb - rb) * ra.q_hi;
+        o.e_odd[b] = (-sb - rb) * ra.q_hi;
       }
       valid[rir] = (ok && !same) ? 1 : 0;
+      origin[rir] = o;
     }
   }
 }
@@ -217,34 +222,67 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-// Smallest i in [0, n] with t[i].d_hi >= b (t[].d_hi is strictly increasing).
-__device__ __forceinline__ int first_ge(const AxisEntry *__restrict__ t, int n, float b) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (t[mid].d_hi < b) lo = mid + 1;
-    else hi = mid;
+
+// Image displacements along one axis are strictly increasing in the lattice
+// index n: even n = 2m at m P + e_even, odd n = 2m - 1 at m P + e_odd (P = 2 L q).
+// first_ge returns the table index (n - lo) of the first n with displacement
+// >= b, or N if there is none. Float rounding can move the answer by one index
+// only for images within ~1e-3 samples of b; callers widen their bounds by a
+// sample so such images lie outside the band that matters.
+struct AxisRange {
+  int lo, N;
+  float inv_p, e_even, e_odd;
+};
+__device__ __forceinline__ int family_first(float b, float e, float inv_p, int m_lo, int m_hi) {
+  // smallest m in [m_lo, m_hi] with m P + e >= b, or m_hi + 1
+  const float mf = ceilf((b - e) * inv_p);
+  if (!(mf > (float)m_lo)) return m_lo;  // also -inf
+  if (mf > (float)(m_hi + 1)) return m_hi + 1;
+  return (int)mf;
+}
+__device__ __forceinline__ int first_ge(const AxisRange &a, float b) {
+  const int hi = a.lo + a.N;  // exclusive
+  int best = hi;
+  const int me_lo = (a.lo + 1) >> 1, me_hi = (hi - 1) >> 1;  // even n = 2m in [lo, hi)
+  if (me_lo <= me_hi) {
+    const int m = family_first(b, a.e_even, a.inv_p, me_lo, me_hi);
+    if (m <= me_hi) best = min(best, 2 * m);
   }
-  return lo;
+  const int mo_lo = (a.lo + 2) >> 1, mo_hi = hi >> 1;  // odd n = 2m - 1 in [lo, hi)
+  if (mo_lo <= mo_hi) {
+    const int m = family_first(b, a.e_odd, a.inv_p, mo_lo, mo_hi);
+    if (m <= mo_hi) best = min(best, 2 * m - 1);
+  }
+  return best - a.lo;
 }
 
 // ---------------------------------------------------------------------------
 // Kernel 2: enumeration of the image shell of one tile + windowed-sinc taps.
+//
+// Each wave accumulates into its own FP32 tile in LDS with plain
+// read-add-write, one tap at a time: within one instruction the active lanes
+// hold images with distinct first-tap positions (enforced by a byte claim per
+// position), and a compiler barrier between taps keeps every lane's
+// read-modify-write of tap j ahead of any lane's access for tap j + 1, so
+// overlapping windows of different lanes never race. At the end the wave tiles
+// are summed in a fixed order, which makes results bitwise reproducible.
 // ---------------------------------------------------------------------------
-constexpr int QCAP = 512;  // per-wave queue of candidate images
+constexpr int QCAP = 256;  // per-wave queue of candidate images
 
 template <int WT, int NW>
 __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
+                                                             const AxisOrigin *__restrict__ origin,
                                                              const int *__restrict__ valid, float *__restrict__ out,
                                                              float *__restrict__ part) {
   constexpr int JLO = 1 - WT / 2;
   constexpr int JHI = WT / 2;
   constexpr int MARGIN = WT;
-  constexpr int ACC = TILE + 2 * MARGIN;
+  constexpr int SPAN = TILE + 2 * MARGIN;
   constexpr TapConsts<WT> K = make_tap_consts<WT>();
 
-  __shared__ double acc[ACC];
+  __shared__ float tile[NW][SPAN];
+  __shared__ uint8_t claim[NW][SPAN];
   __shared__ uint32_t queue[NW][QCAP];
   __shared__ float col_sh[NW][64], col_sl[NW][64], col_g[NW][64];
   __shared__ int nx_pref[NW][64], nx_nylo[NW][64];
@@ -264,12 +302,12 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
     }
     pos = lo;
   }
-  const int tile = pa.n_tiles - 1 - pos;
-  const int C = pa.chunks[tile];
+  const int tile_id = pa.n_tiles - 1 - pos;
+  const int C = pa.chunks[tile_id];
   const uint32_t rel = item - pa.first_item[pos];
   const int rir = (int)(rel / (uint32_t)C);
   const int c = (int)(rel % (uint32_t)C);
-  const int T0 = tile * TILE;
+  const int T0 = tile_id * TILE;
   const int T1 = min(T0 + TILE, ra.n_samples);
   float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + T0 : part + (size_t)item * TILE;
 
@@ -281,11 +319,17 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
   const AxisEntry *__restrict__ tx = tab + ra.off[0];
   const AxisEntry *__restrict__ ty = tab + ra.off[1];
   const AxisEntry *__restrict__ tz = tab + ra.off[2];
+  const AxisOrigin org = origin[rir];
+  const AxisRange ax{ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]};
+  const AxisRange ay{ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]};
+  const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
 
-  for (int i = threadIdx.x; i < ACC; i += NW * 64) acc[i] = 0.0;
+  float *__restrict__ wt = tile[wave];
+  uint8_t *__restrict__ wc = claim[wave];
+  for (int i = lane; i < SPAN; i += 64) wt[i] = 0.0f;
 
   // Images whose window reaches the tile have delay x in (T0 - W/2, T1 - 1 + W/2);
-  // the enumeration bounds are widened by one sample on each side and every
+  // the enumeration bounds are widened by two samples on each side and every
   // candidate is then filtered exactly on its integer delay.
   const float R1 = (float)(T1 - 1) + ra.half_w + 2.0f;
   const float R0 = (float)T0 - ra.half_w - 2.0f;
@@ -297,9 +341,36 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
   float dlo = -INFINITY, dhi = INFINITY;
   if (c > 0) dlo = -R1 + (2.0f * R1) * ((float)c / (float)C);
   if (c < C - 1) dhi = -R1 + (2.0f * R1) * ((float)(c + 1) / (float)C);
-  const int nx_a = max(first_ge(tx, ra.N[0], dlo), first_ge(tx, ra.N[0], -R1));
-  const int nx_b = min(first_ge(tx, ra.N[0], dhi), first_ge(tx, ra.N[0], R1));
-  __syncthreads();
+  const int nx_a = max(first_ge(ax, dlo), first_ge(ax, -R1));
+  const int nx_b = min(first_ge(ax, dhi), first_ge(ax, R1));
+
+  // Image held by this lane, with its tap parameters.
+  bool has = false;
+  float f = 0.0f, C2 = 0.0f, CP = 0.0f, CQ = 0.0f;
+  int base = 0;
+
+  // Claim positions, add the taps of the winning lanes (distinct bases).
+  auto tap_round = [&]() {
+    volatile uint8_t *vc = wc;
+    if (has) vc[base] = (uint8_t)lane;
+    wave_sync();
+    const bool win = has && vc[base] == (uint8_t)lane;
+    if (win) {
+      float *t = wt + base;
+#pragma unroll
+      for (int jj = 0; jj < WT; ++jj) {
+        const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
+        const float r = __builtin_amdgcn_rcpf(u);
+        float w = __builtin_fmaf(K.cth[jj], CP, C2);
+        w = __builtin_fmaf(K.sth[jj], CQ, w);
+        const float o = t[jj];
+        t[jj] = __builtin_fmaf(w, r, o);
+        __asm__ volatile("" ::: "memory");
+      }
+    }
+    has = has && !win;
+    wave_sync();
+  };
 
   for (int nx0 = nx_a; nx0 < nx_b; nx0 += 64) {
     // lanes = x indices: y range of the columns that reach the outer sphere
@@ -312,8 +383,8 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
       ff_sub(r1h, r1l, qh, ql, rh, rl);
       if (rh > 0.0f) {
         const float R = __builtin_sqrtf(rh) + 1.0f;
-        ny_lo = first_ge(ty, ra.N[1], -R);
-        ny_cnt = first_ge(ty, ra.N[1], R) - ny_lo;
+        ny_lo = first_ge(ay, -R);
+        ny_cnt = first_ge(ay, R) - ny_lo;
       }
     }
     const int incl_y = wave_incl_scan(ny_cnt);
@@ -353,13 +424,13 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
             if (hh > 0.0f) zmin = fmaxf(__builtin_sqrtf(hh) - 1.0f, 0.0f);
           }
           if (zmin > 0.0f) {
-            z1 = first_ge(tz, ra.N[2], -zmax);
-            n1 = first_ge(tz, ra.N[2], -zmin) - z1;
-            z2 = first_ge(tz, ra.N[2], zmin);
-            n2 = first_ge(tz, ra.N[2], zmax) - z2;
+            z1 = first_ge(az, -zmax);
+            n1 = max(first_ge(az, -zmin) - z1, 0);
+            z2 = first_ge(az, zmin);
+            n2 = max(first_ge(az, zmax) - z2, 0);
           } else {
-            z1 = first_ge(tz, ra.N[2], -zmax);
-            n1 = first_ge(tz, ra.N[2], zmax) - z1;
+            z1 = first_ge(az, -zmax);
+            n1 = max(first_ge(az, zmax) - z1, 0);
           }
         }
       }
@@ -377,13 +448,15 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
         }
         wave_sync();
         const int qn = min(QCAP, total - q0);
-        for (int b0 = 0; b0 < qn; b0 += 64) {
-          // lanes = images
-          bool keep = false;
-          float f = 0.0f, C2 = 0.0f, CP = 0.0f, CQ = 0.0f;
-          int base = 0;
-          if (b0 + lane < qn) {
-            const uint32_t ent = queue[wave][b0 + lane];
+        int qpos = 0;
+        while (qpos < qn) {
+          // refill the lanes without an image from the queue (lanes = images)
+          const bool need = !has;
+          const uint64_t need_mask = __ballot(need);
+          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need_mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
+          if (need && qpos + rank < qn) {
+            const uint32_t ent = queue[wave][qpos + rank];
             const int cl = (int)(ent >> 16);
             const int nz = (int)(ent & 0xffffu);
             const AxisEntry ez = tz[nz];
@@ -397,21 +470,21 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
             const float rx = __builtin_amdgcn_rcpf(x0);
             const float xl = (__builtin_fmaf(-x0, x0, Sh) + Sl) * (0.5f * rx);
             float kf = floorf(x0);
-            f = (x0 - kf) + xl;
-            if (f < 0.0f) {
-              f += 1.0f;
+            float fr = (x0 - kf) + xl;
+            if (fr < 0.0f) {
+              fr += 1.0f;
               kf -= 1.0f;
             }
-            if (f >= 1.0f) {
-              f -= 1.0f;
+            if (fr >= 1.0f) {
+              fr -= 1.0f;
               kf += 1.0f;
             }
             const int k0 = (int)kf;
             base = k0 + JLO - T0 + MARGIN;
-            keep = (x0 < 1.0e9f) && (k0 + JHI >= T0) && (k0 + JLO <= T1 - 1) && base >= 0 && base + WT <= ACC;
+            has = (x0 < 1.0e9f) && (k0 + JHI >= T0) && (k0 + JLO <= T1 - 1) && base >= 0 && base + WT <= SPAN;
             // Eq. (4) amplitude and the per-image factors of the taps
             const float A = col_g[wave][cl] * ez.gain * ra.kappa * rx;
-            f = fmaxf(f, 0x1p-100f);
+            f = fmaxf(fr, 0x1p-100f);
             const float Cc = A * sinpi_over_pi(fminf(f, 1.0f - f));
             float sp, cp;
             small_sincos(f * ra.two_pi_over_w, sp, cp);
@@ -419,89 +492,86 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
             CP = C2 * cp;
             CQ = C2 * sp;
           }
-          if (keep) {
-            double *a = acc + base;
-#pragma unroll
-            for (int jj = 0; jj < WT; ++jj) {
-              const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
-              const float r = __builtin_amdgcn_rcpf(u);
-              float w = __builtin_fmaf(K.cth[jj], CP, C2);
-              w = __builtin_fmaf(K.sth[jj], CQ, w);
-              __hip_atomic_fetch_add(a + jj, (double)(w * r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-          }
+          qpos += __builtin_popcountll(need_mask);
+          tap_round();
         }
         wave_sync();
       }
     }
     wave_sync();
   }
+  // images still waiting after their queue ran out
+  while (__ballot(has) != 0) tap_round();
+
   __syncthreads();
-  for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) dst[k] = (float)acc[MARGIN + k];
+  for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) {
+    float v = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += tile[w][MARGIN + k];
+    dst[k] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Kernel 3: ordered sum of the partial tiles of split tiles.
+// grid = (rir, dispatch position of the tile, 256-sample segment)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, const uint16_t *multi_unused,
-                                                     const float *__restrict__ part, float *__restrict__ out,
-                                                     int n_multi_rows) {
-  (void)multi_unused;
-  (void)n_multi_rows;
-  // blockIdx.y = dispatch position of the tile, blockIdx.x = rir
+__global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, const float *__restrict__ part,
+                                                     float *__restrict__ out) {
   const int pos = blockIdx.y;
-  const int tile = pa.n_tiles - 1 - pos;
-  const int C = pa.chunks[tile];
+  const int tile_id = pa.n_tiles - 1 - pos;
+  const int C = pa.chunks[tile_id];
   if (C <= 1) return;
   const int rir = blockIdx.x;
-  const int T0 = tile * TILE;
+  const int T0 = tile_id * TILE;
   const int T1 = min(T0 + TILE, ra.n_samples);
+  const int k = blockIdx.z * 256 + threadIdx.x;
+  if (k >= T1 - T0) return;
   const size_t first = (size_t)pa.first_item[pos] + (size_t)rir * C;
-  for (int k = threadIdx.x; k < T1 - T0; k += blockDim.x) {
-    float v = 0.0f;
-    for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
-    out[(size_t)rir * ra.n_samples + T0 + k] = v;
-  }
+  float v = 0.0f;
+  for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
+  out[(size_t)rir * ra.n_samples + T0 + k] = v;
 }
 
 // ---------------------------------------------------------------------------
 // Launchers (called from ism_host.cpp).
 // ---------------------------------------------------------------------------
-int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, int *valid, int n_rir,
-                  hipStream_t st) {
+int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
+                  int *valid, int n_rir, hipStream_t st) {
   const int64_t total = (int64_t)n_rir * ra.n_tab;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65535) blocks = 65535;
-  hipLaunchKernelGGL(tables_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ra, src, rcv, tab, valid, n_rir);
+  hipLaunchKernelGGL(tables_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ra, src, rcv, tab, origin, valid,
+                     n_rir);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int WT>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
-                        const int *valid, float *out, float *part, hipStream_t st) {
+                        const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st) {
   constexpr int NW = 4;
-  hipLaunchKernelGGL((accumulate_kernel<WT, NW>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, valid, out,
-                     part);
+  hipLaunchKernelGGL((accumulate_kernel<WT, NW>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, origin, valid,
+                     out, part);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt == 128; }
 
 int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
-                      const int *valid, float *out, float *part, hipStream_t st) {
+                      const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st) {
   switch (wt) {
-    case 32: return launch_acc_w<32>(ra, pa, n_items, tab, valid, out, part, st);
-    case 64: return launch_acc_w<64>(ra, pa, n_items, tab, valid, out, part, st);
-    case 96: return launch_acc_w<96>(ra, pa, n_items, tab, valid, out, part, st);
-    case 128: return launch_acc_w<128>(ra, pa, n_items, tab, valid, out, part, st);
+    case 32: return launch_acc_w<32>(ra, pa, n_items, tab, origin, valid, out, part, st);
+    case 64: return launch_acc_w<64>(ra, pa, n_items, tab, origin, valid, out, part, st);
+    case 96: return launch_acc_w<96>(ra, pa, n_items, tab, origin, valid, out, part, st);
+    case 128: return launch_acc_w<128>(ra, pa, n_items, tab, origin, valid, out, part, st);
     default: return -2;
   }
 }
 
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
                   hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)n_rir, (unsigned)pa.n_tiles), dim3(256), 0, st, ra, pa,
-                     (const uint16_t *)nullptr, part, out, 0);
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)n_rir, (unsigned)pa.n_tiles, TILE / 256), dim3(256), 0, st, ra,
+                     pa, part, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

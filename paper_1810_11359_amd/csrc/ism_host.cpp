@@ -14,10 +14,10 @@
 #include "ism_internal.h"
 
 namespace ism {
-int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, int *valid, int n_rir,
-                  hipStream_t st);
+int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
+                  int *valid, int n_rir, hipStream_t st);
 int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
-                      const int *valid, float *out, float *part, hipStream_t st);
+                      const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st);
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
                   hipStream_t st);
 bool supported_window(int wt);
@@ -59,7 +59,7 @@ struct Plan {
   int n_rir;
   uint32_t n_items;
   bool any_split;
-  size_t off_valid, off_tab, off_part, ws_bytes;
+  size_t off_valid, off_origin, off_tab, off_part, ws_bytes;
 };
 
 int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
@@ -83,6 +83,8 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
     ra.N[a] = r->n_img[a];
     ra.off[a] = off;
     off += r->n_img[a];
+    ra.period[a] = (float)(2.0 * r->room[a] * q);
+    ra.inv_period[a] = (float)(1.0 / (2.0 * r->room[a] * q));
   }
   for (int i = 0; i < 6; ++i) ra.beta[i] = (float)r->beta[i];
   ra.n_tab = off;
@@ -126,7 +128,8 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   p.n_items = (uint32_t)acc;
 
   p.off_valid = 0;
-  p.off_tab = align_up(sizeof(int) * (size_t)p.n_rir);
+  p.off_origin = align_up(sizeof(int) * (size_t)p.n_rir);
+  p.off_tab = align_up(p.off_origin + sizeof(AxisOrigin) * (size_t)p.n_rir);
   p.off_part = align_up(p.off_tab + sizeof(AxisEntry) * (size_t)p.n_rir * ra.n_tab);
   p.ws_bytes = p.off_part + (p.any_split ? sizeof(float) * (size_t)p.n_items * TILE : 0);
   return ISM_OK;
@@ -302,11 +305,12 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
   hipStream_t s = (hipStream_t)stream;
   char *w = (char *)ws;
   int *valid = (int *)(w + p.off_valid);
+  AxisOrigin *origin = (AxisOrigin *)(w + p.off_origin);
   AxisEntry *tab = (AxisEntry *)(w + p.off_tab);
   float *part = p.any_split ? (float *)(w + p.off_part) : nullptr;
-  if (launch_tables(p.ra, src, rcv, tab, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
+  if (launch_tables(p.ra, src, rcv, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, s) != hipSuccess) return ISM_E_DEVICE;
-  if (launch_accumulate(p.wt, p.ra, p.pa, p.n_items, tab, valid, out, part, s) != 0) return ISM_E_DEVICE;
+  if (launch_accumulate(p.wt, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, s) != 0) return ISM_E_DEVICE;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
   if (p.any_split && launch_reduce(p.ra, p.pa, p.n_rir, part, out, s) != 0) return ISM_E_DEVICE;
   return ISM_OK;

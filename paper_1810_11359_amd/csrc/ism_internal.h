@@ -29,6 +29,8 @@ struct RoomArgs {
   float half_w;            // W / 2
   int n_samples;           // nS
   int n_src, n_rcv;
+  float period[3];         // 2 L q: displacement step between images of one parity [samples]
+  float inv_period[3];     // 1 / period
 };
 
 // Work decomposition of one call. Items are ordered by tile (last tile first,
@@ -47,6 +49,12 @@ struct PlanArgs {
 // factor of the reflection gain.
 struct AxisEntry {
   float d_hi, d_lo, gain, pad;
+};
+
+// Per-RIR offsets of the two image families of each axis, in samples: even
+// n = 2m sits at m*period + e_even, odd n = 2m - 1 at m*period + e_odd.
+struct AxisOrigin {
+  float e_even[3], e_odd[3];
 };
 
 }  // namespace ism
