@@ -54,26 +54,38 @@ class _HipEvents:
         self.hip.hipEventDestroy(ctypes.c_void_p(ev))
 
 
-def cpu_baseline(w, n_rcv_sample: int):
-    """FP64 oracle on the first ``n_rcv_sample`` receivers of the workload (full RIRs)."""
-    from oracle import oracle as orc
-
-    orc.build()
+def _oracle_args(orc, w):
     beta = orc.beta_from_t60(w.room, w.t60)
     if w.beta_jitter is not None:
         beta = np.minimum(beta * np.asarray(w.beta_jitter), 0.999)
     n = orc.n_img_for_time(w.room, w.c, w.t_max)
-    args = (w.room, beta, n, w.c, w.fs, w.t_max, w.t_w)
-    rcv = w.rcv[:n_rcv_sample]
-    threads = max(1, min(os.cpu_count() or 1, 16, rcv.shape[0] * w.src.shape[0]))
-    taps = orc.count_taps(*args, w.src, rcv)
+    return (w.room, beta, n, w.c, w.fs, w.t_max, w.t_w)
+
+
+def cpu_baseline(ws, n_rcv_sample: int):
+    """FP64 oracle on a bounded sample: the first ``n_rcv_sample`` receivers of a
+    single-room workload, or the first rooms of a batch up to that many RIRs."""
+    from oracle import oracle as orc
+
+    orc.build()
+    jobs, left = [], n_rcv_sample
+    for w in ws:
+        if left <= 0:
+            break
+        k = min(left, w.rcv.shape[0])
+        jobs.append((w, w.rcv[:k]))
+        left -= k
+    threads = max(1, min(os.cpu_count() or 1, 16, sum(r.shape[0] for _, r in jobs)))
+    taps = sum(orc.count_taps(*_oracle_args(orc, w), w.src, r) for w, r in jobs)
     t0 = time.perf_counter()
-    orc.rir(*args, w.src, rcv, n_threads=threads)
+    for w, r in jobs:
+        orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=min(threads, r.shape[0]))
     dt = time.perf_counter() - t0
+    n = sum(r.shape[0] for _, r in jobs)
     return {"value": taps / dt / 1e9, "unit": "G taps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{w.src.shape[0]} source x {rcv.shape[0]} receivers of the workload, full RIRs "
-                      f"({taps} taps, {dt:.2f} s wall, {threads} threads)",
-            "rirs_per_s": rcv.shape[0] * w.src.shape[0] / dt}
+            "sample": f"{n} full RIRs of the workload ({len(jobs)} room(s); {taps} taps, {dt:.2f} s wall, "
+                      f"up to {threads} threads)",
+            "rirs_per_s": n / dt}
 
 
 def main() -> int:
@@ -82,7 +94,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="room_32_receivers",
-                    choices=["room_32_receivers", "single_rir", "large_room_uca"])
+                    choices=["room_32_receivers", "single_rir", "large_room_uca", "batch_rooms"])
     ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -95,11 +107,32 @@ def main() -> int:
 
     from paper_1810_11359_amd import ism, workloads
 
-    w = workloads.WORKLOADS[args.workload](0)
-    room = ism.room_for(w)
-    sim = ism.Simulator(room, w.src, w.rcv)
-    n_rir = sim.n_src * sim.n_rcv
-    taps = ism.count_taps(room, w.src, w.rcv)
+    if args.workload == "batch_rooms":
+        def feasible(room, t60):
+            try:
+                ism.beta_from_t60(room, t60)
+                return True
+            except ism.IsmError:
+                return False
+
+        ws = workloads.batch_rooms(1024, seed=0, feasible=feasible)
+        rooms = [ism.room_for(w) for w in ws]
+        sim = ism.BatchSimulator([(r, w.src, w.rcv) for r, w in zip(rooms, ws)])
+        n_rir = sim.n_rirs
+        taps = sum(ism.count_taps(r, w.src, w.rcv) for r, w in zip(rooms, ws))
+        config = {"workload": f"batch_1024_rooms_{n_rir}_rirs", "n_rooms": len(ws), "n_rirs": n_rir, "fs": 16000.0,
+                  "t_w_s": 0.004, "room_m": "U(3,10)^3", "t60_s": "U(0.2,1.0)", "taps_per_step": int(taps),
+                  "parallelism": "single GPU"}
+    else:
+        w = workloads.WORKLOADS[args.workload](0)
+        ws = [w]
+        room = ism.room_for(w)
+        sim = ism.Simulator(room, w.src, w.rcv)
+        n_rir = sim.n_src * sim.n_rcv
+        taps = ism.count_taps(room, w.src, w.rcv)
+        config = {"workload": w.name, "room_m": list(map(float, w.room)), "t60_s": w.t60, "fs": w.fs,
+                  "t_w_s": w.t_w, "n_src": int(sim.n_src), "n_rcv": int(sim.n_rcv), "n_samples": room.n_samples,
+                  "n_img": list(room.n_img), "taps_per_step": int(taps), "parallelism": "single GPU"}
     hip = _HipEvents()
     ev_a = [hip.create() for _ in range(args.steps)]
     ev_b = [hip.create() for _ in range(args.steps)]
@@ -138,18 +171,17 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": w.name, "room_m": list(map(float, w.room)), "t60_s": w.t60, "fs": w.fs,
-                   "t_w_s": w.t_w, "n_src": int(sim.n_src), "n_rcv": int(sim.n_rcv), "n_samples": room.n_samples,
-                   "n_img": list(room.n_img), "taps_per_step": int(taps), "parallelism": "single GPU"},
+        "config": config,
         "rirs_per_s": n_rir / (ms_step / 1e3),
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
-                     "kernel": "accumulate_kernel", "kernel_ms_mean": kmean,
+                     "kernel": "accumulate_kernel" if args.workload != "batch_rooms" else "accumulate_batch_kernel",
+                     "kernel_ms_mean": kmean,
                      "kernel_ms_p50": float(np.median(kern_ms)), "flop_per_tap": FLOP_PER_TAP},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, sim.n_rcv))
+        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_sample)
     print(json.dumps(out), flush=True)
     return 0
 

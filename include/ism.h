@@ -138,6 +138,47 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
                        int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
                        void *ev_stop);
 
+/* ---- Batches of rooms --------------------------------------------------------- */
+
+/* One job of a batch: one room with its own sources, receivers and output. */
+typedef struct {
+  ism_room room;
+  const float *src; /* device float32 [n_src][3] */
+  int n_src;
+  const float *rcv; /* device float32 [n_rcv][3] */
+  int n_rcv;
+  float *out;       /* device float32 [n_src][n_rcv][nS(room)], caller-owned, overwritten */
+} ism_job;
+
+/* Host-side record of a prepared batch, filled by ism_batch_prepare and read by
+ * ism_batch_run. Caller-owned plain memory; its contents are private. */
+typedef struct {
+  uint64_t opaque[40];
+} ism_batch;
+
+/* Device workspace (bytes) for a batch of n_jobs jobs (host array). */
+int ism_batch_workspace_size(const ism_job *jobs, int n_jobs, int precision, size_t *bytes);
+
+/* Plans a batch on the host (every job checked as in ism_simulate; the first
+ * failing job's status is returned), uploads the job and work tables into ws
+ * (a blocking host-to-device copy on stream), and fills *batch. After it
+ * returns, jobs may be freed; the device pointers inside them must stay valid
+ * for every ism_batch_run of this batch. Work items of all jobs are ordered by
+ * decreasing estimated work, so rooms of very different sizes share one launch
+ * per window length (Sec. 3 discusses why uneven image counts made the paper
+ * process one room per call). */
+int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, size_t ws_bytes, void *stream,
+                      ism_batch *batch);
+
+/* Simulates every job of a prepared batch on stream: kernel launches only (no
+ * host-device copies, no allocation), so it can be captured in a HIP graph and
+ * replayed. Results are bitwise identical to ism_simulate of each job. */
+int ism_batch_run(const ism_batch *batch, void *stream);
+
+/* ism_batch_run that also records the caller's HIP events ev_start before the
+ * first and ev_stop after the last tap-accumulation launch (either may be NULL). */
+int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, void *ev_stop);
+
 #ifdef __cplusplus
 }
 #endif

@@ -153,6 +153,52 @@ __device__ __forceinline__ void small_sincos(float phi, float &s, float &c) {
 // ---------------------------------------------------------------------------
 // Kernel 1: per-RIR axis tables.
 // ---------------------------------------------------------------------------
+// Table entry e (axis a, lattice index n) of the RIR with source s, receiver r.
+__device__ __forceinline__ AxisEntry table_entry(const RoomArgs &ra, const float *__restrict__ s3,
+                                                 const float *__restrict__ r3, int e) {
+  const int a = e < ra.off[1] ? 0 : (e < ra.off[2] ? 1 : 2);
+  const int n = ra.lo[a] + (e - ra.off[a]);
+  const float s = s3[a], r = r3[a];
+  // Eq. (1): even n -> n L + s, odd n -> (n + 1) L - s.
+  const bool odd = (n & 1) != 0;
+  const float m = (float)(odd ? n + 1 : n);
+  float p, pe;
+  two_prod(m, ra.L_hi[a], p, pe);
+  pe = __builtin_fmaf(m, ra.L_lo[a], pe);
+  float t, te;
+  two_sum(odd ? -s : s, -r, t, te);  // exact
+  float u, ue;
+  two_sum(p, t, u, ue);
+  ue += pe + te;
+  fast_two_sum(u, ue, u, ue);
+  // times fs / c: displacement in samples
+  float v, ve;
+  two_prod(u, ra.q_hi, v, ve);
+  ve = __builtin_fmaf(u, ra.q_lo, ve);
+  ve = __builtin_fmaf(ue, ra.q_hi, ve);
+  fast_two_sum(v, ve, v, ve);
+  // Gain factor: the path from image n crosses |floor(n/2)| copies of the wall
+  // at 0 and |ceil(n/2)| copies of the wall at L along this axis.
+  const int e0 = abs(n >> 1), e1 = abs((n + 1) >> 1);
+  const float g = ff_pow(ra.beta[2 * a], e0) * ff_pow(ra.beta[2 * a + 1], e1);
+  return AxisEntry{v, ve, g, 0.0f};
+}
+
+// Validity of a pair (both points strictly inside, distinct) and the family
+// offsets of its axes.
+__device__ __forceinline__ int rir_header(const RoomArgs &ra, const float *__restrict__ s3,
+                                          const float *__restrict__ r3, AxisOrigin &o) {
+  bool ok = true, same = true;
+  for (int b = 0; b < 3; ++b) {
+    const float sb = s3[b], rb = r3[b];
+    ok = ok && sb > 0.0f && (sb - ra.L_hi[b]) < ra.L_lo[b] && rb > 0.0f && (rb - ra.L_hi[b]) < ra.L_lo[b];
+    same = same && (sb == rb);
+    o.e_even[b] = (sb - rb) * ra.q_hi;
+    o.e_odd[b] = (-sb - rb) * ra.q_hi;
+  }
+  return (ok && !same) ? 1 : 0;
+}
+
 __global__ __launch_bounds__(256) void tables_kernel(RoomArgs ra, const float *__restrict__ src,
                                                      const float *__restrict__ rcv, AxisEntry *__restrict__ tab,
                                                      AxisOrigin *__restrict__ origin, int *__restrict__ valid,
@@ -162,46 +208,34 @@ __global__ __launch_bounds__(256) void tables_kernel(RoomArgs ra, const float *_
        gid += (int64_t)gridDim.x * blockDim.x) {
     const int rir = (int)(gid / ra.n_tab);
     const int e = (int)(gid % ra.n_tab);
-    const int si = rir / ra.n_rcv, ri = rir % ra.n_rcv;
-    const int a = e < ra.off[1] ? 0 : (e < ra.off[2] ? 1 : 2);
-    const int n = ra.lo[a] + (e - ra.off[a]);
-    const float s = src[3 * si + a], r = rcv[3 * ri + a];
-    // Eq. (1): even n -> n L + s, odd n -> (n + 1) L - s.
-    const bool odd = (n & 1) != 0;
-    const float m = (float)(odd ? n + 1 : n);
-    float p, pe;
-    two_prod(m, ra.L_hi[a], p, pe);
-    pe = __builtin_fmaf(m, ra.L_lo[a], pe);
-    float t, te;
-    two_sum(odd ? -s : s, -r, t, te);  // exact
-    float u, ue;
-    two_sum(p, t, u, ue);
-    ue += pe + te;
-    fast_two_sum(u, ue, u, ue);
-    // times fs / c: displacement in samples
-    float v, ve;
-    two_prod(u, ra.q_hi, v, ve);
-    ve = __builtin_fmaf(u, ra.q_lo, ve);
-    ve = __builtin_fmaf(ue, ra.q_hi, ve);
-    fast_two_sum(v, ve, v, ve);
-    // Gain factor: the path from image n crosses |floor(n/2)| copies of the wall
-    // at 0 and |ceil(n/2)| copies of the wall at L along this axis.
-    const int e0 = abs(n >> 1), e1 = abs((n + 1) >> 1);
-    const float g = ff_pow(ra.beta[2 * a], e0) * ff_pow(ra.beta[2 * a + 1], e1);
-    tab[gid] = AxisEntry{v, ve, g, 0.0f};
+    const float *s3 = src + 3 * (rir / ra.n_rcv);
+    const float *r3 = rcv + 3 * (rir % ra.n_rcv);
+    tab[gid] = table_entry(ra, s3, r3, e);
     if (e == 0) {
-      bool ok = true, same = true;
       AxisOrigin o;
-      for (int b = 0; b < 3; ++b) {
-        const float sb = src[3 * si + b], rb = rcv[3 * ri + b];
-        ok = ok && sb > 0.0f && (sb - ra.L_hi[b]) < ra.L_lo[b] && rb > 0.0f && (rb - ra.L_hi[b]) < ra.L_lo[b];
-        same = same && (sb == rb);
-        o.e_even[b] = (sb - rb) * ra.q_hi;
-        o.e_odd[b] = (-sb - rb) * ra.q_hi;
-      }
-      valid[rir] = (ok && !same) ? 1 : 0;
+      valid[rir] = rir_header(ra, s3, r3, o);
       origin[rir] = o;
     }
+  }
+}
+
+// Batch mode: one block per batch-wide RIR.
+__global__ __launch_bounds__(256) void tables_batch_kernel(const JobDev *__restrict__ jobs,
+                                                           const BatchRir *__restrict__ rirs,
+                                                           AxisEntry *__restrict__ tab,
+                                                           AxisOrigin *__restrict__ origin,
+                                                           int *__restrict__ valid) {
+  const BatchRir br = rirs[blockIdx.x];
+  const JobDev &jb = jobs[br.job];
+  const RoomArgs ra = jb.ra;
+  const float *s3 = jb.src + 3 * (br.rir / ra.n_rcv);
+  const float *r3 = jb.rcv + 3 * (br.rir % ra.n_rcv);
+  AxisEntry *t = tab + jb.tab_base + (size_t)br.rir * ra.n_tab;
+  for (int e = threadIdx.x; e < ra.n_tab; e += blockDim.x) t[e] = table_entry(ra, s3, r3, e);
+  if (threadIdx.x == 0) {
+    AxisOrigin o;
+    valid[blockIdx.x] = rir_header(ra, s3, r3, o);
+    origin[blockIdx.x] = o;
   }
 }
 
@@ -269,12 +303,13 @@ __device__ __forceinline__ int first_ge(const AxisRange &a, float b) {
 // ---------------------------------------------------------------------------
 constexpr int QCAP = 256;  // per-wave queue of candidate images
 
+// Work of one item: the taps of the images of the shell slab (chunk c of C) of
+// output tile tile_id of one RIR, written to dst (the RIR's samples of the
+// tile, or a partial tile when C > 1).
 template <int WT, int NW>
-__global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
-                                                             const AxisEntry *__restrict__ tab_all,
-                                                             const AxisOrigin *__restrict__ origin,
-                                                             const int *__restrict__ valid, float *__restrict__ out,
-                                                             float *__restrict__ part) {
+__device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
+                                                const AxisEntry *__restrict__ tab, const AxisOrigin &org,
+                                                const bool valid, float *__restrict__ dst) {
   constexpr int JLO = 1 - WT / 2;
   constexpr int JHI = WT / 2;
   constexpr int MARGIN = WT;
@@ -289,37 +324,16 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-
-  // ---- work item -> (tile, rir, chunk)
-  const uint32_t item = blockIdx.x;
-  int pos = 0;
-  {
-    int lo = 0, hi = pa.n_tiles;  // largest pos with first_item[pos] <= item
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (pa.first_item[mid] <= item) lo = mid;
-      else hi = mid;
-    }
-    pos = lo;
-  }
-  const int tile_id = pa.n_tiles - 1 - pos;
-  const int C = pa.chunks[tile_id];
-  const uint32_t rel = item - pa.first_item[pos];
-  const int rir = (int)(rel / (uint32_t)C);
-  const int c = (int)(rel % (uint32_t)C);
   const int T0 = tile_id * TILE;
   const int T1 = min(T0 + TILE, ra.n_samples);
-  float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + T0 : part + (size_t)item * TILE;
 
-  if (!valid[rir]) {
+  if (!valid) {
     for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) dst[k] = __builtin_nanf("");
     return;
   }
-  const AxisEntry *__restrict__ tab = tab_all + (size_t)rir * ra.n_tab;
   const AxisEntry *__restrict__ tx = tab + ra.off[0];
   const AxisEntry *__restrict__ ty = tab + ra.off[1];
   const AxisEntry *__restrict__ tz = tab + ra.off[2];
-  const AxisOrigin org = origin[rir];
   const AxisRange ax{ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]};
   const AxisRange ay{ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]};
   const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
@@ -512,6 +526,53 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
   }
 }
 
+// Single-room launch: the item index decodes through the per-tile chunk counts.
+template <int WT, int NW>
+__global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
+                                                             const AxisEntry *__restrict__ tab_all,
+                                                             const AxisOrigin *__restrict__ origin,
+                                                             const int *__restrict__ valid, float *__restrict__ out,
+                                                             float *__restrict__ part) {
+  const uint32_t item = blockIdx.x;
+  int pos = 0;
+  {
+    int lo = 0, hi = pa.n_tiles;  // largest pos with first_item[pos] <= item
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pa.first_item[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    pos = lo;
+  }
+  const int tile_id = pa.n_tiles - 1 - pos;
+  const int C = pa.chunks[tile_id];
+  const uint32_t rel = item - pa.first_item[pos];
+  const int rir = (int)(rel / (uint32_t)C);
+  const int c = (int)(rel % (uint32_t)C);
+  float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
+  const AxisOrigin org = origin[rir];
+  accumulate_item<WT, NW>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst);
+}
+
+// Batch launch: every item names its job; the job table carries the room.
+template <int WT, int NW>
+__global__ __launch_bounds__(NW * 64) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
+                                                                   const BatchItem *__restrict__ items,
+                                                                   const AxisEntry *__restrict__ tab_all,
+                                                                   const AxisOrigin *__restrict__ origin,
+                                                                   const int *__restrict__ valid,
+                                                                   float *__restrict__ part) {
+  const BatchItem it = items[blockIdx.x];
+  const JobDev &jb = jobs[it.job];
+  const RoomArgs ra = jb.ra;
+  const uint32_t grir = jb.rir_base + it.rir;
+  float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
+                                        : part + (size_t)it.slot * TILE;
+  const AxisOrigin org = origin[grir];
+  accumulate_item<WT, NW>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org,
+                          valid[grir] != 0, dst);
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 3: ordered sum of the partial tiles of split tiles.
 // grid = (rir, dispatch position of the tile, 256-sample segment)
@@ -531,6 +592,22 @@ __global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, c
   float v = 0.0f;
   for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
   out[(size_t)rir * ra.n_samples + T0 + k] = v;
+}
+
+// Batch mode: grid = (split tile, 256-sample segment).
+__global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restrict__ jobs,
+                                                           const BatchReduce *__restrict__ red,
+                                                           const float *__restrict__ part) {
+  const BatchReduce br = red[blockIdx.x];
+  const JobDev &jb = jobs[br.job];
+  const int n_samples = jb.ra.n_samples;
+  const int T0 = (int)br.tile * TILE;
+  const int T1 = min(T0 + TILE, n_samples);
+  const int k = blockIdx.y * 256 + threadIdx.x;
+  if (k >= T1 - T0) return;
+  float v = 0.0f;
+  for (int cc = 0; cc < br.chunks; ++cc) v += part[((size_t)br.first + cc) * TILE + k];
+  jb.out[(size_t)br.rir * n_samples + T0 + k] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -566,6 +643,43 @@ int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n
     case 128: return launch_acc_w<128>(ra, pa, n_items, tab, origin, valid, out, part, st);
     default: return -2;
   }
+}
+
+template <int WT>
+static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
+                              const AxisOrigin *origin, const int *valid, float *part, hipStream_t st) {
+  constexpr int NW = 4;
+  hipLaunchKernelGGL((accumulate_batch_kernel<WT, NW>), dim3(n_items), dim3(NW * 64), 0, st, jobs, items, tab, origin,
+                     valid, part);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
+                 const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
+                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
+                 hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
+  if (hipGetLastError() != hipSuccess) return -1;
+  if (ev_start && hipEventRecord(ev_start, st) != hipSuccess) return -1;
+  for (int k = 0; k < n_classes; ++k) {
+    if (class_count[k] == 0) continue;
+    const BatchItem *it = items + class_first[k];
+    int rc = -2;
+    switch (class_wt[k]) {
+      case 32: rc = launch_acc_batch_w<32>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
+      case 64: rc = launch_acc_batch_w<64>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
+      case 96: rc = launch_acc_batch_w<96>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
+      case 128: rc = launch_acc_batch_w<128>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
+      default: break;
+    }
+    if (rc != 0) return -1;
+  }
+  if (ev_stop && hipEventRecord(ev_stop, st) != hipSuccess) return -1;
+  if (n_red > 0) {
+    hipLaunchKernelGGL(reduce_batch_kernel, dim3(n_red, TILE / 256), dim3(256), 0, st, jobs, red, part);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  return 0;
 }
 
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,

@@ -21,6 +21,10 @@ int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
                   hipStream_t st);
 bool supported_window(int wt);
+int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
+                 const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
+                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
+                 hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 }  // namespace ism
 
 using namespace ism;
@@ -55,6 +59,7 @@ int even_window(const ism_room &r) {
 struct Plan {
   RoomArgs ra;
   PlanArgs pa;
+  double tile_taps[MAX_TILES];  // estimated taps of each tile's image shell
   int wt;
   int n_rir;
   uint32_t n_items;
@@ -113,6 +118,7 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
     const double x1 = T1 + W / 2.0, x0 = std::max(T0 - W / 2.0, 0.0);
     const double imgs = std::min(4.0 / 3.0 * kPi * (x1 * x1 * x1 - x0 * x0 * x0) / cell, lattice);
     const double taps = imgs * W;
+    p.tile_taps[t] = taps;
     int ch = (int)std::ceil(taps / target);
     ch = std::max(1, std::min(ch, MAX_CHUNKS));
     pa.chunks[t] = (uint8_t)ch;
@@ -314,6 +320,176 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
   if (p.any_split && launch_reduce(p.ra, p.pa, p.n_rir, part, out, s) != 0) return ISM_E_DEVICE;
   return ISM_OK;
+}
+
+// ---- batches ------------------------------------------------------------------
+
+namespace {
+
+constexpr int kMaxClasses = 4;
+
+struct BatchState {  // stored in ism_batch::opaque
+  uint64_t ws;
+  uint64_t off_jobs, off_rirs, off_items, off_red, off_valid, off_origin, off_tab, off_part;
+  uint32_t n_rir, n_red, n_classes, pad;
+  uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
+  int32_t class_wt[kMaxClasses];
+};
+static_assert(sizeof(BatchState) <= sizeof(ism_batch), "ism_batch too small");
+
+struct BatchPlan {
+  std::vector<JobDev> jobs;
+  std::vector<BatchRir> rirs;
+  std::vector<BatchItem> items;
+  std::vector<BatchReduce> red;
+  BatchState st;
+  size_t ws_bytes;
+};
+
+int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
+  if (!jobs || n_jobs < 1) return ISM_E_INVALID_ARG;
+  std::memset(&bp.st, 0, sizeof(bp.st));
+  bp.jobs.resize(n_jobs);
+  struct Cand {
+    double cost;
+    int cls;
+    BatchItem it;
+  };
+  std::vector<Cand> cand;
+  uint64_t tab_entries = 0, n_rir = 0;
+  uint32_t slots = 0;
+  int n_classes = 0;
+  int class_wt[kMaxClasses] = {0, 0, 0, 0};
+  for (int j = 0; j < n_jobs; ++j) {
+    const ism_job &jb = jobs[j];
+    Plan p;
+    const int stt = make_plan(&jb.room, jb.n_src, jb.n_rcv, precision, p);
+    if (stt != ISM_OK) return stt;
+    if (!jb.src || !jb.rcv || !jb.out) return ISM_E_INVALID_ARG;
+    int cls = -1;
+    for (int k = 0; k < n_classes; ++k)
+      if (class_wt[k] == p.wt) cls = k;
+    if (cls < 0) {
+      if (n_classes == kMaxClasses) return ISM_E_UNSUPPORTED;
+      cls = n_classes++;
+      class_wt[cls] = p.wt;
+    }
+    JobDev &d = bp.jobs[j];
+    std::memset(&d, 0, sizeof(d));
+    d.ra = p.ra;
+    d.src = jb.src;
+    d.rcv = jb.rcv;
+    d.out = jb.out;
+    d.tab_base = tab_entries;
+    d.rir_base = (uint32_t)n_rir;
+    for (int r = 0; r < p.n_rir; ++r) bp.rirs.push_back(BatchRir{(uint32_t)j, (uint32_t)r});
+    for (int t = 0; t < p.pa.n_tiles; ++t) {
+      const int C = p.pa.chunks[t];
+      for (int r = 0; r < p.n_rir; ++r) {
+        const uint32_t first = slots;
+        if (C > 1) {
+          bp.red.push_back(BatchReduce{(uint32_t)j, (uint32_t)r, (uint16_t)t, (uint16_t)C, first});
+          slots += (uint32_t)C;
+        }
+        for (int c = 0; c < C; ++c) {
+          BatchItem it{(uint32_t)j, (uint32_t)r, (uint16_t)t, (uint8_t)c, (uint8_t)C,
+                       C > 1 ? first + (uint32_t)c : 0xffffffffu};
+          cand.push_back(Cand{p.tile_taps[t] / C, cls, it});
+        }
+      }
+    }
+    tab_entries += (uint64_t)p.n_rir * p.ra.n_tab;
+    n_rir += (uint64_t)p.n_rir;
+    if (n_rir > 0x7fffffffULL || cand.size() > 0x7fffffffULL) return ISM_E_TOO_LARGE;
+  }
+  // Items grouped by window length, each group in decreasing estimated work.
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand &a, const Cand &b) {
+    if (a.cls != b.cls) return a.cls < b.cls;
+    return a.cost > b.cost;
+  });
+  bp.items.resize(cand.size());
+  for (size_t i = 0; i < cand.size(); ++i) {
+    bp.items[i] = cand[i].it;
+    bp.st.class_count[cand[i].cls]++;
+  }
+  uint32_t acc = 0;
+  for (int k = 0; k < n_classes; ++k) {
+    bp.st.class_first[k] = acc;
+    acc += bp.st.class_count[k];
+    bp.st.class_wt[k] = class_wt[k];
+  }
+  bp.st.n_classes = (uint32_t)n_classes;
+  bp.st.n_rir = (uint32_t)n_rir;
+  bp.st.n_red = (uint32_t)bp.red.size();
+  size_t o = 0;
+  bp.st.off_jobs = o;
+  o = align_up(o + sizeof(JobDev) * bp.jobs.size());
+  bp.st.off_rirs = o;
+  o = align_up(o + sizeof(BatchRir) * bp.rirs.size());
+  bp.st.off_items = o;
+  o = align_up(o + sizeof(BatchItem) * bp.items.size());
+  bp.st.off_red = o;
+  o = align_up(o + sizeof(BatchReduce) * bp.red.size());
+  bp.st.off_valid = o;
+  o = align_up(o + sizeof(int) * n_rir);
+  bp.st.off_origin = o;
+  o = align_up(o + sizeof(AxisOrigin) * n_rir);
+  bp.st.off_tab = o;
+  o = align_up(o + sizeof(AxisEntry) * tab_entries);
+  bp.st.off_part = o;
+  o = align_up(o + sizeof(float) * (size_t)slots * TILE);
+  bp.ws_bytes = o;
+  return ISM_OK;
+}
+
+}  // namespace
+
+int ism_batch_workspace_size(const ism_job *jobs, int n_jobs, int precision, size_t *bytes) {
+  if (!bytes) return ISM_E_INVALID_ARG;
+  BatchPlan bp;
+  const int st = plan_batch(jobs, n_jobs, precision, bp);
+  if (st != ISM_OK) return st;
+  *bytes = bp.ws_bytes;
+  return ISM_OK;
+}
+
+int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, size_t ws_bytes, void *stream,
+                      ism_batch *batch) {
+  if (!batch) return ISM_E_INVALID_ARG;
+  BatchPlan bp;
+  const int st = plan_batch(jobs, n_jobs, precision, bp);
+  if (st != ISM_OK) return st;
+  if (!ws || ws_bytes < bp.ws_bytes) return ISM_E_WORKSPACE;
+  // one contiguous host image of the metadata, copied with a single transfer
+  std::vector<char> host(bp.st.off_valid, 0);
+  std::memcpy(host.data() + bp.st.off_jobs, bp.jobs.data(), sizeof(JobDev) * bp.jobs.size());
+  std::memcpy(host.data() + bp.st.off_rirs, bp.rirs.data(), sizeof(BatchRir) * bp.rirs.size());
+  std::memcpy(host.data() + bp.st.off_items, bp.items.data(), sizeof(BatchItem) * bp.items.size());
+  if (!bp.red.empty()) std::memcpy(host.data() + bp.st.off_red, bp.red.data(), sizeof(BatchReduce) * bp.red.size());
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess) return ISM_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return ISM_E_DEVICE;
+  bp.st.ws = (uint64_t)(uintptr_t)ws;
+  std::memset(batch, 0, sizeof(*batch));
+  std::memcpy(batch, &bp.st, sizeof(bp.st));
+  return ISM_OK;
+}
+
+int ism_batch_run(const ism_batch *batch, void *stream) { return ism_batch_run_timed(batch, stream, nullptr, nullptr); }
+
+int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, void *ev_stop) {
+  if (!batch) return ISM_E_INVALID_ARG;
+  BatchState b;
+  std::memcpy(&b, batch, sizeof(b));
+  if (!b.ws || b.n_rir == 0 || b.n_classes == 0 || b.n_classes > (uint32_t)kMaxClasses) return ISM_E_INVALID_ARG;
+  char *w = (char *)(uintptr_t)b.ws;
+  const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (const BatchRir *)(w + b.off_rirs), b.n_rir,
+                              (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_wt,
+                              (int)b.n_classes, (const BatchReduce *)(w + b.off_red), b.n_red,
+                              (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
+                              (int *)(w + b.off_valid), (float *)(w + b.off_part), (hipStream_t)stream,
+                              (hipEvent_t)ev_start, (hipEvent_t)ev_stop);
+  return rc == 0 ? ISM_OK : ISM_E_DEVICE;
 }
 
 }  // extern "C"

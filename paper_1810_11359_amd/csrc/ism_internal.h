@@ -57,4 +57,37 @@ struct AxisOrigin {
   float e_even[3], e_odd[3];
 };
 
+// Batch mode: one entry per job (room) of a batch, uploaded once per prepared
+// batch. Pointers are device pointers owned by the caller.
+struct JobDev {
+  RoomArgs ra;
+  const float *src;
+  const float *rcv;
+  float *out;
+  uint64_t tab_base;  // first table entry of the job's first RIR
+  uint32_t rir_base;  // batch-wide index of the job's first RIR
+  uint32_t pad;
+};
+
+// Batch-wide RIR index -> (job, RIR within the job).
+struct BatchRir {
+  uint32_t job, rir;
+};
+
+// One work item of a batch (same meaning as in single-room mode). slot is the
+// partial tile written when the tile is split (chunks > 1), else 0xffffffff.
+struct BatchItem {
+  uint32_t job, rir;
+  uint16_t tile;
+  uint8_t chunk, chunks;
+  uint32_t slot;
+};
+
+// One split tile of a batch: its partials occupy slots first .. first+chunks-1.
+struct BatchReduce {
+  uint32_t job, rir;
+  uint16_t tile, chunks;
+  uint32_t first;
+};
+
 }  // namespace ism

@@ -33,6 +33,7 @@ EXPORTS = (
     "ism_status_string", "ism_abi_version", "ism_beta_from_t60", "ism_n_img_for_time",
     "ism_time_for_attenuation", "ism_n_samples", "ism_check_room", "ism_check_positions",
     "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed",
+    "ism_batch_workspace_size", "ism_batch_prepare", "ism_batch_run", "ism_batch_run_timed",
 )
 
 
@@ -46,6 +47,15 @@ class _Room(ctypes.Structure):
     _fields_ = [("room", ctypes.c_double * 3), ("beta", ctypes.c_double * 6), ("n_img", ctypes.c_int * 3),
                 ("c", ctypes.c_double), ("fs", ctypes.c_double), ("t_max", ctypes.c_double),
                 ("t_w", ctypes.c_double)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("room", _Room), ("src", ctypes.c_void_p), ("n_src", ctypes.c_int), ("rcv", ctypes.c_void_p),
+                ("n_rcv", ctypes.c_int), ("out", ctypes.c_void_p)]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("opaque", ctypes.c_uint64 * 40)]
 
 
 _lib = None
@@ -83,6 +93,15 @@ def lib() -> ctypes.CDLL:
         L.ism_workspace_size.argtypes = [rp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.ism_simulate.restype = ctypes.c_int
         L.ism_simulate.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t, fp]
+        jp = ctypes.POINTER(_Job)
+        L.ism_batch_workspace_size.restype = ctypes.c_int
+        L.ism_batch_workspace_size.argtypes = [jp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.ism_batch_prepare.restype = ctypes.c_int
+        L.ism_batch_prepare.argtypes = [jp, ctypes.c_int, ctypes.c_int, fp, ctypes.c_size_t, fp, ctypes.POINTER(_Batch)]
+        L.ism_batch_run.restype = ctypes.c_int
+        L.ism_batch_run.argtypes = [ctypes.POINTER(_Batch), fp]
+        L.ism_batch_run_timed.restype = ctypes.c_int
+        L.ism_batch_run_timed.argtypes = [ctypes.POINTER(_Batch), fp, fp, fp]
         L.ism_simulate_timed.restype = ctypes.c_int
         L.ism_simulate_timed.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
                                          fp, fp, fp]
@@ -231,3 +250,51 @@ def room_for(w) -> Room:
         beta = np.minimum(beta * np.asarray(w.beta_jitter), 0.999)
     n = n_img_for_time(w.room, w.c, w.t_max)
     return Room(list(map(float, w.room)), list(map(float, beta)), n, w.c, w.fs, w.t_max, w.t_w)
+
+
+class BatchSimulator:
+    """Many rooms in one prepared batch (``ism_batch_prepare`` once, ``ism_batch_run`` per call).
+
+    ``jobs`` is a list of (Room, src, rcv); outputs are ``self.outs[i]`` with
+    shape [n_src, n_rcv, nS] on ``device``.
+    """
+
+    def __init__(self, jobs, precision: str = "fp32", device: str = "cuda", check: bool = True, stream=None):
+        import torch
+
+        self.torch = torch
+        self.precision = PRECISIONS[precision]
+        self._keep = []
+        self.outs = []
+        arr = (_Job * len(jobs))()
+        for i, (room, src, rcv) in enumerate(jobs):
+            s, r = _host_pos(src), _host_pos(rcv)
+            if check:
+                check_positions(room, s, r)
+            ds, dr = torch.from_numpy(s).to(device), torch.from_numpy(r).to(device)
+            out = torch.empty((s.shape[0], r.shape[0], room.n_samples), dtype=torch.float32, device=device)
+            self._keep += [ds, dr]
+            self.outs.append(out)
+            arr[i].room = room._c()
+            arr[i].src, arr[i].n_src = ds.data_ptr(), s.shape[0]
+            arr[i].rcv, arr[i].n_rcv = dr.data_ptr(), r.shape[0]
+            arr[i].out = out.data_ptr()
+        self.n_rirs = sum(int(o.shape[0] * o.shape[1]) for o in self.outs)
+        nbytes = ctypes.c_size_t()
+        _check(lib().ism_batch_workspace_size(arr, len(jobs), self.precision, ctypes.byref(nbytes)),
+               "ism_batch_workspace_size")
+        self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=device)
+        self.ws_bytes = nbytes.value
+        self.batch = _Batch()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().ism_batch_prepare(arr, len(jobs), self.precision, self.ws.data_ptr(), self.ws_bytes,
+                                       st.cuda_stream, ctypes.byref(self.batch)), "ism_batch_prepare")
+
+    def run(self, stream=None, ev_start=None, ev_stop=None):
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        if ev_start is None and ev_stop is None:
+            _check(lib().ism_batch_run(ctypes.byref(self.batch), st.cuda_stream), "ism_batch_run")
+        else:
+            _check(lib().ism_batch_run_timed(ctypes.byref(self.batch), st.cuda_stream, ev_start, ev_stop),
+                   "ism_batch_run_timed")
+        return self.outs

@@ -137,3 +137,25 @@ def test_simulate_rejects_bad_arguments_before_launch():
     assert L.ism_simulate(ctypes.byref(rc), fake, 1, fake, 1, 0, fake, fake, need - 1, None) == ism.ISM_E_WORKSPACE
     assert L.ism_simulate(ctypes.byref(rc), fake, 0, fake, 1, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
     assert L.ism_simulate(ctypes.byref(rc), fake, 1, fake, 1, 7, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
+
+
+def test_batch_checks_before_any_launch():
+    r = _room()
+    fake = 0x1000
+    jobs = (ism._Job * 2)()
+    for j in jobs:
+        j.room = r._c()
+        j.src, j.n_src, j.rcv, j.n_rcv, j.out = fake, 1, fake, 2, fake
+    L = ism.lib()
+    n = ctypes.c_size_t()
+    assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_OK and n.value > 0
+    assert L.ism_batch_workspace_size(jobs, 0, 0, ctypes.byref(n)) == ism.ISM_E_INVALID_ARG
+    jobs[1].n_rcv = 0
+    assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_E_INVALID_ARG
+    jobs[1].n_rcv = 2
+    jobs[1].out = None
+    assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_E_INVALID_ARG
+    jobs[1].out = fake
+    b = ism._Batch()
+    assert L.ism_batch_prepare(jobs, 2, 0, None, 0, None, ctypes.byref(b)) == ism.ISM_E_WORKSPACE
+    assert L.ism_batch_run(ctypes.byref(ism._Batch()), None) == ism.ISM_E_INVALID_ARG

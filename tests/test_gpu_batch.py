@@ -1,0 +1,136 @@
+"""Batches of rooms through ism_batch_prepare / ism_batch_run (GPU).
+
+A batch must give, job by job, bitwise the same RIRs as ism_simulate of that
+job alone, match the FP64 oracle within 1e-5 of the peak, and replay
+identically from a captured HIP graph.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_11359_amd import ism, workloads
+
+from .helpers import oracle_room_args, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ism.lib()
+    return torch
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_jobs():
+    rng = np.random.default_rng(7)
+    jobs = []
+    specs = [((3.0, 4.0, 2.5), 0.25, 16000.0, 0.004, 1, 3), ((4.4, 3.1, 2.7), 0.08, 48000.0, 0.002, 2, 2),
+             ((6.0, 5.0, 3.0), 0.3, 8000.0, 0.004, 1, 1), ((2.5, 2.5, 2.5), 0.12, 16000.0, 0.004, 1, 5),
+             ((8.0, 7.0, 3.5), 0.4, 16000.0, 0.004, 1, 2)]
+    for L, t60, fs, tw, ns, nr in specs:
+        beta = ism.beta_from_t60(L, t60) * rng.uniform(0.92, 1.0, 6)
+        room = ism.Room(list(L), list(beta), ism.n_img_for_time(L, 343.0, t60), 343.0, fs, t60, tw)
+        src = rng.uniform(0.5, np.array(L) - 0.5, (ns, 3)).astype(np.float32)
+        rcv = rng.uniform(0.5, np.array(L) - 0.5, (nr, 3)).astype(np.float32)
+        jobs.append((room, src, rcv))
+    return jobs
+
+
+def test_batch_equals_single_room_calls(oracle_mod):
+    import torch
+
+    jobs = _mixed_jobs()
+    _say("mixed batch")
+    b = ism.BatchSimulator(jobs)
+    outs = [o.clone() for o in b.run()]
+    torch.cuda.synchronize()
+    for (room, src, rcv), o in zip(jobs, outs):
+        single = ism.simulate(room, src, rcv)
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), f"batch differs from single-room call for {room.room}"
+    # oracle on two of the jobs
+    for k in (0, 1):
+        room, src, rcv = jobs[k]
+        ref = oracle_mod.rir(room.room, room.beta, room.n_img, room.c, room.fs, room.t_max, room.t_w, src, rcv)
+        err = rel_err(outs[k].cpu().numpy(), ref)
+        print("job", k, "rel err", err)
+        assert np.all(err <= TOL_FP32)
+
+
+def _feasible(oracle_mod):
+    def ok(room, t60):
+        try:
+            oracle_mod.beta_from_t60(room, t60)
+            return True
+        except ValueError:
+            return False
+
+    return ok
+
+
+def test_batch_1024_rooms_sampled(oracle_mod):
+    import torch
+
+    ws = workloads.batch_rooms(1024, seed=0, feasible=_feasible(oracle_mod))
+    jobs = [(ism.room_for(w), w.src, w.rcv) for w in ws]
+    _say(f"1024-room batch, {sum(w.src.shape[0] * w.rcv.shape[0] for w in ws)} RIRs")
+    b = ism.BatchSimulator(jobs)
+    outs = b.run()
+    torch.cuda.synchronize()
+    # rooms with the fewest and the most image taps per RIR (volume vs T60^3) + random ones
+    dens = np.array([w.t60 ** 3 / np.prod(w.room) for w in ws])
+    pick = [int(np.argmin(dens)), int(np.argmax(dens))] + list(np.random.default_rng(1).choice(len(ws), 3, replace=False))
+    for k in pick:
+        w = ws[k]
+        args = oracle_room_args(oracle_mod, w)
+        got = outs[k].cpu().numpy()
+        assert np.all(np.isfinite(got))
+        nS = got.shape[-1]
+        if nS * w.t60 ** 3 / np.prod(w.room) < 40.0:
+            ref = oracle_mod.rir(*args, w.src, w.rcv)
+            err = rel_err(got, ref)
+        else:  # long, dense RIR: early window (holds the peak) and the last window
+            peak = np.max(np.abs(got), axis=-1)
+            err = np.zeros(peak.shape)
+            for k0, k1 in [(0, 1200), (nS - 1200, nS)]:
+                ref = oracle_mod.rir(*args, w.src, w.rcv, k_begin=k0, k_end=k1)
+                err = np.maximum(err, np.max(np.abs(got[..., k0:k1] - ref), axis=-1) / peak)
+        print("room", k, w.room.round(2), "t60", round(w.t60, 3), "rel err", err.ravel())
+        assert np.all(err <= TOL_FP32)
+
+
+def test_batch_graph_replay():
+    import torch
+
+    jobs = _mixed_jobs()
+    _say("graph replay")
+    b = ism.BatchSimulator(jobs)
+    eager = [o.clone() for o in b.run()]
+    torch.cuda.synchronize()
+    for o in b.outs:
+        o.zero_()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for o in b.outs:
+            o.fill_(float(rep + 1))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for e, o in zip(eager, b.outs):
+            assert torch.equal(e, o), f"replay {rep} differs from the eager run"
