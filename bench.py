@@ -88,6 +88,42 @@ def cpu_baseline(ws, n_rcv_sample: int):
             "rirs_per_s": n / dt}
 
 
+def serve(args) -> int:
+    """Continuous-batching serving of a Poisson stream; prints RIRs/s with p50/p99 latency."""
+    import torch
+
+    from paper_1810_11359_amd import ism, workloads
+    from paper_1810_11359_amd.serving import GpuExecutor, Job, Scheduler, replay
+
+    def feasible(room, t60):
+        try:
+            ism.beta_from_t60(room, t60)
+            return True
+        except ism.IsmError:
+            return False
+
+    reqs = workloads.serving_stream(rate=args.rate, n_jobs=args.jobs, seed=0, feasible=feasible)
+    jobs = [Job(i, ism.room_for(r.workload), r.workload.src, r.workload.rcv, r.arrival) for i, r in enumerate(reqs)]
+    taps = sum(ism.count_taps(j.room, j.src, j.rcv) for j in jobs)
+    # warm-up: compile/load every kernel variant once
+    warm = [Job(-1, j.room, j.src[:1], j.rcv[:1], 0.0) for j in jobs[:8]]
+    replay(Scheduler(GpuExecutor(2), budget_bytes=8 << 30, n_slots=2), warm)
+    torch.cuda.synchronize()
+    n_slots = 4
+    sch = Scheduler(GpuExecutor(n_slots), budget_bytes=64 << 30, n_slots=n_slots, max_batch_jobs=256)
+    st = replay(sch, jobs)
+    torch.cuda.synchronize()
+    out = {"metric": METRIC, "value": st.rirs_per_s, "unit": "RIRs/s", "n_gpus": 1, "steps": len(jobs),
+           "warmup": len(warm), "ms_per_step": st.makespan_s * 1e3 / len(jobs), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"serving_poisson_{args.rate:g}_jobs_per_s", "n_jobs": len(jobs),
+                      "n_rirs": st.n_rirs, "taps": int(taps), "slots": n_slots, "budget_bytes": 64 << 30,
+                      "parallelism": "single GPU"},
+           "serving": st.as_dict(), "taps_per_s": taps / st.makespan_s}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +133,9 @@ def main() -> int:
                     choices=["room_32_receivers", "single_rir", "large_room_uca", "batch_rooms"])
     ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving mode: replay a Poisson stream of mixed RIR jobs at this many jobs/s")
+    ap.add_argument("--jobs", type=int, default=2000, help="serving mode: jobs in the stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the ISM path here does not "
@@ -107,6 +146,8 @@ def main() -> int:
 
     from paper_1810_11359_amd import ism, workloads
 
+    if args.rate > 0:
+        return serve(args)
     if args.workload == "batch_rooms":
         def feasible(room, t60):
             try:

@@ -95,3 +95,42 @@ WORKLOADS = {
     "room_32_receivers": room_32_receivers,
     "large_room_uca": large_room_uca,
 }
+
+
+@dataclass
+class ServingRequest:
+    arrival: float            # seconds from the start of the stream
+    workload: Workload
+
+
+def serving_stream(rate: float, n_jobs: int, seed: int = 0,
+                   feasible: Optional[Callable[[np.ndarray, float], bool]] = None) -> List[ServingRequest]:
+    """Poisson arrivals at ``rate`` jobs/s. Each job: a room with sides U(3, 10) m,
+    T60 U(0.1, 1.5) s (redrawn while ``feasible`` is False), T_max = T60,
+    fs 16 kHz (T_w 4 ms) or 48 kHz (T_w 2 ms) with equal probability. 80% of
+    jobs are one source with U{1..64} receivers; 20% are a moving source: 100
+    positions evenly spaced on a segment between two seeded interior points,
+    one receiver."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_jobs):
+        t += float(rng.exponential(1.0 / rate))
+        room = rng.uniform(3.0, 10.0, 3)
+        t60 = float(rng.uniform(0.1, 1.5))
+        while feasible is not None and not feasible(room, t60):
+            t60 = float(rng.uniform(0.1, 1.5))
+        fs, t_w = (16000.0, 0.004) if rng.random() < 0.5 else (48000.0, 0.002)
+        if rng.random() < 0.8:
+            src = _uniform_positions(rng, room, 1)
+            rcv = _uniform_positions(rng, room, int(rng.integers(1, 65)))
+            kind = "static"
+        else:
+            a, b = _uniform_positions(rng, room, 2)
+            s = np.linspace(0.0, 1.0, 100)[:, None]
+            src = (a[None, :] * (1.0 - s) + b[None, :] * s).astype(np.float32)
+            rcv = _uniform_positions(rng, room, 1)
+            kind = "trajectory"
+        w = Workload(f"serving_{kind}_{i}", room, t60, src, rcv, fs=fs, t_max=t60, t_w=t_w)
+        out.append(ServingRequest(t, w))
+    return out
