@@ -133,6 +133,8 @@ def main() -> int:
                     choices=["room_32_receivers", "single_rir", "large_room_uca", "batch_rooms"])
     ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"],
+                    help="tap arithmetic (accumulation is FP32 in both)")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving mode: replay a Poisson stream of mixed RIR jobs at this many jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving mode: jobs in the stream")
@@ -158,7 +160,7 @@ def main() -> int:
 
         ws = workloads.batch_rooms(1024, seed=0, feasible=feasible)
         rooms = [ism.room_for(w) for w in ws]
-        sim = ism.BatchSimulator([(r, w.src, w.rcv) for r, w in zip(rooms, ws)])
+        sim = ism.BatchSimulator([(r, w.src, w.rcv) for r, w in zip(rooms, ws)], precision=args.precision)
         n_rir = sim.n_rirs
         taps = sum(ism.count_taps(r, w.src, w.rcv) for r, w in zip(rooms, ws))
         config = {"workload": f"batch_1024_rooms_{n_rir}_rirs", "n_rooms": len(ws), "n_rirs": n_rir, "fs": 16000.0,
@@ -168,7 +170,7 @@ def main() -> int:
         w = workloads.WORKLOADS[args.workload](0)
         ws = [w]
         room = ism.room_for(w)
-        sim = ism.Simulator(room, w.src, w.rcv)
+        sim = ism.Simulator(room, w.src, w.rcv, precision=args.precision)
         n_rir = sim.n_src * sim.n_rcv
         taps = ism.count_taps(room, w.src, w.rcv)
         config = {"workload": w.name, "room_m": list(map(float, w.room)), "t60_s": w.t60, "fs": w.fs,
@@ -210,7 +212,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": config,
         "rirs_per_s": n_rir / (ms_step / 1e3),

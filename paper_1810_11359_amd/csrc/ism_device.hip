@@ -119,6 +119,56 @@ constexpr TapConsts<WT> make_tap_consts() {
   return t;
 }
 
+// FP16 taps. Away from the centre (j <= -2 or j >= 3) the tap of an image is
+// C g_j(t) with t = f - 1/2 in [-1/2, 1/2) and
+//   g_j = (1 + cos(2 pi (j - f) / W)) sigma_j / (2 (j - f)),
+// which is analytic on the interval (its nearest pole is 2.5 away in t). Each
+// g_j is replaced by its cubic interpolant at the four Chebyshev nodes of
+// [-1/2, 1/2] (interpolation error < 2e-4 of max|g_j|), evaluated in packed
+// FP16 two taps at a time. The four central taps keep the exact FP32 form.
+constexpr bool poly_tap(int j) { return j <= -2 || j >= 3; }
+
+template <int WT>
+struct PolyConsts {
+  float c[4][WT];  // monomial coefficients in t, rounded to FP16 where used
+};
+constexpr double g_tap(int j, double t, int wt) {
+  const double v = j - (t + 0.5);
+  const double sg = (j % 2 == 0) ? -1.0 : 1.0;
+  return (1.0 + cx_cos(2.0 * kPi * v / wt)) * sg / (2.0 * v);
+}
+template <int WT>
+constexpr PolyConsts<WT> make_poly_consts() {
+  PolyConsts<WT> P{};
+  for (int jj = 0; jj < WT; ++jj) {
+    const int j = jj + 1 - WT / 2;
+    if (!poly_tap(j)) continue;
+    double x[4] = {}, y[4] = {};
+    for (int k = 0; k < 4; ++k) {
+      x[k] = 0.5 * cx_cos((2.0 * k + 1.0) * kPi / 8.0);
+      y[k] = g_tap(j, x[k], WT);
+    }
+    // Newton divided differences, then expansion to monomials
+    double d[4] = {y[0], y[1], y[2], y[3]};
+    for (int lvl = 1; lvl < 4; ++lvl)
+      for (int k = 3; k >= lvl; --k) d[k] = (d[k] - d[k - 1]) / (x[k] - x[k - lvl]);
+    double m[4] = {d[3], 0.0, 0.0, 0.0};  // coefficients of the running polynomial, highest first
+    int deg = 0;
+    for (int k = 2; k >= 0; --k) {  // m(t) = m(t) * (t - x[k]) + d[k]
+      double nm[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q <= deg; ++q) {
+        nm[q] += m[q];
+        nm[q + 1] -= m[q] * x[k];
+      }
+      ++deg;
+      nm[deg] += d[k];
+      for (int q = 0; q < 4; ++q) m[q] = nm[q];
+    }
+    for (int q = 0; q < 4; ++q) P.c[3 - q][jj] = (float)m[q];  // c[k] multiplies t^k
+  }
+  return P;
+}
+
 // sin(pi h) / pi for h in [0, 1/2]: Taylor series of sin to the h^13 term
 // (truncation < 2e-10 at h = 1/2), Horner in h^2.
 __device__ __forceinline__ float sinpi_over_pi(float h) {
@@ -306,7 +356,9 @@ constexpr int QCAP = 256;  // per-wave queue of candidate images
 // Work of one item: the taps of the images of the shell slab (chunk c of C) of
 // output tile tile_id of one RIR, written to dst (the RIR's samples of the
 // tile, or a partial tile when C > 1).
-template <int WT, int NW>
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+template <int WT, int NW, bool HALF>
 __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                 const AxisEntry *__restrict__ tab, const AxisOrigin &org,
                                                 const bool valid, float *__restrict__ dst) {
@@ -369,17 +421,62 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     if (has) vc[base] = (uint8_t)lane;
     wave_sync();
     const bool win = has && vc[base] == (uint8_t)lane;
-    if (win) {
+    // Each tap: issue the LDS read, compute the tap while it is in flight, add,
+    // write back. The scheduling barrier keeps taps in this order (bounded
+    // register use, hence more waves to hide the LDS round trip).
+    if (win && !HALF) {
       float *t = wt + base;
 #pragma unroll
       for (int jj = 0; jj < WT; ++jj) {
+        const float o = t[jj];
+        // ties this tap's arithmetic to its place in the chain (no instruction)
+        __asm__ volatile("" : "+v"(f), "+v"(CP), "+v"(CQ), "+v"(C2) :: "memory");
         const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
         const float r = __builtin_amdgcn_rcpf(u);
         float w = __builtin_fmaf(K.cth[jj], CP, C2);
         w = __builtin_fmaf(K.sth[jj], CQ, w);
-        const float o = t[jj];
         t[jj] = __builtin_fmaf(w, r, o);
         __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (win && HALF) {
+      constexpr PolyConsts<WT> P = make_poly_consts<WT>();
+      float *t = wt + base;
+      const _Float16 th = (_Float16)(f - 0.5f);
+      half2_t tt = {th, th};
+      const float Cc = 2.0f * C2;
+#pragma unroll
+      for (int jj = 0; jj < WT; ++jj) {
+        const int j = jj + 1 - WT / 2;
+        if (!poly_tap(j)) {
+          const float o = t[jj];
+          __asm__ volatile("" : "+v"(f), "+v"(CP), "+v"(CQ), "+v"(C2) :: "memory");
+          const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
+          const float r = __builtin_amdgcn_rcpf(u);
+          float w = __builtin_fmaf(K.cth[jj], CP, C2);
+          w = __builtin_fmaf(K.sth[jj], CQ, w);
+          t[jj] = __builtin_fmaf(w, r, o);
+          __asm__ volatile("" ::: "memory");
+          __builtin_amdgcn_sched_barrier(0);
+        } else if (jj + 1 < WT && poly_tap(j + 1) && ((j <= -2) ? (j - JLO) % 2 == 0 : (j - 3) % 2 == 0)) {
+          // taps jj and jj + 1 in one packed register
+          const half2_t c3 = {(_Float16)P.c[3][jj], (_Float16)P.c[3][jj + 1]};
+          const half2_t c2 = {(_Float16)P.c[2][jj], (_Float16)P.c[2][jj + 1]};
+          const half2_t c1 = {(_Float16)P.c[1][jj], (_Float16)P.c[1][jj + 1]};
+          const half2_t c0 = {(_Float16)P.c[0][jj], (_Float16)P.c[0][jj + 1]};
+          const float o0 = t[jj];
+          __asm__ volatile("" : "+v"(tt) :: "memory");
+          half2_t pv = __builtin_elementwise_fma(c3, tt, c2);
+          pv = __builtin_elementwise_fma(pv, tt, c1);
+          pv = __builtin_elementwise_fma(pv, tt, c0);
+          t[jj] = __builtin_fmaf((float)pv.x, Cc, o0);
+          __asm__ volatile("" ::: "memory");
+          const float o1 = t[jj + 1];
+          t[jj + 1] = __builtin_fmaf((float)pv.y, Cc, o1);
+          __asm__ volatile("" ::: "memory");
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
     has = has && !win;
@@ -527,7 +624,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
 }
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
-template <int WT, int NW>
+template <int WT, int NW, bool HALF>
 __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
@@ -551,11 +648,11 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
   const int c = (int)(rel % (uint32_t)C);
   float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
   const AxisOrigin org = origin[rir];
-  accumulate_item<WT, NW>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst);
+  accumulate_item<WT, NW, HALF>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst);
 }
 
 // Batch launch: every item names its job; the job table carries the room.
-template <int WT, int NW>
+template <int WT, int NW, bool HALF>
 __global__ __launch_bounds__(NW * 64) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
@@ -569,7 +666,7 @@ __global__ __launch_bounds__(NW * 64) void accumulate_batch_kernel(const JobDev 
   float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
                                         : part + (size_t)it.slot * TILE;
   const AxisOrigin org = origin[grir];
-  accumulate_item<WT, NW>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org,
+  accumulate_item<WT, NW, HALF>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org,
                           valid[grir] != 0, dst);
 }
 
@@ -623,41 +720,47 @@ int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEn
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int WT>
+template <int WT, bool HALF>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                         const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st) {
   constexpr int NW = 4;
-  hipLaunchKernelGGL((accumulate_kernel<WT, NW>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, origin, valid,
-                     out, part);
+  hipLaunchKernelGGL((accumulate_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, origin,
+                     valid, out, part);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt == 128; }
 
-int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
-                      const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st) {
+int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
+                      const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
+                      hipStream_t st) {
+#define ISM_ACC(W)                                                                             \
+  case W:                                                                                      \
+    return half ? launch_acc_w<W, true>(ra, pa, n_items, tab, origin, valid, out, part, st)    \
+                : launch_acc_w<W, false>(ra, pa, n_items, tab, origin, valid, out, part, st);
   switch (wt) {
-    case 32: return launch_acc_w<32>(ra, pa, n_items, tab, origin, valid, out, part, st);
-    case 64: return launch_acc_w<64>(ra, pa, n_items, tab, origin, valid, out, part, st);
-    case 96: return launch_acc_w<96>(ra, pa, n_items, tab, origin, valid, out, part, st);
-    case 128: return launch_acc_w<128>(ra, pa, n_items, tab, origin, valid, out, part, st);
+    ISM_ACC(32)
+    ISM_ACC(64)
+    ISM_ACC(96)
+    ISM_ACC(128)
     default: return -2;
   }
+#undef ISM_ACC
 }
 
-template <int WT>
+template <int WT, bool HALF>
 static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
                               const AxisOrigin *origin, const int *valid, float *part, hipStream_t st) {
   constexpr int NW = 4;
-  hipLaunchKernelGGL((accumulate_batch_kernel<WT, NW>), dim3(n_items), dim3(NW * 64), 0, st, jobs, items, tab, origin,
-                     valid, part);
+  hipLaunchKernelGGL((accumulate_batch_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, jobs, items, tab,
+                     origin, valid, part);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
-                 hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                 bool half, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid,
+                 float *part, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
   if (hipGetLastError() != hipSuccess) return -1;
   if (ev_start && hipEventRecord(ev_start, st) != hipSuccess) return -1;
@@ -665,13 +768,19 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
     if (class_count[k] == 0) continue;
     const BatchItem *it = items + class_first[k];
     int rc = -2;
+#define ISM_BACC(W)                                                                                     \
+  case W:                                                                                               \
+    rc = half ? launch_acc_batch_w<W, true>(jobs, it, class_count[k], tab, origin, valid, part, st)     \
+              : launch_acc_batch_w<W, false>(jobs, it, class_count[k], tab, origin, valid, part, st);   \
+    break;
     switch (class_wt[k]) {
-      case 32: rc = launch_acc_batch_w<32>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
-      case 64: rc = launch_acc_batch_w<64>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
-      case 96: rc = launch_acc_batch_w<96>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
-      case 128: rc = launch_acc_batch_w<128>(jobs, it, class_count[k], tab, origin, valid, part, st); break;
+      ISM_BACC(32)
+      ISM_BACC(64)
+      ISM_BACC(96)
+      ISM_BACC(128)
       default: break;
     }
+#undef ISM_BACC
     if (rc != 0) return -1;
   }
   if (ev_stop && hipEventRecord(ev_stop, st) != hipSuccess) return -1;

@@ -16,15 +16,16 @@
 namespace ism {
 int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
                   int *valid, int n_rir, hipStream_t st);
-int launch_accumulate(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
-                      const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st);
+int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
+                      const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
+                      hipStream_t st);
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
                   hipStream_t st);
 bool supported_window(int wt);
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
-                 hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
+                 bool half, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid,
+                 float *part, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 }  // namespace ism
 
 using namespace ism;
@@ -61,6 +62,7 @@ struct Plan {
   PlanArgs pa;
   double tile_taps[MAX_TILES];  // estimated taps of each tile's image shell
   int wt;
+  bool half;
   int n_rir;
   uint32_t n_items;
   bool any_split;
@@ -72,7 +74,9 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   if (st != ISM_OK) return st;
   if (n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
   if ((int64_t)n_src * n_rcv > ISM_MAX_PAIRS) return ISM_E_TOO_LARGE;
-  if (precision != ISM_FP32) return precision == ISM_FP16 || precision == ISM_BF16 ? ISM_E_UNSUPPORTED : ISM_E_INVALID_ARG;
+  if (precision != ISM_FP32 && precision != ISM_FP16)
+    return precision == ISM_BF16 ? ISM_E_UNSUPPORTED : ISM_E_INVALID_ARG;
+  p.half = precision == ISM_FP16;
   p.wt = even_window(*r);
   if (p.wt == 0 || !supported_window(p.wt)) return ISM_E_UNSUPPORTED;
   const int64_t nS = ism_n_samples(r->t_max, r->fs);
@@ -316,7 +320,8 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
   float *part = p.any_split ? (float *)(w + p.off_part) : nullptr;
   if (launch_tables(p.ra, src, rcv, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, s) != hipSuccess) return ISM_E_DEVICE;
-  if (launch_accumulate(p.wt, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, s) != 0) return ISM_E_DEVICE;
+  if (launch_accumulate(p.wt, p.half, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, s) != 0)
+    return ISM_E_DEVICE;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
   if (p.any_split && launch_reduce(p.ra, p.pa, p.n_rir, part, out, s) != 0) return ISM_E_DEVICE;
   return ISM_OK;
@@ -331,7 +336,7 @@ constexpr int kMaxClasses = 4;
 struct BatchState {  // stored in ism_batch::opaque
   uint64_t ws;
   uint64_t off_jobs, off_rirs, off_items, off_red, off_valid, off_origin, off_tab, off_part;
-  uint32_t n_rir, n_red, n_classes, pad;
+  uint32_t n_rir, n_red, n_classes, half;
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
   int32_t class_wt[kMaxClasses];
 };
@@ -419,6 +424,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
     bp.st.class_wt[k] = class_wt[k];
   }
   bp.st.n_classes = (uint32_t)n_classes;
+  bp.st.half = precision == ISM_FP16 ? 1u : 0u;
   bp.st.n_rir = (uint32_t)n_rir;
   bp.st.n_red = (uint32_t)bp.red.size();
   size_t o = 0;
@@ -485,7 +491,7 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
   char *w = (char *)(uintptr_t)b.ws;
   const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (const BatchRir *)(w + b.off_rirs), b.n_rir,
                               (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_wt,
-                              (int)b.n_classes, (const BatchReduce *)(w + b.off_red), b.n_red,
+                              (int)b.n_classes, b.half != 0, (const BatchReduce *)(w + b.off_red), b.n_red,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
                               (int *)(w + b.off_valid), (float *)(w + b.off_part), (hipStream_t)stream,
                               (hipEvent_t)ev_start, (hipEvent_t)ev_stop);

@@ -108,8 +108,9 @@ def test_unsupported_requests():
         ism.workspace_size(_room(t_w=0.0041), 1, 1)  # W = 65.6 samples
     assert e.value.status == ism.ISM_E_UNSUPPORTED
     with pytest.raises(ism.IsmError) as e:
-        ism.workspace_size(_room(), 1, 1, precision="fp16")
+        ism.workspace_size(_room(), 1, 1, precision="bf16")
     assert e.value.status == ism.ISM_E_UNSUPPORTED
+    assert ism.workspace_size(_room(), 1, 1, precision="fp16") > 0
 
 
 def test_position_checks():

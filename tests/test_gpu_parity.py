@@ -18,6 +18,7 @@ from .helpers import oracle_room_args, rel_err
 pytestmark = pytest.mark.gpu
 
 TOL_FP32 = 1e-5
+TOL_FP16 = 2e-3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -34,10 +35,10 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _gpu_rir(room, src, rcv):
+def _gpu_rir(room, src, rcv, precision="fp32"):
     import torch
 
-    out = ism.simulate(room, src, rcv)
+    out = ism.simulate(room, src, rcv, precision=precision)
     torch.cuda.synchronize()
     return out.cpu().numpy().astype(np.float64)
 
@@ -152,7 +153,49 @@ def test_repeatable_and_split_invariant(monkeypatch):
     a = _gpu_rir(room, w.src, w.rcv[:8])
     b = _gpu_rir(room, w.src, w.rcv[:8])
     peak = np.max(np.abs(a), axis=-1)
-    assert np.all(np.max(np.abs(a - b), axis=-1) <= 1e-7 * peak)
+    assert np.array_equal(a, b)  # fixed summation order: bitwise reproducible
     monkeypatch.setenv("ISM_TARGET_TAPS", "20000")  # many more work items per tile
     c = _gpu_rir(room, w.src, w.rcv[:8])
     assert np.all(np.max(np.abs(a - c), axis=-1) <= 2e-7 * peak)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_small_rooms_fp16_taps(oracle_mod, case):
+    name, L, beta, n, fs, t_max, t_w, src, rcv = case
+    room = ism.Room(L, beta, n, 343.0, fs, t_max, t_w)
+    _say(f"fp16 {name}")
+    got = _gpu_rir(room, src, rcv, "fp16")
+    ref = _oracle_rir(oracle_mod, room, src, rcv)
+    err = rel_err(got, ref)
+    print(name, "fp16 rel err", err)
+    assert np.all(err <= TOL_FP16)
+
+
+def test_fp16_workloads_sampled(oracle_mod):
+    w = workloads.room_32_receivers(0)
+    room = ism.room_for(w)
+    _say("fp16 room_32_receivers")
+    got = _gpu_rir(room, w.src, w.rcv, "fp16")
+    pick = [0, 19]
+    ref = oracle_mod.rir(*oracle_room_args(oracle_mod, w), w.src, w.rcv[pick])
+    err = rel_err(got[:, pick], ref)
+    print("fp16 32rcv rel err", err)
+    assert np.all(err <= TOL_FP16)
+    w = workloads.large_room_uca(0)
+    room = ism.room_for(w)
+    _say("fp16 large_room_uca")
+    got = _gpu_rir(room, w.src, w.rcv, "fp16")
+    args = oracle_room_args(oracle_mod, w)
+    peak = np.max(np.abs(got[0, :1]), axis=-1)
+    for k0, k1 in [(0, 1500), (94800, 96000)]:
+        ref = oracle_mod.rir(*args, w.src, w.rcv[:1], k_begin=k0, k_end=k1)
+        err = np.max(np.abs(got[0, :1, k0:k1] - ref[0]), axis=-1) / peak
+        print("fp16 uca window", k0, k1, "rel err", err)
+        assert np.all(err <= TOL_FP16)
+
+
+def test_bf16_is_reported_unsupported():
+    room = ism.Room([4.0, 5.0, 3.0], [0.9] * 6, (10, 10, 10), 343.0, 16000.0, 0.05, 0.004)
+    with pytest.raises(ism.IsmError) as e:
+        ism.simulate(room, [[1.0, 1.0, 1.0]], [[2.0, 2.0, 2.0]], precision="bf16")
+    assert e.value.status == ism.ISM_E_UNSUPPORTED
