@@ -35,7 +35,7 @@ def _say(msg):
 def _mixed_jobs():
     rng = np.random.default_rng(7)
     jobs = []
-    specs = [((3.0, 4.0, 2.5), 0.25, 16000.0, 0.004, 1, 3), ((4.4, 3.1, 2.7), 0.08, 48000.0, 0.002, 2, 2),
+    specs = [((3.0, 4.0, 2.5), 0.25, 16000.0, 0.004, 1, 3), ((4.4, 3.1, 2.7), 0.15, 48000.0, 0.002, 2, 2),
              ((6.0, 5.0, 3.0), 0.3, 8000.0, 0.004, 1, 1), ((2.5, 2.5, 2.5), 0.12, 16000.0, 0.004, 1, 5),
              ((8.0, 7.0, 3.5), 0.4, 16000.0, 0.004, 1, 2)]
     for L, t60, fs, tw, ns, nr in specs:
