@@ -343,155 +343,82 @@ __device__ __forceinline__ int first_ge(const AxisRange &a, float b) {
 // ---------------------------------------------------------------------------
 // Kernel 2: enumeration of the image shell of one tile + windowed-sinc taps.
 //
-// Each wave accumulates into its own FP32 tile in LDS with plain
-// read-add-write, one tap at a time: within one instruction the active lanes
-// hold images with distinct first-tap positions (enforced by a byte claim per
-// position), and a compiler barrier between taps keeps every lane's
-// read-modify-write of tap j ahead of any lane's access for tap j + 1, so
-// overlapping windows of different lanes never race. At the end the wave tiles
-// are summed in a fixed order, which makes results bitwise reproducible.
+// Work item = (RIR, output tile, slab of the image shell along x). The wave
+// walks the columns (nx, ny) that cross the shell, queues their z candidates
+// and hands the queue to a consumer that turns candidates into image
+// parameters (delay, amplitude; lanes = images) and adds their taps.
+//
+// FP32 consumer (lanes = taps): the candidates' parameters are staged in LDS;
+// each half-wave then takes one staged image per step and its 32 lanes add
+// W/32 taps each into the half-wave's own FP32 tile. All addresses of one
+// step are distinct and consecutive, so there are no bank conflicts and no
+// lost updates; steps of a half-wave reach LDS in program order.
+//
+// FP16 consumer (lanes = images): each lane adds all taps of its image, one
+// tap per instruction, into the wave's tile; a byte claim per position keeps
+// the active lanes of one instruction on distinct positions.
+//
+// Both end with a fixed-order sum of the tiles, so results are bitwise
+// reproducible.
 // ---------------------------------------------------------------------------
 constexpr int QCAP = 256;  // per-wave queue of candidate images
 
-// Work of one item: the taps of the images of the shell slab (chunk c of C) of
-// output tile tile_id of one RIR, written to dst (the RIR's samples of the
-// tile, or a partial tile when C > 1).
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+// Per-wave LDS of the shell enumeration.
+struct EnumLds {
+  uint32_t queue[QCAP];  // (column lane << 16) | table index of nz
+  float col_sh[64], col_sl[64], col_g[64];
+  int nx_pref[64], nx_nylo[64];
+};
 
-template <int WT, int NW, bool HALF>
-__device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
-                                                const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                const bool valid, float *__restrict__ dst) {
-  constexpr int JLO = 1 - WT / 2;
-  constexpr int JHI = WT / 2;
-  constexpr int MARGIN = WT;
-  constexpr int SPAN = TILE + 2 * MARGIN;
-  constexpr TapConsts<WT> K = make_tap_consts<WT>();
+// Wave-uniform geometry of one work item.
+struct ItemGeom {
+  int T0, T1;                    // output samples of the tile
+  float R0, R1;                  // shell radii in samples, widened by W/2 + 2
+  float r1h, r1l, r0h, r0l;      // their squares (float-float)
+  int nx_a, nx_b;                // x table indices of the slab
+};
 
-  __shared__ float tile[NW][SPAN];
-  __shared__ uint8_t claim[NW][SPAN];
-  __shared__ uint32_t queue[NW][QCAP];
-  __shared__ float col_sh[NW][64], col_sl[NW][64], col_g[NW][64];
-  __shared__ int nx_pref[NW][64], nx_nylo[NW][64];
-
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int T0 = tile_id * TILE;
-  const int T1 = min(T0 + TILE, ra.n_samples);
-
-  if (!valid) {
-    for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) dst[k] = __builtin_nanf("");
-    return;
-  }
-  const AxisEntry *__restrict__ tx = tab + ra.off[0];
-  const AxisEntry *__restrict__ ty = tab + ra.off[1];
-  const AxisEntry *__restrict__ tz = tab + ra.off[2];
-  const AxisRange ax{ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]};
-  const AxisRange ay{ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]};
-  const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
-
-  float *__restrict__ wt = tile[wave];
-  uint8_t *__restrict__ wc = claim[wave];
-  for (int i = lane; i < SPAN; i += 64) wt[i] = 0.0f;
-
+__device__ __forceinline__ ItemGeom item_geom(const RoomArgs &ra, const AxisRange &ax, int tile_id, int C, int c) {
+  ItemGeom g;
+  g.T0 = tile_id * TILE;
+  g.T1 = min(g.T0 + TILE, ra.n_samples);
   // Images whose window reaches the tile have delay x in (T0 - W/2, T1 - 1 + W/2);
   // the enumeration bounds are widened by two samples on each side and every
   // candidate is then filtered exactly on its integer delay.
-  const float R1 = (float)(T1 - 1) + ra.half_w + 2.0f;
-  const float R0 = (float)T0 - ra.half_w - 2.0f;
-  float r1h, r1l, r0h = 0.0f, r0l = 0.0f;
-  two_prod(R1, R1, r1h, r1l);
-  if (R0 > 0.0f) two_prod(R0, R0, r0h, r0l);
-
-  // Slab of the shell along the x displacement owned by this chunk.
+  g.R1 = (float)(g.T1 - 1) + ra.half_w + 2.0f;
+  g.R0 = (float)g.T0 - ra.half_w - 2.0f;
+  two_prod(g.R1, g.R1, g.r1h, g.r1l);
+  g.r0h = 0.0f;
+  g.r0l = 0.0f;
+  if (g.R0 > 0.0f) two_prod(g.R0, g.R0, g.r0h, g.r0l);
+  // Slab of the shell along the x displacement owned by chunk c of C.
   float dlo = -INFINITY, dhi = INFINITY;
-  if (c > 0) dlo = -R1 + (2.0f * R1) * ((float)c / (float)C);
-  if (c < C - 1) dhi = -R1 + (2.0f * R1) * ((float)(c + 1) / (float)C);
-  const int nx_a = max(first_ge(ax, dlo), first_ge(ax, -R1));
-  const int nx_b = min(first_ge(ax, dhi), first_ge(ax, R1));
+  if (c > 0) dlo = -g.R1 + (2.0f * g.R1) * ((float)c / (float)C);
+  if (c < C - 1) dhi = -g.R1 + (2.0f * g.R1) * ((float)(c + 1) / (float)C);
+  g.nx_a = max(first_ge(ax, dlo), first_ge(ax, -g.R1));
+  g.nx_b = min(first_ge(ax, dhi), first_ge(ax, g.R1));
+  return g;
+}
 
-  // Image held by this lane, with its tap parameters.
-  bool has = false;
-  float f = 0.0f, C2 = 0.0f, CP = 0.0f, CQ = 0.0f;
-  int base = 0;
-
-  // Claim positions, add the taps of the winning lanes (distinct bases).
-  auto tap_round = [&]() {
-    volatile uint8_t *vc = wc;
-    if (has) vc[base] = (uint8_t)lane;
-    wave_sync();
-    const bool win = has && vc[base] == (uint8_t)lane;
-    // Each tap: issue the LDS read, compute the tap while it is in flight, add,
-    // write back. The scheduling barrier keeps taps in this order (bounded
-    // register use, hence more waves to hide the LDS round trip).
-    if (win && !HALF) {
-      float *t = wt + base;
-#pragma unroll
-      for (int jj = 0; jj < WT; ++jj) {
-        const float o = t[jj];
-        // ties this tap's arithmetic to its place in the chain (no instruction)
-        __asm__ volatile("" : "+v"(f), "+v"(CP), "+v"(CQ), "+v"(C2) :: "memory");
-        const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
-        const float r = __builtin_amdgcn_rcpf(u);
-        float w = __builtin_fmaf(K.cth[jj], CP, C2);
-        w = __builtin_fmaf(K.sth[jj], CQ, w);
-        t[jj] = __builtin_fmaf(w, r, o);
-        __asm__ volatile("" ::: "memory");
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    if (win && HALF) {
-      constexpr PolyConsts<WT> P = make_poly_consts<WT>();
-      float *t = wt + base;
-      const _Float16 th = (_Float16)(f - 0.5f);
-      half2_t tt = {th, th};
-      const float Cc = 2.0f * C2;
-#pragma unroll
-      for (int jj = 0; jj < WT; ++jj) {
-        const int j = jj + 1 - WT / 2;
-        if (!poly_tap(j)) {
-          const float o = t[jj];
-          __asm__ volatile("" : "+v"(f), "+v"(CP), "+v"(CQ), "+v"(C2) :: "memory");
-          const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
-          const float r = __builtin_amdgcn_rcpf(u);
-          float w = __builtin_fmaf(K.cth[jj], CP, C2);
-          w = __builtin_fmaf(K.sth[jj], CQ, w);
-          t[jj] = __builtin_fmaf(w, r, o);
-          __asm__ volatile("" ::: "memory");
-          __builtin_amdgcn_sched_barrier(0);
-        } else if (jj + 1 < WT && poly_tap(j + 1) && ((j <= -2) ? (j - JLO) % 2 == 0 : (j - 3) % 2 == 0)) {
-          // taps jj and jj + 1 in one packed register
-          const half2_t c3 = {(_Float16)P.c[3][jj], (_Float16)P.c[3][jj + 1]};
-          const half2_t c2 = {(_Float16)P.c[2][jj], (_Float16)P.c[2][jj + 1]};
-          const half2_t c1 = {(_Float16)P.c[1][jj], (_Float16)P.c[1][jj + 1]};
-          const half2_t c0 = {(_Float16)P.c[0][jj], (_Float16)P.c[0][jj + 1]};
-          const float o0 = t[jj];
-          __asm__ volatile("" : "+v"(tt) :: "memory");
-          half2_t pv = __builtin_elementwise_fma(c3, tt, c2);
-          pv = __builtin_elementwise_fma(pv, tt, c1);
-          pv = __builtin_elementwise_fma(pv, tt, c0);
-          t[jj] = __builtin_fmaf((float)pv.x, Cc, o0);
-          __asm__ volatile("" ::: "memory");
-          const float o1 = t[jj + 1];
-          t[jj + 1] = __builtin_fmaf((float)pv.y, Cc, o1);
-          __asm__ volatile("" ::: "memory");
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-    }
-    has = has && !win;
-    wave_sync();
-  };
-
-  for (int nx0 = nx_a; nx0 < nx_b; nx0 += 64) {
+// Walks the shell of the item. For every filled queue chunk (entries
+// [0, qn) of es.queue, with the column data of the current batch in es.col_*)
+// calls consume(qn), which must use up all qn entries. Waves of a block take
+// column batches round-robin (wave = 0..NW-1).
+template <int NW, class Consume>
+__device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEntry *__restrict__ tx,
+                                                const AxisEntry *__restrict__ ty, const AxisRange &ay,
+                                                const AxisRange &az, EnumLds &es, const int wave,
+                                                Consume &&consume) {
+  const int lane = threadIdx.x & 63;
+  for (int nx0 = g.nx_a; nx0 < g.nx_b; nx0 += 64) {
     // lanes = x indices: y range of the columns that reach the outer sphere
     const int nxi = nx0 + lane;
     int ny_lo = 0, ny_cnt = 0;
-    if (nxi < nx_b) {
+    if (nxi < g.nx_b) {
       const AxisEntry ex = tx[nxi];
       float qh, ql, rh, rl;
       ff_sq(ex.d_hi, ex.d_lo, qh, ql);
-      ff_sub(r1h, r1l, qh, ql, rh, rl);
+      ff_sub(g.r1h, g.r1l, qh, ql, rh, rl);
       if (rh > 0.0f) {
         const float R = __builtin_sqrtf(rh) + 1.0f;
         ny_lo = first_ge(ay, -R);
@@ -500,38 +427,38 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     }
     const int incl_y = wave_incl_scan(ny_cnt);
     const int ncols = __builtin_amdgcn_readlane(incl_y, 63);
-    nx_pref[wave][lane] = incl_y - ny_cnt;
-    nx_nylo[wave][lane] = ny_lo;
+    es.nx_pref[lane] = incl_y - ny_cnt;
+    es.nx_nylo[lane] = ny_lo;
     wave_sync();
 
     for (int cb = wave; cb * 64 < ncols; cb += NW) {
       // lanes = columns (nx, ny): z ranges of the shell
-      const int g = cb * 64 + lane;
+      const int gcol = cb * 64 + lane;
       int z1 = 0, n1 = 0, z2 = 0, n2 = 0;
-      if (g < ncols) {
+      if (gcol < ncols) {
         int i = 0;
 #pragma unroll
         for (int step = 32; step > 0; step >>= 1)
-          if (i + step < 64 && nx_pref[wave][i + step] <= g) i += step;
+          if (i + step < 64 && es.nx_pref[i + step] <= gcol) i += step;
         const AxisEntry ex = tx[nx0 + i];
-        const AxisEntry ey = ty[nx_nylo[wave][i] + (g - nx_pref[wave][i])];
+        const AxisEntry ey = ty[es.nx_nylo[i] + (gcol - es.nx_pref[i])];
         float ah, al, bh, bl, sh, sl;
         ff_sq(ex.d_hi, ex.d_lo, ah, al);
         ff_sq(ey.d_hi, ey.d_lo, bh, bl);
         two_sum(ah, bh, sh, sl);
         sl += al + bl;
         fast_two_sum(sh, sl, sh, sl);
-        col_sh[wave][lane] = sh;
-        col_sl[wave][lane] = sl;
-        col_g[wave][lane] = ex.gain * ey.gain;
+        es.col_sh[lane] = sh;
+        es.col_sl[lane] = sl;
+        es.col_g[lane] = ex.gain * ey.gain;
         float rh, rl;
-        ff_sub(r1h, r1l, sh, sl, rh, rl);
+        ff_sub(g.r1h, g.r1l, sh, sl, rh, rl);
         if (rh > 0.0f) {
           const float zmax = __builtin_sqrtf(rh) + 1.0f;
           float zmin = 0.0f;
-          if (R0 > 0.0f) {
+          if (g.R0 > 0.0f) {
             float hh, hl;
-            ff_sub(r0h, r0l, sh, sl, hh, hl);
+            ff_sub(g.r0h, g.r0l, sh, sl, hh, hl);
             if (hh > 0.0f) zmin = fmaxf(__builtin_sqrtf(hh) - 1.0f, 0.0f);
           }
           if (zmin > 0.0f) {
@@ -555,62 +482,306 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         const int i_lo = max(0, q0 - excl), i_hi = min(cnt, q0 + QCAP - excl);
         for (int i = i_lo; i < i_hi; ++i) {
           const int nz = (i < n1) ? z1 + i : z2 + (i - n1);
-          queue[wave][excl + i - q0] = ((uint32_t)lane << 16) | (uint32_t)nz;
+          es.queue[excl + i - q0] = ((uint32_t)lane << 16) | (uint32_t)nz;
         }
         wave_sync();
-        const int qn = min(QCAP, total - q0);
-        int qpos = 0;
-        while (qpos < qn) {
-          // refill the lanes without an image from the queue (lanes = images)
-          const bool need = !has;
-          const uint64_t need_mask = __ballot(need);
-          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need_mask >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
-          if (need && qpos + rank < qn) {
-            const uint32_t ent = queue[wave][qpos + rank];
-            const int cl = (int)(ent >> 16);
-            const int nz = (int)(ent & 0xffffu);
-            const AxisEntry ez = tz[nz];
-            float ph, pl, s, se, Sh, Sl;
-            ff_sq(ez.d_hi, ez.d_lo, ph, pl);
-            two_sum(col_sh[wave][cl], ph, s, se);
-            se += col_sl[wave][cl] + pl;
-            fast_two_sum(s, se, Sh, Sl);
-            // x = sqrt(S) in samples (Eq. (2)-(3)): one Newton correction in float-float
-            const float x0 = __builtin_amdgcn_sqrtf(Sh);
-            const float rx = __builtin_amdgcn_rcpf(x0);
-            const float xl = (__builtin_fmaf(-x0, x0, Sh) + Sl) * (0.5f * rx);
-            float kf = floorf(x0);
-            float fr = (x0 - kf) + xl;
-            if (fr < 0.0f) {
-              fr += 1.0f;
-              kf -= 1.0f;
-            }
-            if (fr >= 1.0f) {
-              fr -= 1.0f;
-              kf += 1.0f;
-            }
-            const int k0 = (int)kf;
-            base = k0 + JLO - T0 + MARGIN;
-            has = (x0 < 1.0e9f) && (k0 + JHI >= T0) && (k0 + JLO <= T1 - 1) && base >= 0 && base + WT <= SPAN;
-            // Eq. (4) amplitude and the per-image factors of the taps
-            const float A = col_g[wave][cl] * ez.gain * ra.kappa * rx;
-            f = fmaxf(fr, 0x1p-100f);
-            const float Cc = A * sinpi_over_pi(fminf(f, 1.0f - f));
-            float sp, cp;
-            small_sincos(f * ra.two_pi_over_w, sp, cp);
-            C2 = 0.5f * Cc;
-            CP = C2 * cp;
-            CQ = C2 * sp;
-          }
-          qpos += __builtin_popcountll(need_mask);
-          tap_round();
-        }
+        consume(min(QCAP, total - q0));
         wave_sync();
       }
     }
     wave_sync();
   }
+}
+
+// Parameters of one image candidate (queue entry ent). ok is false when the
+// image's window misses the tile. base is the tile-local LDS index of its tap
+// j = 1 - W/2 (tiles carry a margin of W samples on both sides).
+struct ImageParams {
+  bool ok;
+  int base;
+  float f, C2, CP, CQ;
+};
+template <int WT>
+__device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const ItemGeom &g, const EnumLds &es,
+                                                    const AxisEntry *__restrict__ tz, uint32_t ent) {
+  constexpr int JLO = 1 - WT / 2, JHI = WT / 2, MARGIN = WT, SPAN = TILE + 2 * MARGIN;
+  ImageParams p;
+  const int cl = (int)(ent >> 16);
+  const int nz = (int)(ent & 0xffffu);
+  const AxisEntry ez = tz[nz];
+  float ph, pl, s, se, Sh, Sl;
+  ff_sq(ez.d_hi, ez.d_lo, ph, pl);
+  two_sum(es.col_sh[cl], ph, s, se);
+  se += es.col_sl[cl] + pl;
+  fast_two_sum(s, se, Sh, Sl);
+  // x = sqrt(S) in samples (Eq. (2)-(3)): one Newton correction in float-float
+  const float x0 = __builtin_amdgcn_sqrtf(Sh);
+  const float rx = __builtin_amdgcn_rcpf(x0);
+  const float xl = (__builtin_fmaf(-x0, x0, Sh) + Sl) * (0.5f * rx);
+  float kf = floorf(x0);
+  float fr = (x0 - kf) + xl;
+  if (fr < 0.0f) {
+    fr += 1.0f;
+    kf -= 1.0f;
+  }
+  if (fr >= 1.0f) {
+    fr -= 1.0f;
+    kf += 1.0f;
+  }
+  const int k0 = (int)kf;
+  p.base = k0 + JLO - g.T0 + MARGIN;
+  p.ok = (x0 < 1.0e9f) && (k0 + JHI >= g.T0) && (k0 + JLO <= g.T1 - 1) && p.base >= 0 && p.base + WT <= SPAN;
+  // Eq. (4) amplitude and the per-image factors of the taps
+  const float A = es.col_g[cl] * ez.gain * ra.kappa * rx;
+  p.f = fmaxf(fr, 0x1p-100f);
+  const float Cc = A * sinpi_over_pi(fminf(p.f, 1.0f - p.f));
+  float sp, cp;
+  small_sincos(p.f * ra.two_pi_over_w, sp, cp);
+  p.C2 = 0.5f * Cc;
+  p.CP = p.C2 * cp;
+  p.CQ = p.C2 * sp;
+  return p;
+}
+
+// Tap constants of the FP32 consumer, lane l of a half-wave holds taps
+// j = 1 - W/2 + l + 32 m, m = 0 .. W/32 - 1 (index jj = l + 32 m).
+__constant__ TapConsts<32> kTap32 = make_tap_consts<32>();
+__constant__ TapConsts<64> kTap64 = make_tap_consts<64>();
+__constant__ TapConsts<96> kTap96 = make_tap_consts<96>();
+__constant__ TapConsts<128> kTap128 = make_tap_consts<128>();
+template <int WT> __device__ __forceinline__ const TapConsts<WT> &tap_table();
+template <> __device__ __forceinline__ const TapConsts<32> &tap_table<32>() { return kTap32; }
+template <> __device__ __forceinline__ const TapConsts<64> &tap_table<64>() { return kTap64; }
+template <> __device__ __forceinline__ const TapConsts<96> &tap_table<96>() { return kTap96; }
+template <> __device__ __forceinline__ const TapConsts<128> &tap_table<128>() { return kTap128; }
+
+constexpr int SCAP = 68;  // staged images: up to 64 new + 1 carried, + read-ahead slots
+
+// FP32 work item, one wave (lanes = taps). dst receives the T1 - T0 samples of
+// the tile (or a partial tile when C > 1).
+template <int WT>
+__device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const int tile_id, const int C, const int c,
+                                                     const AxisEntry *__restrict__ tab, const AxisOrigin &org,
+                                                     const bool valid, float *__restrict__ dst) {
+  constexpr int MARGIN = WT;
+  constexpr int SPAN = TILE + 2 * MARGIN;
+  constexpr int TPL = WT / 32;
+
+  __shared__ float tile[2][SPAN];
+  __shared__ float4 stp[SCAP];  // f, CP, CQ, C2 of staged images
+  __shared__ int stb[SCAP];     // their bases
+  __shared__ EnumLds es;
+
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, l = lane & 31;
+  const int T0 = tile_id * TILE;
+  const int T1 = min(T0 + TILE, ra.n_samples);
+  if (!valid) {
+    for (int k = lane; k < T1 - T0; k += 64) dst[k] = __builtin_nanf("");
+    return;
+  }
+  const AxisEntry *__restrict__ tx = tab + ra.off[0];
+  const AxisEntry *__restrict__ ty = tab + ra.off[1];
+  const AxisEntry *__restrict__ tz = tab + ra.off[2];
+  const AxisRange ax{ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]};
+  const AxisRange ay{ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]};
+  const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
+  const ItemGeom g = item_geom(ra, ax, tile_id, C, c);
+
+  float nsg[TPL], sgj[TPL], cth[TPL], sth[TPL];
+  {
+    const TapConsts<WT> &K = tap_table<WT>();
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+      nsg[m] = -K.sig[l + 32 * m];
+      sgj[m] = K.sig_j[l + 32 * m];
+      cth[m] = K.cth[l + 32 * m];
+      sth[m] = K.sth[l + 32 * m];
+    }
+  }
+  for (int i = lane; i < 2 * SPAN; i += 64) (&tile[0][0])[i] = 0.0f;
+  float *const th = &tile[h][l];
+
+  // One step: staged image (P, b) on this half-wave, taps l + 32 m.
+  auto step = [&](const float4 P, const int b) {
+    float *t = th + b;
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+      const float u = __builtin_fmaf(nsg[m], P.x, sgj[m]);
+      const float r = __builtin_amdgcn_rcpf(u);
+      float w = __builtin_fmaf(cth[m], P.y, P.w);
+      w = __builtin_fmaf(sth[m], P.z, w);
+      t[32 * m] = __builtin_fmaf(w, r, t[32 * m]);
+    }
+  };
+
+  int ns = 0;  // staged images (wave-uniform)
+  enumerate_shell<1>(g, tx, ty, ay, az, es, 0, [&](int qn) {
+    for (int q = 0; q < qn; q += 64) {
+      // lanes = candidates: parameters, then compaction into the stage
+      ImageParams p;
+      p.ok = false;
+      if (q + lane < qn) p = image_params<WT>(ra, g, es, tz, es.queue[q + lane]);
+      const uint64_t okm = __ballot(p.ok);
+      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
+      if (p.ok) {
+        stp[ns + rank] = make_float4(p.f, p.CP, p.CQ, p.C2);
+        stb[ns + rank] = p.base;
+      }
+      ns += __builtin_popcountll(okm);
+      wave_sync();
+      // lanes = taps: two staged images per step, one per half-wave; the
+      // next step's parameters are read ahead of this step's tile update
+      const int np = ns >> 1;
+      // (reads ahead stay inside the stage: indices <= 2 np + 1 <= SCAP - 1)
+      float4 PA = stp[h];
+      int bA = stb[h];
+      for (int s = 0; s < np; s += 2) {
+        const float4 PB = stp[2 * s + 2 + h];
+        const int bB = stb[2 * s + 2 + h];
+        __builtin_amdgcn_sched_barrier(0);  // keep the read-ahead in front of the step
+        step(PA, bA);
+        if (s + 1 < np) {
+          PA = stp[2 * s + 4 + h];
+          bA = stb[2 * s + 4 + h];
+          __builtin_amdgcn_sched_barrier(0);
+          step(PB, bB);
+        }
+      }
+      if (ns & 1) {  // carry the odd image to the front of the stage
+        const float4 P = stp[ns - 1];
+        const int b = stb[ns - 1];
+        wave_sync();
+        if (lane == 0) {
+          stp[0] = P;
+          stb[0] = b;
+        }
+      }
+      ns &= 1;
+      wave_sync();
+    }
+  });
+  if (ns == 1 && h == 0) step(stp[0], stb[0]);
+
+  wave_sync();
+  for (int k = lane; k < T1 - T0; k += 64) dst[k] = tile[0][MARGIN + k] + tile[1][MARGIN + k];
+}
+
+// FP16 work item (lanes = images), NW waves per block.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+template <int WT, int NW>
+__device__ __forceinline__ void accumulate_item_half(const RoomArgs &ra, const int tile_id, const int C, const int c,
+                                                     const AxisEntry *__restrict__ tab, const AxisOrigin &org,
+                                                     const bool valid, float *__restrict__ dst) {
+  constexpr int JLO = 1 - WT / 2;
+  constexpr int MARGIN = WT;
+  constexpr int SPAN = TILE + 2 * MARGIN;
+  constexpr TapConsts<WT> K = make_tap_consts<WT>();
+  constexpr PolyConsts<WT> PC = make_poly_consts<WT>();
+
+  __shared__ float tile[NW][SPAN];
+  __shared__ uint8_t claim[NW][SPAN];
+  __shared__ EnumLds es_all[NW];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int T0 = tile_id * TILE;
+  const int T1 = min(T0 + TILE, ra.n_samples);
+
+  if (!valid) {
+    for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) dst[k] = __builtin_nanf("");
+    return;
+  }
+  const AxisEntry *__restrict__ tx = tab + ra.off[0];
+  const AxisEntry *__restrict__ ty = tab + ra.off[1];
+  const AxisEntry *__restrict__ tz = tab + ra.off[2];
+  const AxisRange ax{ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]};
+  const AxisRange ay{ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]};
+  const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
+  const ItemGeom g = item_geom(ra, ax, tile_id, C, c);
+  EnumLds &es = es_all[wave];
+
+  float *__restrict__ wt = tile[wave];
+  uint8_t *__restrict__ wc = claim[wave];
+  for (int i = lane; i < SPAN; i += 64) wt[i] = 0.0f;
+
+  // Image held by this lane, with its tap parameters.
+  bool has = false;
+  float f = 0.0f, C2 = 0.0f, CP = 0.0f, CQ = 0.0f;
+  int base = 0;
+
+  // Claim positions, add the taps of the winning lanes (distinct bases). A
+  // compiler barrier between taps keeps every lane's read-modify-write of tap
+  // j ahead of any lane's access for tap j + 1.
+  auto tap_round = [&]() {
+    volatile uint8_t *vc = wc;
+    if (has) vc[base] = (uint8_t)lane;
+    wave_sync();
+    const bool win = has && vc[base] == (uint8_t)lane;
+    if (win) {
+      float *t = wt + base;
+      const _Float16 thf = (_Float16)(f - 0.5f);
+      half2_t tt = {thf, thf};
+      const float Cc = 2.0f * C2;
+#pragma unroll
+      for (int jj = 0; jj < WT; ++jj) {
+        const int j = jj + JLO;
+        if (!poly_tap(j)) {
+          const float o = t[jj];
+          __asm__ volatile("" : "+v"(f), "+v"(CP), "+v"(CQ), "+v"(C2) :: "memory");
+          const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
+          const float r = __builtin_amdgcn_rcpf(u);
+          float w = __builtin_fmaf(K.cth[jj], CP, C2);
+          w = __builtin_fmaf(K.sth[jj], CQ, w);
+          t[jj] = __builtin_fmaf(w, r, o);
+          __asm__ volatile("" ::: "memory");
+          __builtin_amdgcn_sched_barrier(0);
+        } else if (jj + 1 < WT && poly_tap(j + 1) && ((j <= -2) ? (j - JLO) % 2 == 0 : (j - 3) % 2 == 0)) {
+          // taps jj and jj + 1 in one packed register
+          const half2_t c3 = {(_Float16)PC.c[3][jj], (_Float16)PC.c[3][jj + 1]};
+          const half2_t c2 = {(_Float16)PC.c[2][jj], (_Float16)PC.c[2][jj + 1]};
+          const half2_t c1 = {(_Float16)PC.c[1][jj], (_Float16)PC.c[1][jj + 1]};
+          const half2_t c0 = {(_Float16)PC.c[0][jj], (_Float16)PC.c[0][jj + 1]};
+          const float o0 = t[jj];
+          __asm__ volatile("" : "+v"(tt) :: "memory");
+          half2_t pv = __builtin_elementwise_fma(c3, tt, c2);
+          pv = __builtin_elementwise_fma(pv, tt, c1);
+          pv = __builtin_elementwise_fma(pv, tt, c0);
+          t[jj] = __builtin_fmaf((float)pv.x, Cc, o0);
+          __asm__ volatile("" ::: "memory");
+          const float o1 = t[jj + 1];
+          t[jj + 1] = __builtin_fmaf((float)pv.y, Cc, o1);
+          __asm__ volatile("" ::: "memory");
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    has = has && !win;
+    wave_sync();
+  };
+
+  enumerate_shell<NW>(g, tx, ty, ay, az, es, wave, [&](int qn) {
+    int qpos = 0;
+    while (qpos < qn) {
+      // refill the lanes without an image from the queue (lanes = images)
+      const bool need = !has;
+      const uint64_t need_mask = __ballot(need);
+      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need_mask >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
+      if (need && qpos + rank < qn) {
+        const ImageParams p = image_params<WT>(ra, g, es, tz, es.queue[qpos + rank]);
+        has = p.ok;
+        base = p.base;
+        f = p.f;
+        C2 = p.C2;
+        CP = p.CP;
+        CQ = p.CQ;
+      }
+      qpos += __builtin_popcountll(need_mask);
+      tap_round();
+    }
+  });
   // images still waiting after their queue ran out
   while (__ballot(has) != 0) tap_round();
 
@@ -621,6 +792,16 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     for (int w = 0; w < NW; ++w) v += tile[w][MARGIN + k];
     dst[k] = v;
   }
+}
+
+template <int WT, int NW, bool HALF>
+__device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
+                                                const AxisEntry *__restrict__ tab, const AxisOrigin &org,
+                                                const bool valid, float *__restrict__ dst) {
+  if constexpr (HALF)
+    accumulate_item_half<WT, NW>(ra, tile_id, C, c, tab, org, valid, dst);
+  else
+    accumulate_item_taps<WT>(ra, tile_id, C, c, tab, org, valid, dst);
 }
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
@@ -723,7 +904,7 @@ int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEn
 template <int WT, bool HALF>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                         const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st) {
-  constexpr int NW = 4;
+  constexpr int NW = HALF ? 4 : 1;  // FP32 items run on one wave, FP16 items on four
   hipLaunchKernelGGL((accumulate_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, origin,
                      valid, out, part);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -751,7 +932,7 @@ int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa,
 template <int WT, bool HALF>
 static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
                               const AxisOrigin *origin, const int *valid, float *part, hipStream_t st) {
-  constexpr int NW = 4;
+  constexpr int NW = HALF ? 4 : 1;  // FP32 items run on one wave, FP16 items on four
   hipLaunchKernelGGL((accumulate_batch_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, jobs, items, tab,
                      origin, valid, part);
   return hipGetLastError() == hipSuccess ? 0 : -1;
