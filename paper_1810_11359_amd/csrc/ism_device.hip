@@ -372,8 +372,9 @@ struct EnumLds {
 
 // Wave-uniform geometry of one work item.
 struct ItemGeom {
-  int T0, T1;                    // output samples of the tile
-  float R0, R1;                  // shell radii in samples, widened by W/2 + 2
+  int T0, T1;                    // output samples [T0, T1) of the tile (empty past nS)
+  int K1;                        // owned integer delays: k0 in [T0, K1)
+  float R0, R1;                  // shell radii in samples, widened by 2
   float r1h, r1l, r0h, r0l;      // their squares (float-float)
   int nx_a, nx_b;                // x table indices of the slab
 };
@@ -382,11 +383,12 @@ __device__ __forceinline__ ItemGeom item_geom(const RoomArgs &ra, const AxisRang
   ItemGeom g;
   g.T0 = tile_id * TILE;
   g.T1 = min(g.T0 + TILE, ra.n_samples);
-  // Images whose window reaches the tile have delay x in (T0 - W/2, T1 - 1 + W/2);
-  // the enumeration bounds are widened by two samples on each side and every
-  // candidate is then filtered exactly on its integer delay.
-  g.R1 = (float)(g.T1 - 1) + ra.half_w + 2.0f;
-  g.R0 = (float)g.T0 - ra.half_w - 2.0f;
+  g.K1 = min(g.T0 + TILE, ra.k_end);
+  // The owned images have delay x in [T0, K1); the enumeration bounds are
+  // widened by two samples on each side and every candidate is then filtered
+  // exactly on its integer delay.
+  g.R1 = (float)g.K1 + 2.0f;
+  g.R0 = (float)g.T0 - 2.0f;
   two_prod(g.R1, g.R1, g.r1h, g.r1l);
   g.r0h = 0.0f;
   g.r0l = 0.0f;
@@ -494,8 +496,8 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
 }
 
 // Parameters of one image candidate (queue entry ent). ok is false when the
-// image's window misses the tile. base is the tile-local LDS index of its tap
-// j = 1 - W/2 (tiles carry a margin of W samples on both sides).
+// tile does not own the image. base = k0 - T0 is the tile-local LDS index of its
+// tap j = 1 - W/2 (the LDS tile starts at sample T0 + 1 - W/2).
 struct ImageParams {
   bool ok;
   int base;
@@ -503,12 +505,9 @@ struct ImageParams {
 };
 template <int WT>
 __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const ItemGeom &g, const EnumLds &es,
-                                                    const AxisEntry *__restrict__ tz, uint32_t ent) {
-  constexpr int JLO = 1 - WT / 2, JHI = WT / 2, MARGIN = WT, SPAN = TILE + 2 * MARGIN;
+                                                    const AxisEntry ez, uint32_t ent) {
   ImageParams p;
   const int cl = (int)(ent >> 16);
-  const int nz = (int)(ent & 0xffffu);
-  const AxisEntry ez = tz[nz];
   float ph, pl, s, se, Sh, Sl;
   ff_sq(ez.d_hi, ez.d_lo, ph, pl);
   two_sum(es.col_sh[cl], ph, s, se);
@@ -518,19 +517,17 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
   const float x0 = __builtin_amdgcn_sqrtf(Sh);
   const float rx = __builtin_amdgcn_rcpf(x0);
   const float xl = (__builtin_fmaf(-x0, x0, Sh) + Sl) * (0.5f * rx);
+  // k0 = floor(x), f = x - k0: |xl| is below half an ulp of x0, so the
+  // fraction (x0 - floor(x0)) + xl lies in (-1, 2) and one floor moves it into
+  // [0, 1); the clamp catches a tiny negative fraction that rounds up to 1.
   float kf = floorf(x0);
   float fr = (x0 - kf) + xl;
-  if (fr < 0.0f) {
-    fr += 1.0f;
-    kf -= 1.0f;
-  }
-  if (fr >= 1.0f) {
-    fr -= 1.0f;
-    kf += 1.0f;
-  }
+  const float d = floorf(fr);
+  fr = fminf(fr - d, 0x1.fffffep-1f);
+  kf += d;
   const int k0 = (int)kf;
-  p.base = k0 + JLO - g.T0 + MARGIN;
-  p.ok = (x0 < 1.0e9f) && (k0 + JHI >= g.T0) && (k0 + JLO <= g.T1 - 1) && p.base >= 0 && p.base + WT <= SPAN;
+  p.base = k0 - g.T0;
+  p.ok = (x0 < 1.0e9f) && (uint32_t)p.base < (uint32_t)(g.K1 - g.T0);
   // Eq. (4) amplitude and the per-image factors of the taps
   const float A = es.col_g[cl] * ez.gain * ra.kappa * rx;
   p.f = fmaxf(fr, 0x1p-100f);
@@ -557,27 +554,54 @@ template <> __device__ __forceinline__ const TapConsts<128> &tap_table<128>() { 
 
 constexpr int SCAP = 68;  // staged images: up to 64 new + 1 carried, + read-ahead slots
 
-// FP32 work item, one wave (lanes = taps). dst receives the T1 - T0 samples of
-// the tile (or a partial tile when C > 1).
+// Output of a work item whose taps are in LDS tiles t0 (+ t1): the tile's own
+// samples go to dst, the W/2 - 1 samples before and the W/2 after to marg
+// (layout: left margin, then right margin; W - 1 values).
+template <int WT, int NT>
+__device__ __forceinline__ void write_item(float (*tile)[TILE + WT - 1], int n_own, float *__restrict__ dst,
+                                           float *__restrict__ marg, int tid, int nthreads) {
+  constexpr int LM = WT / 2 - 1;
+  for (int k = tid; k < n_own; k += nthreads) {
+    float v = tile[0][LM + k];
+#pragma unroll
+    for (int w = 1; w < NT; ++w) v += tile[w][LM + k];
+    dst[k] = v;
+  }
+  for (int i = tid; i < WT - 1; i += nthreads) {
+    const int ti = i < LM ? i : TILE + i;
+    float v = tile[0][ti];
+#pragma unroll
+    for (int w = 1; w < NT; ++w) v += tile[w][ti];
+    marg[i] = v;
+  }
+}
+template <int WT>
+__device__ __forceinline__ void write_invalid(int n_own, float *__restrict__ dst, float *__restrict__ marg, int tid,
+                                              int nthreads) {
+  for (int k = tid; k < n_own; k += nthreads) dst[k] = __builtin_nanf("");
+  for (int i = tid; i < WT - 1; i += nthreads) marg[i] = __builtin_nanf("");
+}
+
+// FP32 work item, one wave (lanes = taps). dst receives the T1 - T0 own
+// samples of the tile (or a partial tile when C > 1), marg the margins.
 template <int WT>
 __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                      const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                     const bool valid, float *__restrict__ dst) {
-  constexpr int MARGIN = WT;
-  constexpr int SPAN = TILE + 2 * MARGIN;
+                                                     const bool valid, float *__restrict__ dst,
+                                                     float *__restrict__ marg) {
+  constexpr int LSPAN = TILE + WT - 1;
   constexpr int TPL = WT / 32;
 
-  __shared__ float tile[2][SPAN];
+  __shared__ float tile[2][LSPAN];
   __shared__ float4 stp[SCAP];  // f, CP, CQ, C2 of staged images
   __shared__ int stb[SCAP];     // their bases
   __shared__ EnumLds es;
 
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, l = lane & 31;
-  const int T0 = tile_id * TILE;
-  const int T1 = min(T0 + TILE, ra.n_samples);
+  const int n_own = min(TILE, ra.n_samples - tile_id * TILE);  // may be <= 0 past nS
   if (!valid) {
-    for (int k = lane; k < T1 - T0; k += 64) dst[k] = __builtin_nanf("");
+    write_invalid<WT>(n_own, dst, marg, lane, 64);
     return;
   }
   const AxisEntry *__restrict__ tx = tab + ra.off[0];
@@ -599,7 +623,7 @@ __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const i
       sth[m] = K.sth[l + 32 * m];
     }
   }
-  for (int i = lane; i < 2 * SPAN; i += 64) (&tile[0][0])[i] = 0.0f;
+  for (int i = lane; i < 2 * LSPAN; i += 64) (&tile[0][0])[i] = 0.0f;
   float *const th = &tile[h][l];
 
   // One step: staged image (P, b) on this half-wave, taps l + 32 m.
@@ -617,11 +641,24 @@ __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const i
 
   int ns = 0;  // staged images (wave-uniform)
   enumerate_shell<1>(g, tx, ty, ay, az, es, 0, [&](int qn) {
+    // queue entries and z table rows are read one chunk of 64 ahead
+    uint32_t ent = 0;
+    AxisEntry ez{0.0f, 0.0f, 0.0f, 0.0f};
+    if (lane < qn) {
+      ent = es.queue[lane];
+      ez = tz[ent & 0xffffu];
+    }
     for (int q = 0; q < qn; q += 64) {
+      const uint32_t ent_c = ent;
+      const AxisEntry ez_c = ez;
+      if (q + 64 + lane < qn) {
+        ent = es.queue[q + 64 + lane];
+        ez = tz[ent & 0xffffu];
+      }
       // lanes = candidates: parameters, then compaction into the stage
       ImageParams p;
       p.ok = false;
-      if (q + lane < qn) p = image_params<WT>(ra, g, es, tz, es.queue[q + lane]);
+      if (q + lane < qn) p = image_params<WT>(ra, g, es, ez_c, ent_c);
       const uint64_t okm = __ballot(p.ok);
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
       if (p.ok) {
@@ -664,7 +701,7 @@ __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const i
   if (ns == 1 && h == 0) step(stp[0], stb[0]);
 
   wave_sync();
-  for (int k = lane; k < T1 - T0; k += 64) dst[k] = tile[0][MARGIN + k] + tile[1][MARGIN + k];
+  write_item<WT, 2>(tile, n_own, dst, marg, lane, 64);
 }
 
 // FP16 work item (lanes = images), NW waves per block.
@@ -673,10 +710,10 @@ typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 template <int WT, int NW>
 __device__ __forceinline__ void accumulate_item_half(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                      const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                     const bool valid, float *__restrict__ dst) {
+                                                     const bool valid, float *__restrict__ dst,
+                                                     float *__restrict__ marg) {
   constexpr int JLO = 1 - WT / 2;
-  constexpr int MARGIN = WT;
-  constexpr int SPAN = TILE + 2 * MARGIN;
+  constexpr int SPAN = TILE + WT - 1;
   constexpr TapConsts<WT> K = make_tap_consts<WT>();
   constexpr PolyConsts<WT> PC = make_poly_consts<WT>();
 
@@ -686,11 +723,10 @@ __device__ __forceinline__ void accumulate_item_half(const RoomArgs &ra, const i
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int T0 = tile_id * TILE;
-  const int T1 = min(T0 + TILE, ra.n_samples);
+  const int n_own = min(TILE, ra.n_samples - tile_id * TILE);
 
   if (!valid) {
-    for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) dst[k] = __builtin_nanf("");
+    write_invalid<WT>(n_own, dst, marg, threadIdx.x, NW * 64);
     return;
   }
   const AxisEntry *__restrict__ tx = tab + ra.off[0];
@@ -770,7 +806,8 @@ __device__ __forceinline__ void accumulate_item_half(const RoomArgs &ra, const i
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need_mask >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
       if (need && qpos + rank < qn) {
-        const ImageParams p = image_params<WT>(ra, g, es, tz, es.queue[qpos + rank]);
+        const uint32_t ent = es.queue[qpos + rank];
+        const ImageParams p = image_params<WT>(ra, g, es, tz[ent & 0xffffu], ent);
         has = p.ok;
         base = p.base;
         f = p.f;
@@ -786,22 +823,17 @@ __device__ __forceinline__ void accumulate_item_half(const RoomArgs &ra, const i
   while (__ballot(has) != 0) tap_round();
 
   __syncthreads();
-  for (int k = threadIdx.x; k < T1 - T0; k += NW * 64) {
-    float v = 0.0f;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) v += tile[w][MARGIN + k];
-    dst[k] = v;
-  }
+  write_item<WT, NW>(tile, n_own, dst, marg, threadIdx.x, NW * 64);
 }
 
 template <int WT, int NW, bool HALF>
 __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                 const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                const bool valid, float *__restrict__ dst) {
+                                                const bool valid, float *__restrict__ dst, float *__restrict__ marg) {
   if constexpr (HALF)
-    accumulate_item_half<WT, NW>(ra, tile_id, C, c, tab, org, valid, dst);
+    accumulate_item_half<WT, NW>(ra, tile_id, C, c, tab, org, valid, dst, marg);
   else
-    accumulate_item_taps<WT>(ra, tile_id, C, c, tab, org, valid, dst);
+    accumulate_item_taps<WT>(ra, tile_id, C, c, tab, org, valid, dst, marg);
 }
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
@@ -810,7 +842,7 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
                                                              const int *__restrict__ valid, float *__restrict__ out,
-                                                             float *__restrict__ part) {
+                                                             float *__restrict__ part, float *__restrict__ marg) {
   const uint32_t item = blockIdx.x;
   int pos = 0;
   {
@@ -827,9 +859,11 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
   const uint32_t rel = item - pa.first_item[pos];
   const int rir = (int)(rel / (uint32_t)C);
   const int c = (int)(rel % (uint32_t)C);
+  // (for a tile past nS, dst is never written: the tile has no own samples)
   float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
   const AxisOrigin org = origin[rir];
-  accumulate_item<WT, NW, HALF>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst);
+  accumulate_item<WT, NW, HALF>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst,
+                                marg + (size_t)item * WT);
 }
 
 // Batch launch: every item names its job; the job table carries the room.
@@ -839,7 +873,7 @@ __global__ __launch_bounds__(NW * 64) void accumulate_batch_kernel(const JobDev 
                                                                    const AxisEntry *__restrict__ tab_all,
                                                                    const AxisOrigin *__restrict__ origin,
                                                                    const int *__restrict__ valid,
-                                                                   float *__restrict__ part) {
+                                                                   float *__restrict__ part, float *__restrict__ marg) {
   const BatchItem it = items[blockIdx.x];
   const JobDev &jb = jobs[it.job];
   const RoomArgs ra = jb.ra;
@@ -847,45 +881,84 @@ __global__ __launch_bounds__(NW * 64) void accumulate_batch_kernel(const JobDev 
   float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
                                         : part + (size_t)it.slot * TILE;
   const AxisOrigin org = origin[grir];
-  accumulate_item<WT, NW, HALF>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org,
-                          valid[grir] != 0, dst);
+  accumulate_item<WT, NW, HALF>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab,
+                                org, valid[grir] != 0, dst, marg + (size_t)it.mslot * MARG_STRIDE);
 }
 
 // ---------------------------------------------------------------------------
-// Kernel 3: ordered sum of the partial tiles of split tiles.
+// Kernel 3: ordered completion of the output tiles. Sample k of tile t is
+//   (own sum) + (right margins of the items of tile t-1) + (left margins of
+//   the items of tile t+1),
+// where the own sum is the ordered sum of the tile's partials when it was
+// split and the value already in the output otherwise. Every term is added in
+// a fixed order, so results do not depend on scheduling.
 // grid = (rir, dispatch position of the tile, 256-sample segment)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, const float *__restrict__ part,
-                                                     float *__restrict__ out) {
+                                                     const float *__restrict__ marg, float *__restrict__ out) {
   const int pos = blockIdx.y;
   const int tile_id = pa.n_tiles - 1 - pos;
   const int C = pa.chunks[tile_id];
-  if (C <= 1) return;
   const int rir = blockIdx.x;
   const int T0 = tile_id * TILE;
-  const int T1 = min(T0 + TILE, ra.n_samples);
   const int k = blockIdx.z * 256 + threadIdx.x;
-  if (k >= T1 - T0) return;
-  const size_t first = (size_t)pa.first_item[pos] + (size_t)rir * C;
-  float v = 0.0f;
-  for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
-  out[(size_t)rir * ra.n_samples + T0 + k] = v;
+  if (k >= ra.n_samples - T0 || k >= TILE) return;
+  const int W = (int)(2.0f * ra.half_w);
+  const int LM = W / 2 - 1;
+  const bool zl = tile_id > 0 && k < W / 2;                  // right margin of tile t-1
+  const bool zr = tile_id + 1 < pa.n_tiles && k >= TILE - LM;  // left margin of tile t+1
+  if (C <= 1 && !zl && !zr) return;
+  float *o = out + (size_t)rir * ra.n_samples + T0 + k;
+  float v;
+  if (C > 1) {
+    const size_t first = (size_t)pa.first_item[pos] + (size_t)rir * C;
+    v = 0.0f;
+    for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
+  } else {
+    v = *o;
+  }
+  if (zl) {  // tile t-1 is dispatched at pos + 1
+    const int Cp = pa.chunks[tile_id - 1];
+    const size_t first = (size_t)pa.first_item[pos + 1] + (size_t)rir * Cp;
+    for (int cc = 0; cc < Cp; ++cc) v += marg[(first + cc) * W + LM + k];
+  }
+  if (zr) {  // tile t+1 is dispatched at pos - 1
+    const int Cn = pa.chunks[tile_id + 1];
+    const size_t first = (size_t)pa.first_item[pos - 1] + (size_t)rir * Cn;
+    for (int cc = 0; cc < Cn; ++cc) v += marg[(first + cc) * W + (k - (TILE - LM))];
+  }
+  *o = v;
 }
 
-// Batch mode: grid = (split tile, 256-sample segment).
+// Batch mode: grid = (output tile of a batch RIR, 256-sample segment).
 __global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restrict__ jobs,
                                                            const BatchReduce *__restrict__ red,
-                                                           const float *__restrict__ part) {
+                                                           const float *__restrict__ part,
+                                                           const float *__restrict__ marg) {
   const BatchReduce br = red[blockIdx.x];
   const JobDev &jb = jobs[br.job];
   const int n_samples = jb.ra.n_samples;
   const int T0 = (int)br.tile * TILE;
-  const int T1 = min(T0 + TILE, n_samples);
   const int k = blockIdx.y * 256 + threadIdx.x;
-  if (k >= T1 - T0) return;
-  float v = 0.0f;
-  for (int cc = 0; cc < br.chunks; ++cc) v += part[((size_t)br.first + cc) * TILE + k];
-  jb.out[(size_t)br.rir * n_samples + T0 + k] = v;
+  if (k >= n_samples - T0 || k >= TILE) return;
+  const int W = (int)(2.0f * jb.ra.half_w);
+  const int LM = W / 2 - 1;
+  const bool zl = br.nprev > 0 && k < W / 2;
+  const bool zr = br.nnext > 0 && k >= TILE - LM;
+  if (br.chunks <= 1 && !zl && !zr) return;
+  float *o = jb.out + (size_t)br.rir * n_samples + T0 + k;
+  float v;
+  if (br.chunks > 1) {
+    v = 0.0f;
+    for (int cc = 0; cc < br.chunks; ++cc) v += part[((size_t)br.first + cc) * TILE + k];
+  } else {
+    v = *o;
+  }
+  if (zl)
+    for (int cc = 0; cc < br.nprev; ++cc) v += marg[((size_t)br.mprev + cc) * MARG_STRIDE + LM + k];
+  if (zr)
+    for (int cc = 0; cc < br.nnext; ++cc) v += marg[((size_t)br.mnext + cc) * MARG_STRIDE + (k - (TILE - LM))];
+  *o = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -903,10 +976,11 @@ int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEn
 
 template <int WT, bool HALF>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
-                        const AxisOrigin *origin, const int *valid, float *out, float *part, hipStream_t st) {
+                        const AxisOrigin *origin, const int *valid, float *out, float *part, float *marg,
+                        hipStream_t st) {
   constexpr int NW = HALF ? 4 : 1;  // FP32 items run on one wave, FP16 items on four
   hipLaunchKernelGGL((accumulate_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, origin,
-                     valid, out, part);
+                     valid, out, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -914,11 +988,11 @@ bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt ==
 
 int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
                       const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
-                      hipStream_t st) {
-#define ISM_ACC(W)                                                                             \
-  case W:                                                                                      \
-    return half ? launch_acc_w<W, true>(ra, pa, n_items, tab, origin, valid, out, part, st)    \
-                : launch_acc_w<W, false>(ra, pa, n_items, tab, origin, valid, out, part, st);
+                      float *marg, hipStream_t st) {
+#define ISM_ACC(W)                                                                                 \
+  case W:                                                                                          \
+    return half ? launch_acc_w<W, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)  \
+                : launch_acc_w<W, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st);
   switch (wt) {
     ISM_ACC(32)
     ISM_ACC(64)
@@ -931,17 +1005,17 @@ int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa,
 
 template <int WT, bool HALF>
 static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
-                              const AxisOrigin *origin, const int *valid, float *part, hipStream_t st) {
+                              const AxisOrigin *origin, const int *valid, float *part, float *marg, hipStream_t st) {
   constexpr int NW = HALF ? 4 : 1;  // FP32 items run on one wave, FP16 items on four
   hipLaunchKernelGGL((accumulate_batch_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, jobs, items, tab,
-                     origin, valid, part);
+                     origin, valid, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
                  bool half, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid,
-                 float *part, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                 float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
   if (hipGetLastError() != hipSuccess) return -1;
   if (ev_start && hipEventRecord(ev_start, st) != hipSuccess) return -1;
@@ -951,8 +1025,8 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
     int rc = -2;
 #define ISM_BACC(W)                                                                                     \
   case W:                                                                                               \
-    rc = half ? launch_acc_batch_w<W, true>(jobs, it, class_count[k], tab, origin, valid, part, st)     \
-              : launch_acc_batch_w<W, false>(jobs, it, class_count[k], tab, origin, valid, part, st);   \
+    rc = half ? launch_acc_batch_w<W, true>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)   \
+              : launch_acc_batch_w<W, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st); \
     break;
     switch (class_wt[k]) {
       ISM_BACC(32)
@@ -966,16 +1040,16 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
   }
   if (ev_stop && hipEventRecord(ev_stop, st) != hipSuccess) return -1;
   if (n_red > 0) {
-    hipLaunchKernelGGL(reduce_batch_kernel, dim3(n_red, TILE / 256), dim3(256), 0, st, jobs, red, part);
+    hipLaunchKernelGGL(reduce_batch_kernel, dim3(n_red, TILE / 256), dim3(256), 0, st, jobs, red, part, marg);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;
 }
 
-int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
-                  hipStream_t st) {
+int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, const float *marg,
+                  float *out, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)n_rir, (unsigned)pa.n_tiles, TILE / 256), dim3(256), 0, st, ra,
-                     pa, part, out);
+                     pa, part, marg, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -18,14 +18,14 @@ int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEn
                   int *valid, int n_rir, hipStream_t st);
 int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
                       const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
-                      hipStream_t st);
-int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, float *out,
-                  hipStream_t st);
+                      float *marg, hipStream_t st);
+int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, const float *marg,
+                  float *out, hipStream_t st);
 bool supported_window(int wt);
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
                  bool half, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid,
-                 float *part, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
+                 float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 }  // namespace ism
 
 using namespace ism;
@@ -66,7 +66,7 @@ struct Plan {
   int n_rir;
   uint32_t n_items;
   bool any_split;
-  size_t off_valid, off_origin, off_tab, off_part, ws_bytes;
+  size_t off_valid, off_origin, off_tab, off_part, off_marg, ws_bytes;
 };
 
 int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
@@ -102,15 +102,18 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   ra.two_pi_over_w = (float)(2.0 * kPi / W);
   ra.half_w = (float)(W / 2.0);
   ra.n_samples = (int)nS;
+  ra.k_end = (int)nS + p.wt / 2 - 1;
   ra.n_src = n_src;
   ra.n_rcv = n_rcv;
 
-  // Work split: estimated taps of a tile's image shell from the shell volume
-  // over the image density 1 / (Lx Ly Lz) (one image per mirrored room copy).
+  // Work split: tile t owns the images with k0 in [t TILE, min((t+1) TILE, k_end));
+  // its estimated taps are the owned shell volume over the image density
+  // 1 / (Lx Ly Lz) (one image per mirrored room copy), times W.
   p.n_rir = n_src * n_rcv;
   PlanArgs &pa = p.pa;
   std::memset(&pa, 0, sizeof(pa));
-  pa.n_tiles = (int)((nS + TILE - 1) / TILE);
+  pa.n_tiles = (ra.k_end + TILE - 1) / TILE;
+  if (pa.n_tiles > MAX_TILES) return ISM_E_TOO_LARGE;
   pa.n_rir = p.n_rir;
   const double cell = r->room[0] * r->room[1] * r->room[2] * q * q * q;
   const double lattice = (double)r->n_img[0] * r->n_img[1] * r->n_img[2];
@@ -120,8 +123,7 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   if (const char *e = std::getenv("ISM_TARGET_TAPS")) target = std::max(1e3, std::atof(e));
   p.any_split = false;
   for (int t = 0; t < pa.n_tiles; ++t) {
-    const double T0 = (double)t * TILE, T1 = std::min((double)(t + 1) * TILE, (double)nS);
-    const double x1 = T1 + W / 2.0, x0 = std::max(T0 - W / 2.0, 0.0);
+    const double x0 = (double)t * TILE, x1 = std::min((double)(t + 1) * TILE, (double)ra.k_end);
     const double imgs = std::min(4.0 / 3.0 * kPi * (x1 * x1 * x1 - x0 * x0 * x0) / cell, lattice);
     const double taps = imgs * W;
     p.tile_taps[t] = taps;
@@ -143,7 +145,8 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   p.off_origin = align_up(sizeof(int) * (size_t)p.n_rir);
   p.off_tab = align_up(p.off_origin + sizeof(AxisOrigin) * (size_t)p.n_rir);
   p.off_part = align_up(p.off_tab + sizeof(AxisEntry) * (size_t)p.n_rir * ra.n_tab);
-  p.ws_bytes = p.off_part + (p.any_split ? sizeof(float) * (size_t)p.n_items * TILE : 0);
+  p.off_marg = align_up(p.off_part + (p.any_split ? sizeof(float) * (size_t)p.n_items * TILE : 0));
+  p.ws_bytes = p.off_marg + sizeof(float) * (size_t)p.n_items * p.wt;
   return ISM_OK;
 }
 
@@ -320,12 +323,15 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
   AxisOrigin *origin = (AxisOrigin *)(w + p.off_origin);
   AxisEntry *tab = (AxisEntry *)(w + p.off_tab);
   float *part = p.any_split ? (float *)(w + p.off_part) : nullptr;
+  float *marg = (float *)(w + p.off_marg);
   if (launch_tables(p.ra, src, rcv, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, s) != hipSuccess) return ISM_E_DEVICE;
-  if (launch_accumulate(p.wt, p.half, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, s) != 0)
+  if (launch_accumulate(p.wt, p.half, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, marg, s) != 0)
     return ISM_E_DEVICE;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
-  if (p.any_split && launch_reduce(p.ra, p.pa, p.n_rir, part, out, s) != 0) return ISM_E_DEVICE;
+  // split tiles and the margins between neighbouring tiles
+  if ((p.any_split || p.pa.n_tiles > 1) && launch_reduce(p.ra, p.pa, p.n_rir, part, marg, out, s) != 0)
+    return ISM_E_DEVICE;
   return ISM_OK;
 }
 
@@ -337,7 +343,7 @@ constexpr int kMaxClasses = 4;
 
 struct BatchState {  // stored in ism_batch::opaque
   uint64_t ws;
-  uint64_t off_jobs, off_rirs, off_items, off_red, off_valid, off_origin, off_tab, off_part;
+  uint64_t off_jobs, off_rirs, off_items, off_red, off_valid, off_origin, off_tab, off_part, off_marg;
   uint32_t n_rir, n_red, n_classes, half;
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
   int32_t class_wt[kMaxClasses];
@@ -365,6 +371,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
   std::vector<Cand> cand;
   uint64_t tab_entries = 0, n_rir = 0;
   uint32_t slots = 0;
+  uint64_t mslots = 0;
   int n_classes = 0;
   int class_wt[kMaxClasses] = {0, 0, 0, 0};
   for (int j = 0; j < n_jobs; ++j) {
@@ -390,17 +397,39 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
     d.tab_base = tab_entries;
     d.rir_base = (uint32_t)n_rir;
     for (int r = 0; r < p.n_rir; ++r) bp.rirs.push_back(BatchRir{(uint32_t)j, (uint32_t)r});
-    for (int t = 0; t < p.pa.n_tiles; ++t) {
+    // margin records of (tile t, RIR r): mfirst[t * n_rir + r] .. + chunks[t] - 1
+    const int nt = p.pa.n_tiles;
+    std::vector<uint64_t> mfirst((size_t)nt * p.n_rir);
+    for (int t = 0; t < nt; ++t)
+      for (int r = 0; r < p.n_rir; ++r) {
+        mfirst[(size_t)t * p.n_rir + r] = mslots;
+        mslots += p.pa.chunks[t];
+      }
+    if (mslots > 0xffffffffULL) return ISM_E_TOO_LARGE;
+    for (int t = 0; t < nt; ++t) {
       const int C = p.pa.chunks[t];
       for (int r = 0; r < p.n_rir; ++r) {
-        const uint32_t first = slots;
-        if (C > 1) {
-          bp.red.push_back(BatchReduce{(uint32_t)j, (uint32_t)r, (uint16_t)t, (uint16_t)C, first});
-          slots += (uint32_t)C;
+        const uint32_t first = C > 1 ? slots : 0xffffffffu;
+        BatchReduce rd{};
+        rd.job = (uint32_t)j;
+        rd.rir = (uint32_t)r;
+        rd.tile = (uint16_t)t;
+        rd.chunks = (uint16_t)C;
+        rd.first = first;
+        if (t > 0) {
+          rd.mprev = (uint32_t)mfirst[(size_t)(t - 1) * p.n_rir + r];
+          rd.nprev = p.pa.chunks[t - 1];
         }
+        if (t + 1 < nt) {
+          rd.mnext = (uint32_t)mfirst[(size_t)(t + 1) * p.n_rir + r];
+          rd.nnext = p.pa.chunks[t + 1];
+        }
+        bp.red.push_back(rd);
+        if (C > 1) slots += (uint32_t)C;
         for (int c = 0; c < C; ++c) {
           BatchItem it{(uint32_t)j, (uint32_t)r, (uint16_t)t, (uint8_t)c, (uint8_t)C,
-                       C > 1 ? first + (uint32_t)c : 0xffffffffu};
+                       C > 1 ? first + (uint32_t)c : 0xffffffffu,
+                       (uint32_t)(mfirst[(size_t)t * p.n_rir + r] + c)};
           cand.push_back(Cand{p.tile_taps[t] / C, cls, it});
         }
       }
@@ -446,6 +475,8 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
   o = align_up(o + sizeof(AxisEntry) * tab_entries);
   bp.st.off_part = o;
   o = align_up(o + sizeof(float) * (size_t)slots * TILE);
+  bp.st.off_marg = o;
+  o = align_up(o + sizeof(float) * (size_t)mslots * MARG_STRIDE);
   bp.ws_bytes = o;
   return ISM_OK;
 }
@@ -495,7 +526,8 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
                               (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_wt,
                               (int)b.n_classes, b.half != 0, (const BatchReduce *)(w + b.off_red), b.n_red,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
-                              (int *)(w + b.off_valid), (float *)(w + b.off_part), (hipStream_t)stream,
+                              (int *)(w + b.off_valid), (float *)(w + b.off_part), (float *)(w + b.off_marg),
+                              (hipStream_t)stream,
                               (hipEvent_t)ev_start, (hipEvent_t)ev_stop);
   return rc == 0 ? ISM_OK : ISM_E_DEVICE;
 }

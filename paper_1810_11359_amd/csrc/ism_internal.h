@@ -6,10 +6,15 @@
 
 namespace ism {
 
-// Output tile handled by one work item: TILE consecutive samples of one RIR.
+// Tiles partition the integer delays k0 = floor(x) of the images: tile t owns
+// the images with k0 in [t*TILE, (t+1)*TILE) and writes output samples
+// [t*TILE, (t+1)*TILE) plus two margins, the W/2 - 1 samples before and the
+// W/2 samples after, which belong to the neighbouring tiles.
 constexpr int TILE = 1024;
-// Most tiles per RIR (ISM_MAX_SAMPLES / TILE).
-constexpr int MAX_TILES = 256;
+// Most tiles per RIR: ceil((ISM_MAX_SAMPLES + 128/2 - 1) / TILE).
+constexpr int MAX_TILES = 257;
+// Stride of one work item's margin record in batch mode (the largest window).
+constexpr int MARG_STRIDE = 128;
 // Work items per tile are capped so the per-tile chunk count fits a byte.
 constexpr int MAX_CHUNKS = 255;
 
@@ -28,14 +33,15 @@ struct RoomArgs {
   float two_pi_over_w;     // 2 pi / W
   float half_w;            // W / 2
   int n_samples;           // nS
+  int k_end;               // nS + W/2 - 1: images with k0 >= k_end add nothing
   int n_src, n_rcv;
   float period[3];         // 2 L q: displacement step between images of one parity [samples]
   float inv_period[3];     // 1 / period
 };
 
 // Work decomposition of one call. Items are ordered by tile (last tile first,
-// where the images are densest), then by RIR, then by chunk. Tile t owns
-// samples [t*TILE, min((t+1)*TILE, nS)); its image shell is split into
+// where the images are densest), then by RIR, then by chunk. Tile t owns the
+// images with k0 in [t*TILE, min((t+1)*TILE, k_end)); that shell is split into
 // chunks[t] slabs along the x displacement.
 struct PlanArgs {
   int n_tiles;
@@ -75,19 +81,26 @@ struct BatchRir {
 };
 
 // One work item of a batch (same meaning as in single-room mode). slot is the
-// partial tile written when the tile is split (chunks > 1), else 0xffffffff.
+// partial tile written when the tile is split (chunks > 1), else 0xffffffff;
+// mslot is its margin record (MARG_STRIDE floats).
 struct BatchItem {
   uint32_t job, rir;
   uint16_t tile;
   uint8_t chunk, chunks;
   uint32_t slot;
+  uint32_t mslot;
 };
 
-// One split tile of a batch: its partials occupy slots first .. first+chunks-1.
+// One output tile of a batch RIR: its own partials (slots first ..
+// first + chunks - 1 when chunks > 1) and the margin records of the items of
+// the previous and next tile (mprev .. mprev + nprev - 1, mnext .. mnext + nnext - 1;
+// counts are 0 where there is no such tile).
 struct BatchReduce {
   uint32_t job, rir;
   uint16_t tile, chunks;
   uint32_t first;
+  uint32_t mprev, mnext;
+  uint16_t nprev, nnext;
 };
 
 }  // namespace ism
