@@ -10,9 +10,9 @@ namespace ism {
 // the images with k0 in [t*TILE, (t+1)*TILE) and writes output samples
 // [t*TILE, (t+1)*TILE) plus two margins, the W/2 - 1 samples before and the
 // W/2 samples after, which belong to the neighbouring tiles.
-constexpr int TILE = 1024;
+constexpr int TILE = 512;
 // Most tiles per RIR: ceil((ISM_MAX_SAMPLES + 128/2 - 1) / TILE).
-constexpr int MAX_TILES = 257;
+constexpr int MAX_TILES = 513;
 // Stride of one work item's margin record in batch mode (the largest window).
 constexpr int MARG_STRIDE = 128;
 // Work items per tile are capped so the per-tile chunk count fits a byte.
