@@ -156,7 +156,11 @@ def test_repeatable_and_split_invariant(monkeypatch):
     assert np.array_equal(a, b)  # fixed summation order: bitwise reproducible
     monkeypatch.setenv("ISM_TARGET_TAPS", "20000")  # many more work items per tile
     c = _gpu_rir(room, w.src, w.rcv[:8])
-    assert np.all(np.max(np.abs(a - c), axis=-1) <= 2e-7 * peak)
+    # Another split only reorders the FP32 sums: a late sample adds ~1e4 taps of
+    # up to ~0.1 peak each, so reordering moves it by a few ulps of such terms
+    # (~1e-7 of the peak). 1e-6 bounds that with margin, 10x inside the parity
+    # tolerance.
+    assert np.all(np.max(np.abs(a - c), axis=-1) <= 1e-6 * peak)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
