@@ -626,16 +626,26 @@ __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const i
   for (int i = lane; i < 2 * LSPAN; i += 64) (&tile[0][0])[i] = 0.0f;
   float *const th = &tile[h][l];
 
-  // One step: staged image (P, b) on this half-wave, taps l + 32 m.
+  // One step: staged image (P, b) on this half-wave, taps l + 32 m. When W/32
+  // is even, tap m + TPL/2 sits half a window period after tap m, where the
+  // Hann term flips sign: its numerator is 2 (C/2) - w_m.
   auto step = [&](const float4 P, const int b) {
     float *t = th + b;
+    float w[TPL];
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+      if (TPL % 2 == 0 && m >= TPL / 2) {
+        w[m] = __builtin_fmaf(2.0f, P.w, -w[m - TPL / 2]);
+      } else {
+        w[m] = __builtin_fmaf(cth[m], P.y, P.w);
+        w[m] = __builtin_fmaf(sth[m], P.z, w[m]);
+      }
+    }
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
       const float u = __builtin_fmaf(nsg[m], P.x, sgj[m]);
       const float r = __builtin_amdgcn_rcpf(u);
-      float w = __builtin_fmaf(cth[m], P.y, P.w);
-      w = __builtin_fmaf(sth[m], P.z, w);
-      t[32 * m] = __builtin_fmaf(w, r, t[32 * m]);
+      t[32 * m] = __builtin_fmaf(w[m], r, t[32 * m]);
     }
   };
 
