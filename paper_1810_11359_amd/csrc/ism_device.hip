@@ -846,27 +846,42 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     accumulate_item_taps<WT>(ra, tile_id, C, c, tab, org, valid, dst, marg);
 }
 
+// First work item of dispatch position pos (see PlanArgs).
+__device__ __forceinline__ uint32_t plan_first_item(const PlanArgs &pa, int pos) {
+  uint32_t f = pa.first_blk[pos / PLAN_BLK];
+  for (int p = pos - pos % PLAN_BLK; p < pos; ++p) f += (uint32_t)pa.n_rir * pa.chunks[pa.n_tiles - 1 - p];
+  return f;
+}
+
 // Single-room launch: the item index decodes through the per-tile chunk counts.
 template <int WT, int NW, bool HALF>
-__global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 1 ? 6 : 1))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
                                                              const int *__restrict__ valid, float *__restrict__ out,
                                                              float *__restrict__ part, float *__restrict__ marg) {
   const uint32_t item = blockIdx.x;
-  int pos = 0;
-  {
-    int lo = 0, hi = pa.n_tiles;  // largest pos with first_item[pos] <= item
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (pa.first_item[mid] <= item) lo = mid;
-      else hi = mid;
-    }
-    pos = lo;
+  // largest dispatch position pos whose first item is <= item: the block by
+  // binary search over first_blk, then the position within the block
+  const int nblk = (pa.n_tiles + PLAN_BLK - 1) / PLAN_BLK;
+  int lo = 0, hi = nblk;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pa.first_blk[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  int pos = lo * PLAN_BLK;
+  uint32_t first = pa.first_blk[lo];
+  const int pend = min(pa.n_tiles, pos + PLAN_BLK);
+  for (;;) {
+    const uint32_t next = first + (uint32_t)pa.n_rir * pa.chunks[pa.n_tiles - 1 - pos];
+    if (pos + 1 >= pend || next > item) break;
+    first = next;
+    ++pos;
   }
   const int tile_id = pa.n_tiles - 1 - pos;
   const int C = pa.chunks[tile_id];
-  const uint32_t rel = item - pa.first_item[pos];
+  const uint32_t rel = item - first;
   const int rir = (int)(rel / (uint32_t)C);
   const int c = (int)(rel % (uint32_t)C);
   // (for a tile past nS, dst is never written: the tile has no own samples)
@@ -878,7 +893,7 @@ __global__ __launch_bounds__(NW * 64) void accumulate_kernel(RoomArgs ra, PlanAr
 
 // Batch launch: every item names its job; the job table carries the room.
 template <int WT, int NW, bool HALF>
-__global__ __launch_bounds__(NW * 64) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 1 ? 6 : 1))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
                                                                    const AxisOrigin *__restrict__ origin,
@@ -921,7 +936,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, c
   float *o = out + (size_t)rir * ra.n_samples + T0 + k;
   float v;
   if (C > 1) {
-    const size_t first = (size_t)pa.first_item[pos] + (size_t)rir * C;
+    const size_t first = (size_t)plan_first_item(pa, pos) + (size_t)rir * C;
     v = 0.0f;
     for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
   } else {
@@ -929,12 +944,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, c
   }
   if (zl) {  // tile t-1 is dispatched at pos + 1
     const int Cp = pa.chunks[tile_id - 1];
-    const size_t first = (size_t)pa.first_item[pos + 1] + (size_t)rir * Cp;
+    const size_t first = (size_t)plan_first_item(pa, pos + 1) + (size_t)rir * Cp;
     for (int cc = 0; cc < Cp; ++cc) v += marg[(first + cc) * W + LM + k];
   }
   if (zr) {  // tile t+1 is dispatched at pos - 1
     const int Cn = pa.chunks[tile_id + 1];
-    const size_t first = (size_t)pa.first_item[pos - 1] + (size_t)rir * Cn;
+    const size_t first = (size_t)plan_first_item(pa, pos - 1) + (size_t)rir * Cn;
     for (int cc = 0; cc < Cn; ++cc) v += marg[(first + cc) * W + (k - (TILE - LM))];
   }
   *o = v;

@@ -134,11 +134,11 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   }
   uint64_t acc = 0;
   for (int pos = 0; pos < pa.n_tiles; ++pos) {
-    pa.first_item[pos] = (uint32_t)acc;
+    if (pos % PLAN_BLK == 0) pa.first_blk[pos / PLAN_BLK] = (uint32_t)acc;
     acc += (uint64_t)p.n_rir * pa.chunks[pa.n_tiles - 1 - pos];
     if (acc > 0x7fffffffULL) return ISM_E_TOO_LARGE;
   }
-  pa.first_item[pa.n_tiles] = (uint32_t)acc;
+  pa.first_blk[(pa.n_tiles + PLAN_BLK - 1) / PLAN_BLK] = (uint32_t)acc;
   p.n_items = (uint32_t)acc;
 
   p.off_valid = 0;

@@ -10,9 +10,11 @@ namespace ism {
 // the images with k0 in [t*TILE, (t+1)*TILE) and writes output samples
 // [t*TILE, (t+1)*TILE) plus two margins, the W/2 - 1 samples before and the
 // W/2 samples after, which belong to the neighbouring tiles.
-constexpr int TILE = 512;
+constexpr int TILE = 256;
 // Most tiles per RIR: ceil((ISM_MAX_SAMPLES + 128/2 - 1) / TILE).
-constexpr int MAX_TILES = 513;
+constexpr int MAX_TILES = 1025;
+// Dispatch positions per block of the plan's coarse first-item table.
+constexpr int PLAN_BLK = 16;
 // Stride of one work item's margin record in batch mode (the largest window).
 constexpr int MARG_STRIDE = 128;
 // Work items per tile are capped so the per-tile chunk count fits a byte.
@@ -43,11 +45,14 @@ struct RoomArgs {
 // where the images are densest), then by RIR, then by chunk. Tile t owns the
 // images with k0 in [t*TILE, min((t+1)*TILE, k_end)); that shell is split into
 // chunks[t] slabs along the x displacement.
+// The first item of dispatch position pos (tile n_tiles - 1 - pos) is
+// first_blk[pos / PLAN_BLK] plus n_rir * chunks of the positions before pos in
+// its block (plan_first_item); the compact form keeps the plan a kernel argument.
 struct PlanArgs {
   int n_tiles;
   int n_rir;
-  uint32_t first_item[MAX_TILES + 1];  // index of the first item of tile t (dispatch order)
-  uint8_t chunks[MAX_TILES];           // chunks per tile
+  uint32_t first_blk[(MAX_TILES + PLAN_BLK) / PLAN_BLK + 1];
+  uint8_t chunks[MAX_TILES];  // chunks per tile (by tile index)
 };
 
 // Per-RIR table entry for one lattice index of one axis: displacement from
