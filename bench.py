@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,10 @@ if ROOT not in sys.path:
 METRIC = "image-source sinc taps/s (G/s) + RIRs/s, FP32 vs FP16; p50/p99 serving latency"
 FLOP_PER_TAP = 18          # frozen accounting of one windowed-sinc tap
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 FLOP/clk)
+# rocprofv3 summaries holding the calibrated HBM traffic of the timed kernel,
+# valid while the kernel sources hash to the value recorded beside it
+TRAFFIC_PROFILES = {"room_32_receivers": "profiles/accumulate_kernel_room_4x5x3_32rcv.md"}
+KERNEL_SOURCES = ("ism_device.hip", "ism_host.cpp", "ism_internal.h")
 
 
 class _HipEvents:
@@ -52,6 +57,32 @@ class _HipEvents:
 
     def destroy(self, ev):
         self.hip.hipEventDestroy(ctypes.c_void_p(ev))
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_11359_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per launch of the accumulate kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    none for this workload or the kernel sources changed since it was taken."""
+    rel = TRAFFIC_PROFILES.get(workload) if precision == "fp32" else None
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    vals = {}
+    with open(os.path.join(ROOT, rel)) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_sources_sha256"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def _oracle_args(orc, w):
@@ -201,6 +232,7 @@ def main() -> int:
     value = taps / (ms_step / 1e3) / 1e9
     kmean = float(np.mean(kern_ms))
     achieved = FLOP_PER_TAP * taps / (kmean / 1e3) / 1e12
+    traffic = measured_traffic(args.workload, args.precision)
     out = {
         "metric": METRIC,
         "value": value,
@@ -218,7 +250,8 @@ def main() -> int:
         "rirs_per_s": n_rir / (ms_step / 1e3),
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                     "frac": achieved / FP32_VECTOR_PEAK, "traffic": traffic,
+                     "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "accumulate_kernel" if args.workload != "batch_rooms" else "accumulate_batch_kernel",
                      "kernel_ms_mean": kmean,
                      "kernel_ms_p50": float(np.median(kern_ms)), "flop_per_tap": FLOP_PER_TAP},
