@@ -119,52 +119,56 @@ constexpr TapConsts<WT> make_tap_consts() {
   return t;
 }
 
-// FP16 taps. Away from the centre (j <= -2 or j >= 3) the tap of an image is
-// C g_j(t) with t = f - 1/2 in [-1/2, 1/2) and
-//   g_j = (1 + cos(2 pi (j - f) / W)) sigma_j / (2 (j - f)),
-// which is analytic on the interval (its nearest pole is 2.5 away in t). Each
-// g_j is replaced by its cubic interpolant at the four Chebyshev nodes of
-// [-1/2, 1/2] (interpolation error < 2e-4 of max|g_j|), evaluated in packed
-// FP16 two taps at a time. The four central taps keep the exact FP32 form.
-constexpr bool poly_tap(int j) { return j <= -2 || j >= 3; }
-
+// FP16 taps. For one image with fractional delay f, tap j (Eq. (6) at
+// v = j - f) is A s_j(t) with t = f - 1/2 in [-1/2, 1/2) and
+//   s_j(t) = sinc(j - f) (1 + cos(2 pi (j - f) / W)) / 2,
+// an entire function of t. Each s_j is replaced by its interpolant of degree
+// SPD at the Chebyshev nodes of [-1/2, 1/2] (interpolation error < 6e-5),
+// written as c0 + t q(t), q = c1 + c2 t + ... + c5 t^4. A tap then adds
+// A c0 in FP32 and q(t) (A t), with q evaluated in packed FP16 (two taps per
+// register) and the product and sum in FP32. FP16 rounding of q and t bounds
+// the tap error by ~6e-4 A at the central taps and ~2.5e-4 A elsewhere.
+constexpr int SPD = 5;
 template <int WT>
-struct PolyConsts {
-  float c[4][WT];  // monomial coefficients in t, rounded to FP16 where used
+struct SincPoly {
+  float c[SPD + 1][WT];  // c[k][jj] multiplies t^k for tap j = jj + 1 - W/2
 };
-constexpr double g_tap(int j, double t, int wt) {
-  const double v = j - (t + 0.5);
-  const double sg = (j % 2 == 0) ? -1.0 : 1.0;
-  return (1.0 + cx_cos(2.0 * kPi * v / wt)) * sg / (2.0 * v);
+constexpr double s_tap(int j, double t, int wt) {
+  const double f = t + 0.5;  // in (0, 1) at the nodes, so j - f != 0
+  const double v = j - f;
+  const double sg = (j % 2 == 0) ? -1.0 : 1.0;  // sin(pi v) = sg sin(pi f)
+  return sg * cx_sin(kPi * f) / (kPi * v) * 0.5 * (1.0 + cx_cos(2.0 * kPi * v / wt));
 }
 template <int WT>
-constexpr PolyConsts<WT> make_poly_consts() {
-  PolyConsts<WT> P{};
+constexpr SincPoly<WT> make_sinc_poly() {
+  constexpr int NP = SPD + 1;
+  SincPoly<WT> P{};
   for (int jj = 0; jj < WT; ++jj) {
     const int j = jj + 1 - WT / 2;
-    if (!poly_tap(j)) continue;
-    double x[4] = {}, y[4] = {};
-    for (int k = 0; k < 4; ++k) {
-      x[k] = 0.5 * cx_cos((2.0 * k + 1.0) * kPi / 8.0);
-      y[k] = g_tap(j, x[k], WT);
+    double x[NP] = {}, y[NP] = {};
+    for (int k = 0; k < NP; ++k) {
+      x[k] = 0.5 * cx_cos((2.0 * k + 1.0) * kPi / (2.0 * NP));
+      y[k] = s_tap(j, x[k], WT);
     }
     // Newton divided differences, then expansion to monomials
-    double d[4] = {y[0], y[1], y[2], y[3]};
-    for (int lvl = 1; lvl < 4; ++lvl)
-      for (int k = 3; k >= lvl; --k) d[k] = (d[k] - d[k - 1]) / (x[k] - x[k - lvl]);
-    double m[4] = {d[3], 0.0, 0.0, 0.0};  // coefficients of the running polynomial, highest first
+    double d[NP] = {};
+    for (int k = 0; k < NP; ++k) d[k] = y[k];
+    for (int lvl = 1; lvl < NP; ++lvl)
+      for (int k = NP - 1; k >= lvl; --k) d[k] = (d[k] - d[k - 1]) / (x[k] - x[k - lvl]);
+    double m[NP] = {};  // coefficients of the running polynomial, highest first
+    m[0] = d[NP - 1];
     int deg = 0;
-    for (int k = 2; k >= 0; --k) {  // m(t) = m(t) * (t - x[k]) + d[k]
-      double nm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = NP - 2; k >= 0; --k) {  // m(t) = m(t) * (t - x[k]) + d[k]
+      double nm[NP] = {};
       for (int q = 0; q <= deg; ++q) {
         nm[q] += m[q];
         nm[q + 1] -= m[q] * x[k];
       }
       ++deg;
       nm[deg] += d[k];
-      for (int q = 0; q < 4; ++q) m[q] = nm[q];
+      for (int q = 0; q < NP; ++q) m[q] = nm[q];
     }
-    for (int q = 0; q < 4; ++q) P.c[3 - q][jj] = (float)m[q];  // c[k] multiplies t^k
+    for (int q = 0; q < NP; ++q) P.c[SPD - q][jj] = (float)m[q];
   }
   return P;
 }
@@ -404,13 +408,11 @@ __device__ __forceinline__ ItemGeom item_geom(const RoomArgs &ra, const AxisRang
 
 // Walks the shell of the item. For every filled queue chunk (entries
 // [0, qn) of es.queue, with the column data of the current batch in es.col_*)
-// calls consume(qn), which must use up all qn entries. Waves of a block take
-// column batches round-robin (wave = 0..NW-1).
-template <int NW, class Consume>
+// calls consume(qn), which must use up all qn entries.
+template <class Consume>
 __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEntry *__restrict__ tx,
                                                 const AxisEntry *__restrict__ ty, const AxisRange &ay,
-                                                const AxisRange &az, EnumLds &es, const int wave,
-                                                Consume &&consume) {
+                                                const AxisRange &az, EnumLds &es, Consume &&consume) {
   const int lane = threadIdx.x & 63;
   for (int nx0 = g.nx_a; nx0 < g.nx_b; nx0 += 64) {
     // lanes = x indices: y range of the columns that reach the outer sphere
@@ -433,7 +435,7 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
     es.nx_nylo[lane] = ny_lo;
     wave_sync();
 
-    for (int cb = wave; cb * 64 < ncols; cb += NW) {
+    for (int cb = 0; cb * 64 < ncols; ++cb) {
       // lanes = columns (nx, ny): z ranges of the shell
       const int gcol = cb * 64 + lane;
       int z1 = 0, n1 = 0, z2 = 0, n2 = 0;
@@ -495,15 +497,22 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
   }
 }
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 // Parameters of one image candidate (queue entry ent). ok is false when the
 // tile does not own the image. base = k0 - T0 is the tile-local LDS index of its
-// tap j = 1 - W/2 (the LDS tile starts at sample T0 + 1 - W/2).
+// tap j = 1 - W/2 (the LDS tile starts at sample T0 + 1 - W/2). rec is the
+// staged record of the taps:
+//   FP32: (f, CP, CQ, C/2) with C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W),
+//         CQ = C/2 sin(2 pi f/W);
+//   FP16: (t, t) in packed FP16 with t = f - 1/2, A, A t, base.
 struct ImageParams {
   bool ok;
   int base;
-  float f, C2, CP, CQ;
+  f4v rec;
 };
-template <int WT>
+template <int WT, bool HALF>
 __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const ItemGeom &g, const EnumLds &es,
                                                     const AxisEntry ez, uint32_t ent) {
   ImageParams p;
@@ -530,18 +539,23 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
   p.ok = (x0 < 1.0e9f) && (uint32_t)p.base < (uint32_t)(g.K1 - g.T0);
   // Eq. (4) amplitude and the per-image factors of the taps
   const float A = es.col_g[cl] * ez.gain * ra.kappa * rx;
-  p.f = fmaxf(fr, 0x1p-100f);
-  const float Cc = A * sinpi_over_pi(fminf(p.f, 1.0f - p.f));
-  float sp, cp;
-  small_sincos(p.f * ra.two_pi_over_w, sp, cp);
-  p.C2 = 0.5f * Cc;
-  p.CP = p.C2 * cp;
-  p.CQ = p.C2 * sp;
+  if constexpr (HALF) {
+    const float t = fr - 0.5f;
+    const half2_t th = {(_Float16)t, (_Float16)t};
+    p.rec = f4v{__builtin_bit_cast(float, th), A, A * t, __int_as_float(p.base)};
+  } else {
+    const float f = fmaxf(fr, 0x1p-100f);
+    const float Cc = A * sinpi_over_pi(fminf(f, 1.0f - f));
+    float sp, cp;
+    small_sincos(f * ra.two_pi_over_w, sp, cp);
+    const float C2 = 0.5f * Cc;
+    p.rec = f4v{f, C2 * cp, C2 * sp, C2};
+  }
   return p;
 }
 
-// Tap constants of the FP32 consumer, lane l of a half-wave holds taps
-// j = 1 - W/2 + l + 32 m, m = 0 .. W/32 - 1 (index jj = l + 32 m).
+// Per-tap constants, lane l of a half-wave holds taps j = 1 - W/2 + l + 32 m,
+// m = 0 .. W/32 - 1 (index jj = l + 32 m).
 __constant__ TapConsts<32> kTap32 = make_tap_consts<32>();
 __constant__ TapConsts<64> kTap64 = make_tap_consts<64>();
 __constant__ TapConsts<96> kTap96 = make_tap_consts<96>();
@@ -551,6 +565,15 @@ template <> __device__ __forceinline__ const TapConsts<32> &tap_table<32>() { re
 template <> __device__ __forceinline__ const TapConsts<64> &tap_table<64>() { return kTap64; }
 template <> __device__ __forceinline__ const TapConsts<96> &tap_table<96>() { return kTap96; }
 template <> __device__ __forceinline__ const TapConsts<128> &tap_table<128>() { return kTap128; }
+__constant__ SincPoly<32> kPoly32 = make_sinc_poly<32>();
+__constant__ SincPoly<64> kPoly64 = make_sinc_poly<64>();
+__constant__ SincPoly<96> kPoly96 = make_sinc_poly<96>();
+__constant__ SincPoly<128> kPoly128 = make_sinc_poly<128>();
+template <int WT> __device__ __forceinline__ const SincPoly<WT> &poly_table();
+template <> __device__ __forceinline__ const SincPoly<32> &poly_table<32>() { return kPoly32; }
+template <> __device__ __forceinline__ const SincPoly<64> &poly_table<64>() { return kPoly64; }
+template <> __device__ __forceinline__ const SincPoly<96> &poly_table<96>() { return kPoly96; }
+template <> __device__ __forceinline__ const SincPoly<128> &poly_table<128>() { return kPoly128; }
 
 constexpr int SCAP = 68;  // staged images: up to 64 new + 1 carried, + read-ahead slots
 
@@ -582,19 +605,20 @@ __device__ __forceinline__ void write_invalid(int n_own, float *__restrict__ dst
   for (int i = tid; i < WT - 1; i += nthreads) marg[i] = __builtin_nanf("");
 }
 
-// FP32 work item, one wave (lanes = taps). dst receives the T1 - T0 own
-// samples of the tile (or a partial tile when C > 1), marg the margins.
-template <int WT>
-__device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const int tile_id, const int C, const int c,
-                                                     const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                     const bool valid, float *__restrict__ dst,
-                                                     float *__restrict__ marg) {
+// One work item on one wave (lanes = taps). dst receives the own samples of
+// the tile (or a partial tile when C > 1), marg the margins. HALF selects the
+// FP16 tap arithmetic; accumulation is FP32 in both.
+template <int WT, bool HALF>
+__device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
+                                                const AxisEntry *__restrict__ tab, const AxisOrigin &org,
+                                                const bool valid, float *__restrict__ dst, float *__restrict__ marg) {
   constexpr int LSPAN = TILE + WT - 1;
-  constexpr int TPL = WT / 32;
+  constexpr int TPL = WT / 32;         // taps per lane per step
+  constexpr int NPAIR = (TPL + 1) / 2;  // packed FP16 tap pairs per lane
 
   __shared__ float tile[2][LSPAN];
-  __shared__ float4 stp[SCAP];  // f, CP, CQ, C2 of staged images
-  __shared__ int stb[SCAP];     // their bases
+  __shared__ f4v stp[SCAP];             // staged records (ImageParams::rec)
+  __shared__ int stb[HALF ? 1 : SCAP];  // FP32: their bases (FP16 records carry the base)
   __shared__ EnumLds es;
 
   const int lane = threadIdx.x & 63;
@@ -612,8 +636,24 @@ __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const i
   const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
   const ItemGeom g = item_geom(ra, ax, tile_id, C, c);
 
-  float nsg[TPL], sgj[TPL], cth[TPL], sth[TPL];
-  {
+  // per-lane tap constants
+  float nsg[TPL], sgj[TPL], cth[TPL], sth[TPL];  // FP32 taps
+  float pc0[TPL];                                // FP16 taps: c0 of each tap
+  half2_t pq[NPAIR][SPD];                        // and c1..c5 of tap pairs (2p, 2p + 1)
+  if constexpr (HALF) {
+    const SincPoly<WT> &P = poly_table<WT>();
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) pc0[m] = P.c[0][l + 32 * m];
+#pragma unroll
+    for (int pr = 0; pr < NPAIR; ++pr)
+#pragma unroll
+      for (int k = 0; k < SPD; ++k) {
+        const int m0 = 2 * pr, m1 = 2 * pr + 1;
+        const float a = P.c[k + 1][l + 32 * m0];
+        const float b = m1 < TPL ? P.c[k + 1][l + 32 * m1] : 0.0f;
+        pq[pr][k] = half2_t{(_Float16)a, (_Float16)b};
+      }
+  } else {
     const TapConsts<WT> &K = tap_table<WT>();
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
@@ -626,31 +666,56 @@ __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const i
   for (int i = lane; i < 2 * LSPAN; i += 64) (&tile[0][0])[i] = 0.0f;
   float *const th = &tile[h][l];
 
-  // One step: staged image (P, b) on this half-wave, taps l + 32 m. When W/32
-  // is even, tap m + TPL/2 sits half a window period after tap m, where the
-  // Hann term flips sign: its numerator is 2 (C/2) - w_m.
-  auto step = [&](const float4 P, const int b) {
+  // One step: staged image (record P, base b) on this half-wave, taps l + 32 m.
+  // The empty asm consumes the record as one 128-bit value where the step
+  // starts, which keeps its LDS read a single ds_read_b128 issued ahead.
+  auto step = [&](const f4v P, const int b) {
+    __asm__ volatile("" ::"v"(P));
     float *t = th + b;
-    float w[TPL];
+    if constexpr (HALF) {
+      // tap = A c0 + (A t) q(t), q in packed FP16 two taps at a time
+      const half2_t tt = __builtin_bit_cast(half2_t, P.x);
+      const float A = P.y, At = P.z;
 #pragma unroll
-    for (int m = 0; m < TPL; ++m) {
-      if (TPL % 2 == 0 && m >= TPL / 2) {
-        w[m] = __builtin_fmaf(2.0f, P.w, -w[m - TPL / 2]);
-      } else {
-        w[m] = __builtin_fmaf(cth[m], P.y, P.w);
-        w[m] = __builtin_fmaf(sth[m], P.z, w[m]);
+      for (int pr = 0; pr < NPAIR; ++pr) {
+        half2_t q = pq[pr][SPD - 1];
+#pragma unroll
+        for (int k = SPD - 2; k >= 0; --k) q = __builtin_elementwise_fma(q, tt, pq[pr][k]);
+        const int m0 = 2 * pr, m1 = 2 * pr + 1;
+        const float o0 = __builtin_fmaf(A, pc0[m0], t[32 * m0]);
+        t[32 * m0] = __builtin_fmaf((float)q.x, At, o0);
+        if (m1 < TPL) {
+          const float o1 = __builtin_fmaf(A, pc0[m1], t[32 * m1]);
+          t[32 * m1] = __builtin_fmaf((float)q.y, At, o1);
+        }
+      }
+    } else {
+      // When W/32 is even, tap m + TPL/2 sits half a window period after tap
+      // m, where the Hann term flips sign: its numerator is 2 (C/2) - w_m.
+      float w[TPL];
+#pragma unroll
+      for (int m = 0; m < TPL; ++m) {
+        if (TPL % 2 == 0 && m >= TPL / 2) {
+          w[m] = __builtin_fmaf(2.0f, P.w, -w[m - TPL / 2]);
+        } else {
+          w[m] = __builtin_fmaf(cth[m], P.y, P.w);
+          w[m] = __builtin_fmaf(sth[m], P.z, w[m]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < TPL; ++m) {
+        const float u = __builtin_fmaf(nsg[m], P.x, sgj[m]);
+        const float r = __builtin_amdgcn_rcpf(u);
+        t[32 * m] = __builtin_fmaf(w[m], r, t[32 * m]);
       }
     }
-#pragma unroll
-    for (int m = 0; m < TPL; ++m) {
-      const float u = __builtin_fmaf(nsg[m], P.x, sgj[m]);
-      const float r = __builtin_amdgcn_rcpf(u);
-      t[32 * m] = __builtin_fmaf(w[m], r, t[32 * m]);
-    }
   };
+  auto base_of = [&](const f4v &P, int k) { return HALF ? __float_as_int(P.w) : stb[k]; };
+  // staged record k (read as one 16-byte access: see step)
+  auto rec = [&](int k) { return stp[k]; };
 
   int ns = 0;  // staged images (wave-uniform)
-  enumerate_shell<1>(g, tx, ty, ay, az, es, 0, [&](int qn) {
+  enumerate_shell(g, tx, ty, ay, az, es, [&](int qn) {
     // queue entries and z table rows are read one chunk of 64 ahead
     uint32_t ent = 0;
     AxisEntry ez{0.0f, 0.0f, 0.0f, 0.0f};
@@ -668,182 +733,50 @@ __device__ __forceinline__ void accumulate_item_taps(const RoomArgs &ra, const i
       // lanes = candidates: parameters, then compaction into the stage
       ImageParams p;
       p.ok = false;
-      if (q + lane < qn) p = image_params<WT>(ra, g, es, ez_c, ent_c);
+      if (q + lane < qn) p = image_params<WT, HALF>(ra, g, es, ez_c, ent_c);
       const uint64_t okm = __ballot(p.ok);
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
       if (p.ok) {
-        stp[ns + rank] = make_float4(p.f, p.CP, p.CQ, p.C2);
-        stb[ns + rank] = p.base;
+        stp[ns + rank] = p.rec;
+        if constexpr (!HALF) stb[ns + rank] = p.base;
       }
       ns += __builtin_popcountll(okm);
       wave_sync();
       // lanes = taps: two staged images per step, one per half-wave; the
       // next step's parameters are read ahead of this step's tile update
-      const int np = ns >> 1;
       // (reads ahead stay inside the stage: indices <= 2 np + 1 <= SCAP - 1)
-      float4 PA = stp[h];
-      int bA = stb[h];
+      const int np = ns >> 1;
+      f4v PA = rec(h);
+      int bA = base_of(PA, h);
       for (int s = 0; s < np; s += 2) {
-        const float4 PB = stp[2 * s + 2 + h];
-        const int bB = stb[2 * s + 2 + h];
+        const f4v PB = rec(2 * s + 2 + h);
+        const int bB = base_of(PB, 2 * s + 2 + h);
         __builtin_amdgcn_sched_barrier(0);  // keep the read-ahead in front of the step
         step(PA, bA);
         if (s + 1 < np) {
-          PA = stp[2 * s + 4 + h];
-          bA = stb[2 * s + 4 + h];
+          PA = rec(2 * s + 4 + h);
+          bA = base_of(PA, 2 * s + 4 + h);
           __builtin_amdgcn_sched_barrier(0);
           step(PB, bB);
         }
       }
       if (ns & 1) {  // carry the odd image to the front of the stage
-        const float4 P = stp[ns - 1];
-        const int b = stb[ns - 1];
+        const f4v P = stp[ns - 1];
+        const int b = HALF ? 0 : stb[ns - 1];
         wave_sync();
         if (lane == 0) {
           stp[0] = P;
-          stb[0] = b;
+          if constexpr (!HALF) stb[0] = b;
         }
       }
       ns &= 1;
       wave_sync();
     }
   });
-  if (ns == 1 && h == 0) step(stp[0], stb[0]);
+  if (ns == 1 && h == 0) step(stp[0], base_of(stp[0], 0));
 
   wave_sync();
   write_item<WT, 2>(tile, n_own, dst, marg, lane, 64);
-}
-
-// FP16 work item (lanes = images), NW waves per block.
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-
-template <int WT, int NW>
-__device__ __forceinline__ void accumulate_item_half(const RoomArgs &ra, const int tile_id, const int C, const int c,
-                                                     const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                     const bool valid, float *__restrict__ dst,
-                                                     float *__restrict__ marg) {
-  constexpr int JLO = 1 - WT / 2;
-  constexpr int SPAN = TILE + WT - 1;
-  constexpr TapConsts<WT> K = make_tap_consts<WT>();
-  constexpr PolyConsts<WT> PC = make_poly_consts<WT>();
-
-  __shared__ float tile[NW][SPAN];
-  __shared__ uint8_t claim[NW][SPAN];
-  __shared__ EnumLds es_all[NW];
-
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int n_own = min(TILE, ra.n_samples - tile_id * TILE);
-
-  if (!valid) {
-    write_invalid<WT>(n_own, dst, marg, threadIdx.x, NW * 64);
-    return;
-  }
-  const AxisEntry *__restrict__ tx = tab + ra.off[0];
-  const AxisEntry *__restrict__ ty = tab + ra.off[1];
-  const AxisEntry *__restrict__ tz = tab + ra.off[2];
-  const AxisRange ax{ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]};
-  const AxisRange ay{ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]};
-  const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
-  const ItemGeom g = item_geom(ra, ax, tile_id, C, c);
-  EnumLds &es = es_all[wave];
-
-  float *__restrict__ wt = tile[wave];
-  uint8_t *__restrict__ wc = claim[wave];
-  for (int i = lane; i < SPAN; i += 64) wt[i] = 0.0f;
-
-  // Image held by this lane, with its tap parameters.
-  bool has = false;
-  float f = 0.0f, C2 = 0.0f, CP = 0.0f, CQ = 0.0f;
-  int base = 0;
-
-  // Claim positions, add the taps of the winning lanes (distinct bases). A
-  // compiler barrier between taps keeps every lane's read-modify-write of tap
-  // j ahead of any lane's access for tap j + 1.
-  auto tap_round = [&]() {
-    volatile uint8_t *vc = wc;
-    if (has) vc[base] = (uint8_t)lane;
-    wave_sync();
-    const bool win = has && vc[base] == (uint8_t)lane;
-    if (win) {
-      float *t = wt + base;
-      const _Float16 thf = (_Float16)(f - 0.5f);
-      half2_t tt = {thf, thf};
-      const float Cc = 2.0f * C2;
-#pragma unroll
-      for (int jj = 0; jj < WT; ++jj) {
-        const int j = jj + JLO;
-        if (!poly_tap(j)) {
-          const float o = t[jj];
-          __asm__ volatile("" : "+v"(f), "+v"(CP), "+v"(CQ), "+v"(C2) :: "memory");
-          const float u = __builtin_fmaf(-K.sig[jj], f, K.sig_j[jj]);
-          const float r = __builtin_amdgcn_rcpf(u);
-          float w = __builtin_fmaf(K.cth[jj], CP, C2);
-          w = __builtin_fmaf(K.sth[jj], CQ, w);
-          t[jj] = __builtin_fmaf(w, r, o);
-          __asm__ volatile("" ::: "memory");
-          __builtin_amdgcn_sched_barrier(0);
-        } else if (jj + 1 < WT && poly_tap(j + 1) && ((j <= -2) ? (j - JLO) % 2 == 0 : (j - 3) % 2 == 0)) {
-          // taps jj and jj + 1 in one packed register
-          const half2_t c3 = {(_Float16)PC.c[3][jj], (_Float16)PC.c[3][jj + 1]};
-          const half2_t c2 = {(_Float16)PC.c[2][jj], (_Float16)PC.c[2][jj + 1]};
-          const half2_t c1 = {(_Float16)PC.c[1][jj], (_Float16)PC.c[1][jj + 1]};
-          const half2_t c0 = {(_Float16)PC.c[0][jj], (_Float16)PC.c[0][jj + 1]};
-          const float o0 = t[jj];
-          __asm__ volatile("" : "+v"(tt) :: "memory");
-          half2_t pv = __builtin_elementwise_fma(c3, tt, c2);
-          pv = __builtin_elementwise_fma(pv, tt, c1);
-          pv = __builtin_elementwise_fma(pv, tt, c0);
-          t[jj] = __builtin_fmaf((float)pv.x, Cc, o0);
-          __asm__ volatile("" ::: "memory");
-          const float o1 = t[jj + 1];
-          t[jj + 1] = __builtin_fmaf((float)pv.y, Cc, o1);
-          __asm__ volatile("" ::: "memory");
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-    }
-    has = has && !win;
-    wave_sync();
-  };
-
-  enumerate_shell<NW>(g, tx, ty, ay, az, es, wave, [&](int qn) {
-    int qpos = 0;
-    while (qpos < qn) {
-      // refill the lanes without an image from the queue (lanes = images)
-      const bool need = !has;
-      const uint64_t need_mask = __ballot(need);
-      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need_mask >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
-      if (need && qpos + rank < qn) {
-        const uint32_t ent = es.queue[qpos + rank];
-        const ImageParams p = image_params<WT>(ra, g, es, tz[ent & 0xffffu], ent);
-        has = p.ok;
-        base = p.base;
-        f = p.f;
-        C2 = p.C2;
-        CP = p.CP;
-        CQ = p.CQ;
-      }
-      qpos += __builtin_popcountll(need_mask);
-      tap_round();
-    }
-  });
-  // images still waiting after their queue ran out
-  while (__ballot(has) != 0) tap_round();
-
-  __syncthreads();
-  write_item<WT, NW>(tile, n_own, dst, marg, threadIdx.x, NW * 64);
-}
-
-template <int WT, int NW, bool HALF>
-__device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
-                                                const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                const bool valid, float *__restrict__ dst, float *__restrict__ marg) {
-  if constexpr (HALF)
-    accumulate_item_half<WT, NW>(ra, tile_id, C, c, tab, org, valid, dst, marg);
-  else
-    accumulate_item_taps<WT>(ra, tile_id, C, c, tab, org, valid, dst, marg);
 }
 
 // First work item of dispatch position pos (see PlanArgs).
@@ -854,8 +787,8 @@ __device__ __forceinline__ uint32_t plan_first_item(const PlanArgs &pa, int pos)
 }
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
-template <int WT, int NW, bool HALF>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 1 ? 6 : 1))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
+template <int WT, bool HALF>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
                                                              const int *__restrict__ valid, float *__restrict__ out,
@@ -887,13 +820,13 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 1
   // (for a tile past nS, dst is never written: the tile has no own samples)
   float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
   const AxisOrigin org = origin[rir];
-  accumulate_item<WT, NW, HALF>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst,
+  accumulate_item<WT, HALF>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst,
                                 marg + (size_t)item * WT);
 }
 
 // Batch launch: every item names its job; the job table carries the room.
-template <int WT, int NW, bool HALF>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 1 ? 6 : 1))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
+template <int WT, bool HALF>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
                                                                    const AxisOrigin *__restrict__ origin,
@@ -906,7 +839,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 1
   float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
                                         : part + (size_t)it.slot * TILE;
   const AxisOrigin org = origin[grir];
-  accumulate_item<WT, NW, HALF>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab,
+  accumulate_item<WT, HALF>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab,
                                 org, valid[grir] != 0, dst, marg + (size_t)it.mslot * MARG_STRIDE);
 }
 
@@ -1003,8 +936,7 @@ template <int WT, bool HALF>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                         const AxisOrigin *origin, const int *valid, float *out, float *part, float *marg,
                         hipStream_t st) {
-  constexpr int NW = HALF ? 4 : 1;  // FP32 items run on one wave, FP16 items on four
-  hipLaunchKernelGGL((accumulate_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, ra, pa, tab, origin,
+  hipLaunchKernelGGL((accumulate_kernel<WT, HALF>), dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin,
                      valid, out, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1031,8 +963,7 @@ int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa,
 template <int WT, bool HALF>
 static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
                               const AxisOrigin *origin, const int *valid, float *part, float *marg, hipStream_t st) {
-  constexpr int NW = HALF ? 4 : 1;  // FP32 items run on one wave, FP16 items on four
-  hipLaunchKernelGGL((accumulate_batch_kernel<WT, NW, HALF>), dim3(n_items), dim3(NW * 64), 0, st, jobs, items, tab,
+  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
                      origin, valid, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

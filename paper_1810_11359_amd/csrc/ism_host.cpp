@@ -117,9 +117,8 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   pa.n_rir = p.n_rir;
   const double cell = r->room[0] * r->room[1] * r->room[2] * q * q * q;
   const double lattice = (double)r->n_img[0] * r->n_img[1] * r->n_img[2];
-  // Estimated taps per work item: FP32 items run on one wave, FP16 items on a
-  // block of four, so FP16 items are larger.
-  double target = p.half ? 2.5e5 : 1.2e5;
+  // Estimated taps per work item (one wave each).
+  double target = 1.2e5;
   if (const char *e = std::getenv("ISM_TARGET_TAPS")) target = std::max(1e3, std::atof(e));
   p.any_split = false;
   for (int t = 0; t < pa.n_tiles; ++t) {
