@@ -93,9 +93,11 @@ def _oracle_args(orc, w):
     return (w.room, beta, n, w.c, w.fs, w.t_max, w.t_w)
 
 
-def cpu_baseline(ws, n_rcv_sample: int):
+def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None):
     """FP64 oracle on a bounded sample: the first ``n_rcv_sample`` receivers of a
-    single-room workload, or the first rooms of a batch up to that many RIRs."""
+    single-room workload, or the first rooms of a batch up to that many RIRs.
+    With ``gpu_outs`` (host arrays [n_src, n_rcv, nS] per workload) it also
+    reports the largest max|h_gpu - h_oracle| / max|h_oracle| over the sample."""
     from oracle import oracle as orc
 
     orc.build()
@@ -109,14 +111,21 @@ def cpu_baseline(ws, n_rcv_sample: int):
     threads = max(1, min(os.cpu_count() or 1, 16, sum(r.shape[0] for _, r in jobs)))
     taps = sum(orc.count_taps(*_oracle_args(orc, w), w.src, r) for w, r in jobs)
     t0 = time.perf_counter()
-    for w, r in jobs:
-        orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=min(threads, r.shape[0]))
+    refs = [orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=min(threads, r.shape[0])) for w, r in jobs]
     dt = time.perf_counter() - t0
     n = sum(r.shape[0] for _, r in jobs)
-    return {"value": taps / dt / 1e9, "unit": "G taps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} full RIRs of the workload ({len(jobs)} room(s); {taps} taps, {dt:.2f} s wall, "
-                      f"up to {threads} threads)",
-            "rirs_per_s": n / dt}
+    out = {"value": taps / dt / 1e9, "unit": "G taps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} full RIRs of the workload ({len(jobs)} room(s); {taps} taps, {dt:.2f} s wall, "
+                     f"up to {threads} threads)",
+           "rirs_per_s": n / dt}
+    if gpu_outs is not None:
+        err = 0.0
+        for (w, r), ref, got in zip(jobs, refs, gpu_outs):
+            g = np.asarray(got, dtype=np.float64)[:, :r.shape[0], :]
+            peak = np.max(np.abs(ref), axis=-1)
+            err = max(err, float(np.max(np.max(np.abs(g - ref), axis=-1) / peak)))
+        out["max_err_vs_oracle"] = err
+    return out
 
 
 def serve(args) -> int:
@@ -135,7 +144,8 @@ def serve(args) -> int:
 
     reqs = workloads.serving_stream(rate=args.rate, n_jobs=args.jobs, seed=0, feasible=feasible)
     jobs = [Job(i, ism.room_for(r.workload), r.workload.src, r.workload.rcv, r.arrival) for i, r in enumerate(reqs)]
-    taps = sum(ism.count_taps(j.room, j.src, j.rcv) for j in jobs)
+    # exact tap counts cost host time proportional to the images of every job
+    taps = sum(ism.count_taps(j.room, j.src, j.rcv) for j in jobs) if args.count_taps else None
     # warm-up: compile/load every kernel variant once
     warm = [Job(-1, j.room, j.src[:1], j.rcv[:1], 0.0) for j in jobs[:8]]
     replay(Scheduler(GpuExecutor(2), budget_bytes=8 << 30, n_slots=2), warm)
@@ -148,9 +158,9 @@ def serve(args) -> int:
            "warmup": len(warm), "ms_per_step": st.makespan_s * 1e3 / len(jobs), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": f"serving_poisson_{args.rate:g}_jobs_per_s", "n_jobs": len(jobs),
-                      "n_rirs": st.n_rirs, "taps": int(taps), "slots": n_slots, "budget_bytes": 64 << 30,
-                      "parallelism": "single GPU"},
-           "serving": st.as_dict(), "taps_per_s": taps / st.makespan_s}
+                      "n_rirs": st.n_rirs, "taps": None if taps is None else int(taps), "slots": n_slots,
+                      "budget_bytes": 64 << 30, "parallelism": "single GPU"},
+           "serving": st.as_dict(), "taps_per_s": None if taps is None else taps / st.makespan_s}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -169,6 +179,7 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving mode: replay a Poisson stream of mixed RIR jobs at this many jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving mode: jobs in the stream")
+    ap.add_argument("--count-taps", action="store_true", help="serving mode: also count the exact taps (slow)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the ISM path here does not "
@@ -257,7 +268,10 @@ def main() -> int:
                      "kernel_ms_p50": float(np.median(kern_ms)), "flop_per_tap": FLOP_PER_TAP},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_sample)
+        res = sim.outs if args.workload == "batch_rooms" else [sim.out]
+        gpu_outs = [o.cpu().numpy() for o in res[:args.cpu_sample]]
+        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_sample, gpu_outs)
+        out["max_err_vs_oracle"] = out["cpu_baseline"].pop("max_err_vs_oracle")
     print(json.dumps(out), flush=True)
     return 0
 

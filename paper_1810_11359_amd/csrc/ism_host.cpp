@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -61,6 +62,7 @@ struct Plan {
   RoomArgs ra;
   PlanArgs pa;
   double tile_taps[MAX_TILES];  // estimated taps of each tile's image shell
+  double total_taps;            // over all RIRs
   int wt;
   bool half;
   int n_rir;
@@ -69,7 +71,20 @@ struct Plan {
   size_t off_valid, off_origin, off_tab, off_part, off_marg, ws_bytes;
 };
 
-int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
+// Work-item size in estimated taps. A launch should hold about kBalanceItems
+// items (some eight per resident wave) so that the largest-first order keeps
+// every CU busy to the end; small calls keep items of kMinItemTaps. The
+// environment variable ISM_TARGET_TAPS fixes the size (tests use it to change
+// the split).
+constexpr double kMinItemTaps = 1.2e5;
+constexpr double kBalanceItems = 49152.0;
+double item_target(double total_taps) {
+  if (const char *e = std::getenv("ISM_TARGET_TAPS")) return std::max(1e3, std::atof(e));
+  return std::max(kMinItemTaps, total_taps / kBalanceItems);
+}
+
+// target <= 0: item size chosen from this call's own estimated work.
+int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, double target = 0.0) {
   int st = ism_check_room(r);
   if (st != ISM_OK) return st;
   if (n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
@@ -117,15 +132,17 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p) {
   pa.n_rir = p.n_rir;
   const double cell = r->room[0] * r->room[1] * r->room[2] * q * q * q;
   const double lattice = (double)r->n_img[0] * r->n_img[1] * r->n_img[2];
-  // Estimated taps per work item (one wave each).
-  double target = 1.2e5;
-  if (const char *e = std::getenv("ISM_TARGET_TAPS")) target = std::max(1e3, std::atof(e));
-  p.any_split = false;
+  p.total_taps = 0.0;
   for (int t = 0; t < pa.n_tiles; ++t) {
     const double x0 = (double)t * TILE, x1 = std::min((double)(t + 1) * TILE, (double)ra.k_end);
     const double imgs = std::min(4.0 / 3.0 * kPi * (x1 * x1 * x1 - x0 * x0 * x0) / cell, lattice);
-    const double taps = imgs * W;
-    p.tile_taps[t] = taps;
+    p.tile_taps[t] = imgs * W;
+    p.total_taps += p.tile_taps[t] * p.n_rir;
+  }
+  if (!(target > 0.0)) target = item_target(p.total_taps);
+  p.any_split = false;
+  for (int t = 0; t < pa.n_tiles; ++t) {
+    const double taps = p.tile_taps[t];
     int ch = (int)std::ceil(taps / target);
     ch = std::max(1, std::min(ch, MAX_CHUNKS));
     pa.chunks[t] = (uint8_t)ch;
@@ -358,27 +375,36 @@ struct BatchPlan {
   size_t ws_bytes;
 };
 
-int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
+// Largest-first order without a comparison sort: items go into buckets of
+// their estimated cost, eight per octave, filled from the most expensive down
+// (stable: jobs, tiles, RIRs and chunks keep their order inside a bucket).
+constexpr int kCostBuckets = 512;
+int cost_bucket(double cost) {
+  const int b = (int)std::floor(8.0 * std::log2(cost + 1.0));
+  return std::max(0, std::min(kCostBuckets - 1, b));
+}
+
+// Plans a batch. With fill == false only the counts and the workspace layout
+// are computed (ism_batch_workspace_size); with fill == true the job, RIR,
+// item and reduce tables are built as well (ism_batch_prepare).
+int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bool fill) {
   if (!jobs || n_jobs < 1) return ISM_E_INVALID_ARG;
   std::memset(&bp.st, 0, sizeof(bp.st));
-  bp.jobs.resize(n_jobs);
-  struct Cand {
-    double cost;
-    int cls;
-    BatchItem it;
-  };
-  std::vector<Cand> cand;
-  uint64_t tab_entries = 0, n_rir = 0;
-  uint32_t slots = 0;
-  uint64_t mslots = 0;
+  // Each job is planned exactly as a single call would plan it (items sized
+  // from the job's own work), so a job's result does not depend on the batch.
+  std::vector<Plan> plans(n_jobs);
+  for (int j = 0; j < n_jobs; ++j)
+    if (!jobs[j].src || !jobs[j].rcv || !jobs[j].out) return ISM_E_INVALID_ARG;
+  // pass 1: plans, window classes and counts
   int n_classes = 0;
   int class_wt[kMaxClasses] = {0, 0, 0, 0};
+  std::vector<int> job_cls(n_jobs);
+  uint64_t tab_entries = 0, n_rir = 0, n_items = 0, slots = 0, n_red = 0;
+  std::vector<uint64_t> bucket_count((size_t)kMaxClasses * kCostBuckets, 0);
   for (int j = 0; j < n_jobs; ++j) {
-    const ism_job &jb = jobs[j];
-    Plan p;
-    const int stt = make_plan(&jb.room, jb.n_src, jb.n_rcv, precision, p);
+    Plan &p = plans[j];
+    const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p);
     if (stt != ISM_OK) return stt;
-    if (!jb.src || !jb.rcv || !jb.out) return ISM_E_INVALID_ARG;
     int cls = -1;
     for (int k = 0; k < n_classes; ++k)
       if (class_wt[k] == p.wt) cls = k;
@@ -387,85 +413,44 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
       cls = n_classes++;
       class_wt[cls] = p.wt;
     }
-    JobDev &d = bp.jobs[j];
-    std::memset(&d, 0, sizeof(d));
-    d.ra = p.ra;
-    d.src = jb.src;
-    d.rcv = jb.rcv;
-    d.out = jb.out;
-    d.tab_base = tab_entries;
-    d.rir_base = (uint32_t)n_rir;
-    for (int r = 0; r < p.n_rir; ++r) bp.rirs.push_back(BatchRir{(uint32_t)j, (uint32_t)r});
-    // margin records of (tile t, RIR r): mfirst[t * n_rir + r] .. + chunks[t] - 1
-    const int nt = p.pa.n_tiles;
-    std::vector<uint64_t> mfirst((size_t)nt * p.n_rir);
-    for (int t = 0; t < nt; ++t)
-      for (int r = 0; r < p.n_rir; ++r) {
-        mfirst[(size_t)t * p.n_rir + r] = mslots;
-        mslots += p.pa.chunks[t];
-      }
-    if (mslots > 0xffffffffULL) return ISM_E_TOO_LARGE;
-    for (int t = 0; t < nt; ++t) {
-      const int C = p.pa.chunks[t];
-      for (int r = 0; r < p.n_rir; ++r) {
-        const uint32_t first = C > 1 ? slots : 0xffffffffu;
-        BatchReduce rd{};
-        rd.job = (uint32_t)j;
-        rd.rir = (uint32_t)r;
-        rd.tile = (uint16_t)t;
-        rd.chunks = (uint16_t)C;
-        rd.first = first;
-        if (t > 0) {
-          rd.mprev = (uint32_t)mfirst[(size_t)(t - 1) * p.n_rir + r];
-          rd.nprev = p.pa.chunks[t - 1];
-        }
-        if (t + 1 < nt) {
-          rd.mnext = (uint32_t)mfirst[(size_t)(t + 1) * p.n_rir + r];
-          rd.nnext = p.pa.chunks[t + 1];
-        }
-        bp.red.push_back(rd);
-        if (C > 1) slots += (uint32_t)C;
-        for (int c = 0; c < C; ++c) {
-          BatchItem it{(uint32_t)j, (uint32_t)r, (uint16_t)t, (uint8_t)c, (uint8_t)C,
-                       C > 1 ? first + (uint32_t)c : 0xffffffffu,
-                       (uint32_t)(mfirst[(size_t)t * p.n_rir + r] + c)};
-          cand.push_back(Cand{p.tile_taps[t] / C, cls, it});
-        }
-      }
+    job_cls[j] = cls;
+    for (int t = 0; t < p.pa.n_tiles; ++t) {
+      const uint64_t C = p.pa.chunks[t];
+      n_items += C * p.n_rir;
+      if (C > 1) slots += C * p.n_rir;
+      bucket_count[(size_t)cls * kCostBuckets + cost_bucket(p.tile_taps[t] / C)] += C * p.n_rir;
     }
+    n_red += (uint64_t)p.pa.n_tiles * p.n_rir;
     tab_entries += (uint64_t)p.n_rir * p.ra.n_tab;
     n_rir += (uint64_t)p.n_rir;
-    if (n_rir > 0x7fffffffULL || cand.size() > 0x7fffffffULL) return ISM_E_TOO_LARGE;
   }
-  // Items grouped by window length, each group in decreasing estimated work.
-  std::stable_sort(cand.begin(), cand.end(), [](const Cand &a, const Cand &b) {
-    if (a.cls != b.cls) return a.cls < b.cls;
-    return a.cost > b.cost;
-  });
-  bp.items.resize(cand.size());
-  for (size_t i = 0; i < cand.size(); ++i) {
-    bp.items[i] = cand[i].it;
-    bp.st.class_count[cand[i].cls]++;
-  }
-  uint32_t acc = 0;
+  if (n_rir > 0x7fffffffULL || n_items > 0x7fffffffULL || slots > 0xffffffffULL || n_red > 0x7fffffffULL)
+    return ISM_E_TOO_LARGE;
+  // item positions: classes in order, each class from its most expensive bucket down
+  std::vector<uint64_t> bucket_next((size_t)kMaxClasses * kCostBuckets, 0);
+  uint64_t acc = 0;
   for (int k = 0; k < n_classes; ++k) {
-    bp.st.class_first[k] = acc;
-    acc += bp.st.class_count[k];
+    bp.st.class_first[k] = (uint32_t)acc;
+    for (int b = kCostBuckets - 1; b >= 0; --b) {
+      bucket_next[(size_t)k * kCostBuckets + b] = acc;
+      acc += bucket_count[(size_t)k * kCostBuckets + b];
+    }
+    bp.st.class_count[k] = (uint32_t)(acc - bp.st.class_first[k]);
     bp.st.class_wt[k] = class_wt[k];
   }
   bp.st.n_classes = (uint32_t)n_classes;
   bp.st.half = precision == ISM_FP16 ? 1u : 0u;
   bp.st.n_rir = (uint32_t)n_rir;
-  bp.st.n_red = (uint32_t)bp.red.size();
+  bp.st.n_red = (uint32_t)n_red;
   size_t o = 0;
   bp.st.off_jobs = o;
-  o = align_up(o + sizeof(JobDev) * bp.jobs.size());
+  o = align_up(o + sizeof(JobDev) * (size_t)n_jobs);
   bp.st.off_rirs = o;
-  o = align_up(o + sizeof(BatchRir) * bp.rirs.size());
+  o = align_up(o + sizeof(BatchRir) * (size_t)n_rir);
   bp.st.off_items = o;
-  o = align_up(o + sizeof(BatchItem) * bp.items.size());
+  o = align_up(o + sizeof(BatchItem) * (size_t)n_items);
   bp.st.off_red = o;
-  o = align_up(o + sizeof(BatchReduce) * bp.red.size());
+  o = align_up(o + sizeof(BatchReduce) * (size_t)n_red);
   bp.st.off_valid = o;
   o = align_up(o + sizeof(int) * n_rir);
   bp.st.off_origin = o;
@@ -475,8 +460,67 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
   bp.st.off_part = o;
   o = align_up(o + sizeof(float) * (size_t)slots * TILE);
   bp.st.off_marg = o;
-  o = align_up(o + sizeof(float) * (size_t)mslots * MARG_STRIDE);
+  o = align_up(o + sizeof(float) * (size_t)n_items * MARG_STRIDE);
   bp.ws_bytes = o;
+  if (!fill) return ISM_OK;
+
+  // pass 2: tables. Margin records are numbered in (job, tile, RIR, chunk)
+  // order, so the records of one (tile, RIR) are contiguous.
+  bp.jobs.resize(n_jobs);
+  bp.rirs.resize(n_rir);
+  bp.items.resize(n_items);
+  bp.red.resize(n_red);
+  uint64_t rir_base = 0, tab_base = 0, mslot = 0, red_i = 0;
+  uint32_t slot = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const Plan &p = plans[j];
+    const ism_job &jb = jobs[j];
+    JobDev &d = bp.jobs[j];
+    std::memset(&d, 0, sizeof(d));
+    d.ra = p.ra;
+    d.src = jb.src;
+    d.rcv = jb.rcv;
+    d.out = jb.out;
+    d.tab_base = tab_base;
+    d.rir_base = (uint32_t)rir_base;
+    for (int r = 0; r < p.n_rir; ++r) bp.rirs[rir_base + r] = BatchRir{(uint32_t)j, (uint32_t)r};
+    const int nt = p.pa.n_tiles;
+    // first margin record of (tile t, RIR r) is mfirst_t + r * chunks[t]
+    std::vector<uint64_t> mfirst(nt);
+    for (int t = 0; t < nt; ++t) {
+      mfirst[t] = mslot;
+      mslot += (uint64_t)p.pa.chunks[t] * p.n_rir;
+    }
+    for (int t = 0; t < nt; ++t) {
+      const int C = p.pa.chunks[t];
+      uint64_t &pos = bucket_next[(size_t)job_cls[j] * kCostBuckets + cost_bucket(p.tile_taps[t] / C)];
+      for (int r = 0; r < p.n_rir; ++r) {
+        BatchReduce &rd = bp.red[red_i++];
+        std::memset(&rd, 0, sizeof(rd));
+        rd.job = (uint32_t)j;
+        rd.rir = (uint32_t)r;
+        rd.tile = (uint16_t)t;
+        rd.chunks = (uint16_t)C;
+        rd.first = C > 1 ? slot : 0xffffffffu;
+        if (t > 0) {
+          rd.mprev = (uint32_t)(mfirst[t - 1] + (uint64_t)r * p.pa.chunks[t - 1]);
+          rd.nprev = p.pa.chunks[t - 1];
+        }
+        if (t + 1 < nt) {
+          rd.mnext = (uint32_t)(mfirst[t + 1] + (uint64_t)r * p.pa.chunks[t + 1]);
+          rd.nnext = p.pa.chunks[t + 1];
+        }
+        for (int c = 0; c < C; ++c)
+          bp.items[pos++] = BatchItem{(uint32_t)j, (uint32_t)r, (uint16_t)t, (uint8_t)c, (uint8_t)C,
+                                      C > 1 ? slot + (uint32_t)c : 0xffffffffu,
+                                      (uint32_t)(mfirst[t] + (uint64_t)r * C + c)};
+        if (C > 1) slot += (uint32_t)C;
+      }
+    }
+    tab_base += (uint64_t)p.n_rir * p.ra.n_tab;
+    rir_base += (uint64_t)p.n_rir;
+  }
+  if (mslot > 0xffffffffULL) return ISM_E_TOO_LARGE;
   return ISM_OK;
 }
 
@@ -485,7 +529,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp) {
 int ism_batch_workspace_size(const ism_job *jobs, int n_jobs, int precision, size_t *bytes) {
   if (!bytes) return ISM_E_INVALID_ARG;
   BatchPlan bp;
-  const int st = plan_batch(jobs, n_jobs, precision, bp);
+  const int st = plan_batch(jobs, n_jobs, precision, bp, false);
   if (st != ISM_OK) return st;
   *bytes = bp.ws_bytes;
   return ISM_OK;
@@ -495,17 +539,19 @@ int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, 
                       ism_batch *batch) {
   if (!batch) return ISM_E_INVALID_ARG;
   BatchPlan bp;
-  const int st = plan_batch(jobs, n_jobs, precision, bp);
+  const int st = plan_batch(jobs, n_jobs, precision, bp, true);
   if (st != ISM_OK) return st;
   if (!ws || ws_bytes < bp.ws_bytes) return ISM_E_WORKSPACE;
   // one contiguous host image of the metadata, copied with a single transfer
-  std::vector<char> host(bp.st.off_valid, 0);
-  std::memcpy(host.data() + bp.st.off_jobs, bp.jobs.data(), sizeof(JobDev) * bp.jobs.size());
-  std::memcpy(host.data() + bp.st.off_rirs, bp.rirs.data(), sizeof(BatchRir) * bp.rirs.size());
-  std::memcpy(host.data() + bp.st.off_items, bp.items.data(), sizeof(BatchItem) * bp.items.size());
-  if (!bp.red.empty()) std::memcpy(host.data() + bp.st.off_red, bp.red.data(), sizeof(BatchReduce) * bp.red.size());
+  // (alignment gaps between the tables are left uninitialised)
+  std::unique_ptr<char[]> host_buf(new char[bp.st.off_valid]);
+  char *const host = host_buf.get();
+  std::memcpy(host + bp.st.off_jobs, bp.jobs.data(), sizeof(JobDev) * bp.jobs.size());
+  std::memcpy(host + bp.st.off_rirs, bp.rirs.data(), sizeof(BatchRir) * bp.rirs.size());
+  std::memcpy(host + bp.st.off_items, bp.items.data(), sizeof(BatchItem) * bp.items.size());
+  if (!bp.red.empty()) std::memcpy(host + bp.st.off_red, bp.red.data(), sizeof(BatchReduce) * bp.red.size());
   hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, s) != hipSuccess) return ISM_E_DEVICE;
+  if (hipMemcpyAsync(ws, host, bp.st.off_valid, hipMemcpyHostToDevice, s) != hipSuccess) return ISM_E_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return ISM_E_DEVICE;
   bp.st.ws = (uint64_t)(uintptr_t)ws;
   std::memset(batch, 0, sizeof(*batch));

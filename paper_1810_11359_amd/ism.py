@@ -267,17 +267,22 @@ class BatchSimulator:
         self._keep = []
         self.outs = []
         arr = (_Job * len(jobs))()
-        for i, (room, src, rcv) in enumerate(jobs):
-            s, r = _host_pos(src), _host_pos(rcv)
-            if check:
+        host = [(_host_pos(src), _host_pos(rcv)) for _, src, rcv in jobs]
+        if check:
+            for (room, _, _), (s, r) in zip(jobs, host):
                 check_positions(room, s, r)
-            ds, dr = torch.from_numpy(s).to(device), torch.from_numpy(r).to(device)
+        # all positions of the batch in one device buffer (one host-to-device copy)
+        pos = torch.from_numpy(np.concatenate([a for sr in host for a in sr], axis=0)).to(device)
+        self._keep.append(pos)
+        row = 0
+        for i, ((room, _, _), (s, r)) in enumerate(zip(jobs, host)):
             out = torch.empty((s.shape[0], r.shape[0], room.n_samples), dtype=torch.float32, device=device)
-            self._keep += [ds, dr]
             self.outs.append(out)
             arr[i].room = room._c()
-            arr[i].src, arr[i].n_src = ds.data_ptr(), s.shape[0]
-            arr[i].rcv, arr[i].n_rcv = dr.data_ptr(), r.shape[0]
+            arr[i].src, arr[i].n_src = pos[row:].data_ptr(), s.shape[0]
+            row += s.shape[0]
+            arr[i].rcv, arr[i].n_rcv = pos[row:].data_ptr(), r.shape[0]
+            row += r.shape[0]
             arr[i].out = out.data_ptr()
         self.n_rirs = sum(int(o.shape[0] * o.shape[1]) for o in self.outs)
         nbytes = ctypes.c_size_t()
