@@ -554,8 +554,7 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
   return p;
 }
 
-// Per-tap constants, lane l of a half-wave holds taps j = 1 - W/2 + l + 32 m,
-// m = 0 .. W/32 - 1 (index jj = l + 32 m).
+// Per-tap constants, indexed by jj = j - (1 - W/2).
 __constant__ TapConsts<32> kTap32 = make_tap_consts<32>();
 __constant__ TapConsts<64> kTap64 = make_tap_consts<64>();
 __constant__ TapConsts<96> kTap96 = make_tap_consts<96>();
@@ -575,7 +574,6 @@ template <> __device__ __forceinline__ const SincPoly<64> &poly_table<64>() { re
 template <> __device__ __forceinline__ const SincPoly<96> &poly_table<96>() { return kPoly96; }
 template <> __device__ __forceinline__ const SincPoly<128> &poly_table<128>() { return kPoly128; }
 
-constexpr int SCAP = 68;  // staged images: up to 64 new + 1 carried, + read-ahead slots
 
 // Output of a work item whose taps are in LDS tiles t0 (+ t1): the tile's own
 // samples go to dst, the W/2 - 1 samples before and the W/2 after to marg
@@ -605,24 +603,31 @@ __device__ __forceinline__ void write_invalid(int n_own, float *__restrict__ dst
   for (int i = tid; i < WT - 1; i += nthreads) marg[i] = __builtin_nanf("");
 }
 
-// One work item on one wave (lanes = taps). dst receives the own samples of
-// the tile (or a partial tile when C > 1), marg the margins. HALF selects the
-// FP16 tap arithmetic; accumulation is FP32 in both.
-template <int WT, bool HALF>
+// One work item on one wave (lanes = taps). Each step takes NQ staged images,
+// one per group of LPG = 64 / NQ lanes; lane l of group g adds the taps
+// j = 1 - W/2 + l + LPG m (m < TPL = W / LPG) of its image into the group's
+// own LDS tile. dst receives the own samples of the tile (or a partial tile
+// when C > 1), marg the margins. HALF selects the FP16 tap arithmetic;
+// accumulation is FP32 in both.
+template <int WT, bool HALF, int NQ>
 __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                 const AxisEntry *__restrict__ tab, const AxisOrigin &org,
                                                 const bool valid, float *__restrict__ dst, float *__restrict__ marg) {
   constexpr int LSPAN = TILE + WT - 1;
-  constexpr int TPL = WT / 32;         // taps per lane per step
+  constexpr int LPG = 64 / NQ;          // lanes per image
+  constexpr int TPL = WT / LPG;         // taps per lane per step
   constexpr int NPAIR = (TPL + 1) / 2;  // packed FP16 tap pairs per lane
+  // staged images: up to 64 new + NQ - 1 carried, + two steps of read-ahead
+  constexpr int SCAP = 64 + 3 * NQ;
+  static_assert(WT % LPG == 0, "window must be a multiple of the lanes per image");
 
-  __shared__ float tile[2][LSPAN];
+  __shared__ float tile[NQ][LSPAN];
   __shared__ f4v stp[SCAP];             // staged records (ImageParams::rec)
   __shared__ int stb[HALF ? 1 : SCAP];  // FP32: their bases (FP16 records carry the base)
   __shared__ EnumLds es;
 
   const int lane = threadIdx.x & 63;
-  const int h = lane >> 5, l = lane & 31;
+  const int h = lane / LPG, l = lane % LPG;  // image group, lane within it
   const int n_own = min(TILE, ra.n_samples - tile_id * TILE);  // may be <= 0 past nS
   if (!valid) {
     write_invalid<WT>(n_own, dst, marg, lane, 64);
@@ -643,30 +648,30 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   if constexpr (HALF) {
     const SincPoly<WT> &P = poly_table<WT>();
 #pragma unroll
-    for (int m = 0; m < TPL; ++m) pc0[m] = P.c[0][l + 32 * m];
+    for (int m = 0; m < TPL; ++m) pc0[m] = P.c[0][l + LPG * m];
 #pragma unroll
     for (int pr = 0; pr < NPAIR; ++pr)
 #pragma unroll
       for (int k = 0; k < SPD; ++k) {
         const int m0 = 2 * pr, m1 = 2 * pr + 1;
-        const float a = P.c[k + 1][l + 32 * m0];
-        const float b = m1 < TPL ? P.c[k + 1][l + 32 * m1] : 0.0f;
+        const float a = P.c[k + 1][l + LPG * m0];
+        const float b = m1 < TPL ? P.c[k + 1][l + LPG * m1] : 0.0f;
         pq[pr][k] = half2_t{(_Float16)a, (_Float16)b};
       }
   } else {
     const TapConsts<WT> &K = tap_table<WT>();
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
-      nsg[m] = -K.sig[l + 32 * m];
-      sgj[m] = K.sig_j[l + 32 * m];
-      cth[m] = K.cth[l + 32 * m];
-      sth[m] = K.sth[l + 32 * m];
+      nsg[m] = -K.sig[l + LPG * m];
+      sgj[m] = K.sig_j[l + LPG * m];
+      cth[m] = K.cth[l + LPG * m];
+      sth[m] = K.sth[l + LPG * m];
     }
   }
-  for (int i = lane; i < 2 * LSPAN; i += 64) (&tile[0][0])[i] = 0.0f;
+  for (int i = lane; i < NQ * LSPAN; i += 64) (&tile[0][0])[i] = 0.0f;
   float *const th = &tile[h][l];
 
-  // One step: staged image (record P, base b) on this half-wave, taps l + 32 m.
+  // One step: staged image (record P, base b) on this lane group, taps l + LPG m.
   // The empty asm consumes the record as one 128-bit value where the step
   // starts, which keeps its LDS read a single ds_read_b128 issued ahead.
   auto step = [&](const f4v P, const int b) {
@@ -682,15 +687,15 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
 #pragma unroll
         for (int k = SPD - 2; k >= 0; --k) q = __builtin_elementwise_fma(q, tt, pq[pr][k]);
         const int m0 = 2 * pr, m1 = 2 * pr + 1;
-        const float o0 = __builtin_fmaf(A, pc0[m0], t[32 * m0]);
-        t[32 * m0] = __builtin_fmaf((float)q.x, At, o0);
+        const float o0 = __builtin_fmaf(A, pc0[m0], t[LPG * m0]);
+        t[LPG * m0] = __builtin_fmaf((float)q.x, At, o0);
         if (m1 < TPL) {
-          const float o1 = __builtin_fmaf(A, pc0[m1], t[32 * m1]);
-          t[32 * m1] = __builtin_fmaf((float)q.y, At, o1);
+          const float o1 = __builtin_fmaf(A, pc0[m1], t[LPG * m1]);
+          t[LPG * m1] = __builtin_fmaf((float)q.y, At, o1);
         }
       }
     } else {
-      // When W/32 is even, tap m + TPL/2 sits half a window period after tap
+      // When TPL is even, tap m + TPL/2 sits half a window period after tap
       // m, where the Hann term flips sign: its numerator is 2 (C/2) - w_m.
       float w[TPL];
 #pragma unroll
@@ -706,7 +711,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       for (int m = 0; m < TPL; ++m) {
         const float u = __builtin_fmaf(nsg[m], P.x, sgj[m]);
         const float r = __builtin_amdgcn_rcpf(u);
-        t[32 * m] = __builtin_fmaf(w[m], r, t[32 * m]);
+        t[LPG * m] = __builtin_fmaf(w[m], r, t[LPG * m]);
       }
     }
   };
@@ -742,41 +747,48 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       }
       ns += __builtin_popcountll(okm);
       wave_sync();
-      // lanes = taps: two staged images per step, one per half-wave; the
-      // next step's parameters are read ahead of this step's tile update
-      // (reads ahead stay inside the stage: indices <= 2 np + 1 <= SCAP - 1)
-      const int np = ns >> 1;
+      // lanes = taps: NQ staged images per step, one per lane group; the next
+      // step's parameters are read ahead of this step's tile update (reads
+      // ahead stay inside the stage: indices < NQ (np + 2) <= SCAP)
+      const int np = ns / NQ;
       f4v PA = rec(h);
       int bA = base_of(PA, h);
       for (int s = 0; s < np; s += 2) {
-        const f4v PB = rec(2 * s + 2 + h);
-        const int bB = base_of(PB, 2 * s + 2 + h);
+        const f4v PB = rec(NQ * (s + 1) + h);
+        const int bB = base_of(PB, NQ * (s + 1) + h);
         __builtin_amdgcn_sched_barrier(0);  // keep the read-ahead in front of the step
         step(PA, bA);
         if (s + 1 < np) {
-          PA = rec(2 * s + 4 + h);
-          bA = base_of(PA, 2 * s + 4 + h);
+          PA = rec(NQ * (s + 2) + h);
+          bA = base_of(PA, NQ * (s + 2) + h);
           __builtin_amdgcn_sched_barrier(0);
           step(PB, bB);
         }
       }
-      if (ns & 1) {  // carry the odd image to the front of the stage
-        const f4v P = stp[ns - 1];
-        const int b = HALF ? 0 : stb[ns - 1];
+      // carry the remaining images to the front of the stage (the ranges do
+      // not overlap when np > 0)
+      const int rem = ns - NQ * np;
+      if (np > 0 && rem > 0) {
+        f4v P{};
+        int b = 0;
+        if (lane < rem) {
+          P = stp[NQ * np + lane];
+          if constexpr (!HALF) b = stb[NQ * np + lane];
+        }
         wave_sync();
-        if (lane == 0) {
-          stp[0] = P;
-          if constexpr (!HALF) stb[0] = b;
+        if (lane < rem) {
+          stp[lane] = P;
+          if constexpr (!HALF) stb[lane] = b;
         }
       }
-      ns &= 1;
+      ns = rem;
       wave_sync();
     }
   });
-  if (ns == 1 && h == 0) step(stp[0], base_of(stp[0], 0));
+  if (h < ns) step(stp[h], base_of(stp[h], h));  // last images, fewer than NQ
 
   wave_sync();
-  write_item<WT, 2>(tile, n_own, dst, marg, lane, 64);
+  write_item<WT, NQ>(tile, n_own, dst, marg, lane, 64);
 }
 
 // First work item of dispatch position pos (see PlanArgs).
@@ -787,7 +799,7 @@ __device__ __forceinline__ uint32_t plan_first_item(const PlanArgs &pa, int pos)
 }
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
-template <int WT, bool HALF>
+template <int WT, bool HALF, int NQ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
@@ -820,12 +832,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void ac
   // (for a tile past nS, dst is never written: the tile has no own samples)
   float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
   const AxisOrigin org = origin[rir];
-  accumulate_item<WT, HALF>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst,
+  accumulate_item<WT, HALF, NQ>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst,
                                 marg + (size_t)item * WT);
 }
 
 // Batch launch: every item names its job; the job table carries the room.
-template <int WT, bool HALF>
+template <int WT, bool HALF, int NQ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
@@ -839,7 +851,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void ac
   float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
                                         : part + (size_t)it.slot * TILE;
   const AxisOrigin org = origin[grir];
-  accumulate_item<WT, HALF>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab,
+  accumulate_item<WT, HALF, NQ>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab,
                                 org, valid[grir] != 0, dst, marg + (size_t)it.mslot * MARG_STRIDE);
 }
 
@@ -922,6 +934,10 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restr
 // ---------------------------------------------------------------------------
 // Launchers (called from ism_host.cpp).
 // ---------------------------------------------------------------------------
+// Staged images per step (lane groups of 64 / NQ lanes). Two (half-waves) is
+// the measured best: four images per step halve the broadcast reads per tap
+// but need four LDS tiles and more registers per wave, and ran 12 % slower.
+constexpr int images_per_step(int wt, bool half) { return (void)wt, (void)half, 2; }
 int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
                   int *valid, int n_rir, hipStream_t st) {
   const int64_t total = (int64_t)n_rir * ra.n_tab;
@@ -936,7 +952,7 @@ template <int WT, bool HALF>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                         const AxisOrigin *origin, const int *valid, float *out, float *part, float *marg,
                         hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_kernel<WT, HALF>), dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin,
+  hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF)>), dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin,
                      valid, out, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -963,7 +979,7 @@ int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa,
 template <int WT, bool HALF>
 static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
                               const AxisOrigin *origin, const int *valid, float *part, float *marg, hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
+  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF)>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
                      origin, valid, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
