@@ -31,7 +31,7 @@ FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz
 # rocprofv3 summaries holding the calibrated HBM traffic of the timed kernel,
 # valid while the kernel sources hash to the value recorded beside it
 TRAFFIC_PROFILES = {"room_32_receivers": "profiles/accumulate_kernel_room_4x5x3_32rcv.md"}
-KERNEL_SOURCES = ("ism_device.hip", "ism_host.cpp", "ism_internal.h")
+KERNEL_SOURCES = ("ism_device.hip", "ism_host.cpp", "ism_internal.h", "ism_tuning.h")
 
 
 class _HipEvents:

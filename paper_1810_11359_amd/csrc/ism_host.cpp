@@ -13,6 +13,7 @@
 
 #include "ism.h"
 #include "ism_internal.h"
+#include "ism_tuning.h"
 
 namespace ism {
 int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
@@ -71,16 +72,26 @@ struct Plan {
   size_t off_valid, off_origin, off_tab, off_part, off_marg, ws_bytes;
 };
 
-// Work-item size in estimated taps. A launch should hold about kBalanceItems
+// Work-item size in estimated taps. A launch should hold about balance_items
 // items (some eight per resident wave) so that the largest-first order keeps
-// every CU busy to the end; small calls keep items of kMinItemTaps. The
-// environment variable ISM_TARGET_TAPS fixes the size (tests use it to change
-// the split).
+// every CU busy to the end; small calls keep items of min_item_taps. Both come
+// from the tuning table (ism_tuning.h) for the window and precision. The
+// environment variables ISM_TARGET_TAPS (a fixed size; tests use it to change
+// the split), ISM_ITEM_MIN_TAPS and ISM_ITEM_BALANCE (used by the tuner)
+// override them.
 constexpr double kMinItemTaps = 1.2e5;
 constexpr double kBalanceItems = 49152.0;
-double item_target(double total_taps) {
+double item_target(double total_taps, int wt, bool half) {
   if (const char *e = std::getenv("ISM_TARGET_TAPS")) return std::max(1e3, std::atof(e));
-  return std::max(kMinItemTaps, total_taps / kBalanceItems);
+  double min_taps = kMinItemTaps, balance = kBalanceItems;
+  for (const ItemTuning &t : kItemTuning)
+    if (t.wt == wt && t.half == (half ? 1 : 0)) {
+      min_taps = t.min_item_taps;
+      balance = t.balance_items;
+    }
+  if (const char *e = std::getenv("ISM_ITEM_MIN_TAPS")) min_taps = std::max(1e3, std::atof(e));
+  if (const char *e = std::getenv("ISM_ITEM_BALANCE")) balance = std::max(1.0, std::atof(e));
+  return std::max(min_taps, total_taps / balance);
 }
 
 // target <= 0: item size chosen from this call's own estimated work.
@@ -139,7 +150,7 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, d
     p.tile_taps[t] = imgs * W;
     p.total_taps += p.tile_taps[t] * p.n_rir;
   }
-  if (!(target > 0.0)) target = item_target(p.total_taps);
+  if (!(target > 0.0)) target = item_target(p.total_taps, p.wt, p.half);
   p.any_split = false;
   for (int t = 0; t < pa.n_tiles; ++t) {
     const double taps = p.tile_taps[t];

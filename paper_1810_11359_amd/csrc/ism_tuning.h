@@ -1,0 +1,40 @@
+// Work-item schedule per window length and tap precision, read by the host
+// planner. Written by paper_1810_11359_amd/autotune.py from timings on the
+// target GPU (AMD Radeon Graphics).
+//   min_item_taps  estimated taps of the smallest work item
+//   balance_items  items a large call is split into (about eight per
+//                  resident wave), which sets the item size of large calls
+//
+// Score: geometric mean over the class's workloads of kernel time relative
+// to the fastest pair on that workload (1.0 = fastest everywhere).
+// W=32 fp16 (room_4x5x3_32rcv_8k): best 60000 / 98304, score 1.0000, default 1.2e5 / 49152 score 1.1346
+// W=32 fp32 (room_4x5x3_32rcv_8k): best 60000 / 98304, score 1.0000, default 1.2e5 / 49152 score 1.0508
+// W=64 fp16 (room_4x5x3_32rcv_16k, batch_256_rooms_16k): best 60000 / 49152, score 1.0226, default 1.2e5 / 49152 score 1.0293
+// W=64 fp32 (room_4x5x3_32rcv_16k, batch_256_rooms_16k): best 120000 / 98304, score 1.0067, default 1.2e5 / 49152 score 1.0211
+// W=96 fp16 (room_6x9x3.5_uca64_48k): best 120000 / 49152, score 1.0000, default 1.2e5 / 49152 score 1.0000
+// W=96 fp32 (room_6x9x3.5_uca64_48k): best 240000 / 24576, score 1.0000, default 1.2e5 / 49152 score 1.0021
+// W=128 fp16 (room_4x5x3_16rcv_32k): best 60000 / 98304, score 1.0000, default 1.2e5 / 49152 score 1.1273
+// W=128 fp32 (room_4x5x3_16rcv_32k): best 60000 / 24576, score 1.0000, default 1.2e5 / 49152 score 1.1556
+#pragma once
+
+namespace ism {
+
+struct ItemTuning {
+  int wt;        // window length in samples
+  int half;      // 1: FP16 taps, 0: FP32 taps
+  double min_item_taps;
+  double balance_items;
+};
+
+constexpr ItemTuning kItemTuning[] = {
+    {32, 1, 60000, 98304.0},
+    {32, 0, 60000, 98304.0},
+    {64, 1, 60000, 49152.0},
+    {64, 0, 120000, 98304.0},
+    {96, 1, 120000, 49152.0},
+    {96, 0, 240000, 24576.0},
+    {128, 1, 60000, 98304.0},
+    {128, 0, 60000, 24576.0},
+};
+
+}  // namespace ism

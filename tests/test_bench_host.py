@@ -20,3 +20,20 @@ def test_traffic_only_for_the_profiled_kernel_sources(monkeypatch):
     assert bench.measured_traffic("room_32_receivers", "fp16") is None
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
     assert bench.measured_traffic("room_32_receivers", "fp32") is None
+
+
+def test_tuner_header_round_trip(tmp_path):
+    """The tuner's header lists one entry per (window, precision) with the chosen pair."""
+    from paper_1810_11359_amd import autotune
+
+    res = {}
+    for wt in (32, 64):
+        for prec in ("fp32", "fp16"):
+            score = {(mt, bal): 1.0 + 0.01 * i for i, (mt, bal) in
+                     enumerate((a, b) for a in autotune.MIN_TAPS for b in autotune.BALANCE)}
+            res[(wt, prec)] = ((autotune.MIN_TAPS[0], autotune.BALANCE[0]), score, {}, ["w"])
+    p = tmp_path / "ism_tuning.h"
+    autotune.write_header(res, str(p), "test device")
+    text = p.read_text()
+    assert text.count("{32, 0, 60000, 24576.0}") == 1 and text.count("{64, 1, 60000, 24576.0}") == 1
+    assert "constexpr ItemTuning kItemTuning[]" in text
