@@ -621,9 +621,13 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   constexpr int SCAP = 64 + 3 * NQ;
   static_assert(WT % LPG == 0, "window must be a multiple of the lanes per image");
 
+  // FP32 bases of the staged images by lane group and step: image k is slot
+  // k / NQ of group k % NQ, so the two bases of one loop iteration are adjacent
+  constexpr int SLOTS = (SCAP / NQ + 1) & ~1;
+  typedef int int2v __attribute__((ext_vector_type(2)));
   __shared__ float tile[NQ][LSPAN];
-  __shared__ f4v stp[SCAP];             // staged records (ImageParams::rec)
-  __shared__ int stb[HALF ? 1 : SCAP];  // FP32: their bases (FP16 records carry the base)
+  __shared__ f4v stp[SCAP];                                 // staged records (ImageParams::rec)
+  __shared__ int2v stb[HALF ? 1 : NQ][HALF ? 1 : SLOTS / 2];  // FP32 bases (FP16 records carry the base)
   __shared__ EnumLds es;
 
   const int lane = threadIdx.x & 63;
@@ -715,9 +719,19 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       }
     }
   };
-  auto base_of = [&](const f4v &P, int k) { return HALF ? __float_as_int(P.w) : stb[k]; };
   // staged record k (read as one 16-byte access: see step)
   auto rec = [&](int k) { return stp[k]; };
+  // bases of this group's images for steps s and s + 1 (s even)
+  auto bases = [&](int s) { return HALF ? int2v{0, 0} : stb[HALF ? 0 : h][HALF ? 0 : s / 2]; };
+  auto set_base = [&](int k, int b) {
+    if constexpr (!HALF) reinterpret_cast<int *>(&stb[k % NQ][0])[k / NQ] = b;
+  };
+  auto get_base = [&](int k) {
+    if constexpr (HALF) return 0;
+    else return reinterpret_cast<const int *>(&stb[k % NQ][0])[k / NQ];
+  };
+  // base of the image with record P whose FP32 base is b
+  auto pick = [&](const f4v &P, int b) { return HALF ? __float_as_int(P.w) : b; };
 
   int ns = 0;  // staged images (wave-uniform)
   enumerate_shell(g, tx, ty, ay, az, es, [&](int qn) {
@@ -743,26 +757,38 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
       if (p.ok) {
         stp[ns + rank] = p.rec;
-        if constexpr (!HALF) stb[ns + rank] = p.base;
+        set_base(ns + rank, p.base);
       }
       ns += __builtin_popcountll(okm);
       wave_sync();
       // lanes = taps: NQ staged images per step, one per lane group; the next
-      // step's parameters are read ahead of this step's tile update (reads
-      // ahead stay inside the stage: indices < NQ (np + 2) <= SCAP)
+      // step's parameters are read ahead of this step's tile update. Four
+      // steps per iteration, so the two base pairs alternate without copies
+      // (reads ahead stay inside the stage: record indices < NQ (np + 1) + h,
+      // base slots < np + 4 <= SLOTS)
       const int np = ns / NQ;
       f4v PA = rec(h);
-      int bA = base_of(PA, h);
-      for (int s = 0; s < np; s += 2) {
+      int2v bbA = bases(0);
+      for (int s = 0; s < np; s += 4) {
         const f4v PB = rec(NQ * (s + 1) + h);
-        const int bB = base_of(PB, NQ * (s + 1) + h);
+        const int2v bbB = bases(s + 2);
         __builtin_amdgcn_sched_barrier(0);  // keep the read-ahead in front of the step
-        step(PA, bA);
+        step(PA, pick(PA, bbA.x));
         if (s + 1 < np) {
-          PA = rec(NQ * (s + 2) + h);
-          bA = base_of(PA, NQ * (s + 2) + h);
+          const f4v PC = rec(NQ * (s + 2) + h);
           __builtin_amdgcn_sched_barrier(0);
-          step(PB, bB);
+          step(PB, pick(PB, bbA.y));
+          if (s + 2 < np) {
+            const f4v PD = rec(NQ * (s + 3) + h);
+            __builtin_amdgcn_sched_barrier(0);
+            step(PC, pick(PC, bbB.x));
+            if (s + 3 < np) {
+              PA = rec(NQ * (s + 4) + h);
+              bbA = bases(s + 4);
+              __builtin_amdgcn_sched_barrier(0);
+              step(PD, pick(PD, bbB.y));
+            }
+          }
         }
       }
       // carry the remaining images to the front of the stage (the ranges do
@@ -773,19 +799,19 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         int b = 0;
         if (lane < rem) {
           P = stp[NQ * np + lane];
-          if constexpr (!HALF) b = stb[NQ * np + lane];
+          b = get_base(NQ * np + lane);
         }
         wave_sync();
         if (lane < rem) {
           stp[lane] = P;
-          if constexpr (!HALF) stb[lane] = b;
+          set_base(lane, b);
         }
       }
       ns = rem;
       wave_sync();
     }
   });
-  if (h < ns) step(stp[h], base_of(stp[h], h));  // last images, fewer than NQ
+  if (h < ns) step(stp[h], pick(stp[h], get_base(h)));  // last images, fewer than NQ
 
   wave_sync();
   write_item<WT, NQ>(tile, n_own, dst, marg, lane, 64);
