@@ -212,7 +212,7 @@ __device__ __forceinline__ AxisEntry table_entry(const RoomArgs &ra, const float
                                                  const float *__restrict__ r3, int e) {
   const int a = e < ra.off[1] ? 0 : (e < ra.off[2] ? 1 : 2);
   const int n = ra.lo[a] + (e - ra.off[a]);
-  const float s = s3[a], r = r3[a];
+  const float s = s3[ra.perm[a]], r = r3[ra.perm[a]];
   // Eq. (1): even n -> n L + s, odd n -> (n + 1) L - s.
   const bool odd = (n & 1) != 0;
   const float m = (float)(odd ? n + 1 : n);
@@ -244,7 +244,7 @@ __device__ __forceinline__ int rir_header(const RoomArgs &ra, const float *__res
                                           const float *__restrict__ r3, AxisOrigin &o) {
   bool ok = true, same = true;
   for (int b = 0; b < 3; ++b) {
-    const float sb = s3[b], rb = r3[b];
+    const float sb = s3[ra.perm[b]], rb = r3[ra.perm[b]];
     ok = ok && sb > 0.0f && (sb - ra.L_hi[b]) < ra.L_lo[b] && rb > 0.0f && (rb - ra.L_hi[b]) < ra.L_lo[b];
     same = same && (sb == rb);
     o.e_even[b] = (sb - rb) * ra.q_hi;

@@ -111,17 +111,23 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, d
 
   RoomArgs &ra = p.ra;
   std::memset(&ra, 0, sizeof(ra));
+  // table axes: room axes by decreasing length (stable), shortest innermost
+  int perm[3] = {0, 1, 2};
+  std::stable_sort(perm, perm + 3, [&](int a, int b) { return r->room[a] > r->room[b]; });
   int off = 0;
-  for (int a = 0; a < 3; ++a) {
-    split(r->room[a], ra.L_hi[a], ra.L_lo[a]);
-    ra.lo[a] = lattice_lo(r->n_img[a]);
-    ra.N[a] = r->n_img[a];
-    ra.off[a] = off;
+  for (int k = 0; k < 3; ++k) {
+    const int a = perm[k];
+    ra.perm[k] = a;
+    split(r->room[a], ra.L_hi[k], ra.L_lo[k]);
+    ra.lo[k] = lattice_lo(r->n_img[a]);
+    ra.N[k] = r->n_img[a];
+    ra.off[k] = off;
     off += r->n_img[a];
-    ra.period[a] = (float)(2.0 * r->room[a] * q);
-    ra.inv_period[a] = (float)(1.0 / (2.0 * r->room[a] * q));
+    ra.period[k] = (float)(2.0 * r->room[a] * q);
+    ra.inv_period[k] = (float)(1.0 / (2.0 * r->room[a] * q));
+    ra.beta[2 * k] = (float)r->beta[2 * a];
+    ra.beta[2 * k + 1] = (float)r->beta[2 * a + 1];
   }
-  for (int i = 0; i < 6; ++i) ra.beta[i] = (float)r->beta[i];
   ra.n_tab = off;
   split(q, ra.q_hi, ra.q_lo);
   ra.kappa = (float)(r->fs / (4.0 * kPi * r->c));

@@ -22,8 +22,12 @@ constexpr int MAX_CHUNKS = 255;
 
 // Per-call room constants, passed by value as a kernel argument. Lengths are in
 // metres, delays in samples. Float-float pairs (hi, lo) carry double-precision
-// host values into FP32-only device arithmetic.
+// host values into FP32-only device arithmetic. The per-axis arrays are in
+// table-axis order: table axis k is room axis perm[k], with the room's
+// shortest side last (the innermost enumeration axis, whose columns then
+// hold the most images).
 struct RoomArgs {
+  int perm[3];             // room axis of each table axis
   float L_hi[3], L_lo[3];  // room size
   float beta[6];           // x0, x1, y0, y1, z0, z1
   int lo[3];               // first lattice index ceil(-N/2) per axis
