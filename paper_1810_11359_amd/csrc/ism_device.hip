@@ -173,37 +173,6 @@ constexpr SincPoly<WT> make_sinc_poly() {
   return P;
 }
 
-// sin(pi h) / pi for h in [0, 1/2]: Taylor series of sin to the h^13 term
-// (truncation < 2e-10 at h = 1/2), Horner in h^2.
-__device__ __forceinline__ float sinpi_over_pi(float h) {
-  constexpr float c1 = (float)(-kPi * kPi / 6.0);
-  constexpr float c2 = (float)(kPi * kPi * kPi * kPi / 120.0);
-  constexpr float c3 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi / 5040.0);
-  constexpr float c4 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 362880.0);
-  constexpr float c5 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 39916800.0);
-  constexpr float c6 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 6227020800.0);
-  const float u = h * h;
-  float p = __builtin_fmaf(u, c6, c5);
-  p = __builtin_fmaf(u, p, c4);
-  p = __builtin_fmaf(u, p, c3);
-  p = __builtin_fmaf(u, p, c2);
-  p = __builtin_fmaf(u, p, c1);
-  p = __builtin_fmaf(u, p, 1.0f);
-  return h * p;
-}
-// cos and sin of a small angle |phi| <= 0.2 (Taylor, truncation < 3e-12).
-__device__ __forceinline__ void small_sincos(float phi, float &s, float &c) {
-  const float u = phi * phi;
-  float pc = __builtin_fmaf(u, (float)(1.0 / 40320.0), (float)(-1.0 / 720.0));
-  pc = __builtin_fmaf(u, pc, (float)(1.0 / 24.0));
-  pc = __builtin_fmaf(u, pc, -0.5f);
-  c = __builtin_fmaf(u, pc, 1.0f);
-  float ps = __builtin_fmaf(u, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
-  ps = __builtin_fmaf(u, ps, (float)(1.0 / 120.0));
-  ps = __builtin_fmaf(u, ps, (float)(-1.0 / 6.0));
-  s = __builtin_fmaf(phi * u, ps, phi);
-}
-
 // ---------------------------------------------------------------------------
 // Kernel 1: per-RIR axis tables.
 // ---------------------------------------------------------------------------
@@ -313,35 +282,35 @@ __device__ __forceinline__ void wave_sync() {
 
 // Image displacements along one axis are strictly increasing in the lattice
 // index n: even n = 2m at m P + e_even, odd n = 2m - 1 at m P + e_odd (P = 2 L q).
-// first_ge returns the table index (n - lo) of the first n with displacement
-// >= b, or N if there is none. Float rounding can move the answer by one index
-// only for images within ~1e-3 samples of b; callers widen their bounds by a
-// sample so such images lie outside the band that matters.
+// The table index (n - lo) of the first n with displacement >= b is therefore
+// the number of images below b, which first_ge counts family by family:
+// family f holds M_f images m = m0_f .. m0_f + M_f - 1, of which
+// clamp(ceil((b - e_f) / P) - m0_f, 0, M_f) lie below b. Float rounding can
+// move the count by one only for images within ~1e-2 samples of b; callers
+// widen their bounds by a sample so such images lie outside the band that
+// matters. first_ge is monotone in b and a pure function of it, so equal
+// bounds split a range exactly.
 struct AxisRange {
-  int lo, N;
-  float inv_p, e_even, e_odd;
+  float inv_p;            // 1 / P
+  float c_even, c_odd;    // -(e_f / P + m0_f)
+  float n_even, n_odd;    // M_f
 };
-__device__ __forceinline__ int family_first(float b, float e, float inv_p, int m_lo, int m_hi) {
-  // smallest m in [m_lo, m_hi] with m P + e >= b, or m_hi + 1
-  const float mf = ceilf((b - e) * inv_p);
-  if (!(mf > (float)m_lo)) return m_lo;  // also -inf
-  if (mf > (float)(m_hi + 1)) return m_hi + 1;
-  return (int)mf;
+__device__ __forceinline__ AxisRange axis_range(int lo, int N, float inv_p, float e_even, float e_odd) {
+  const int hi = lo + N;  // exclusive
+  const int me0 = (lo + 1) >> 1, me1 = (hi - 1) >> 1;  // even n = 2m in [lo, hi)
+  const int mo0 = (lo + 2) >> 1, mo1 = hi >> 1;        // odd n = 2m - 1 in [lo, hi)
+  AxisRange a;
+  a.inv_p = inv_p;
+  a.c_even = -__builtin_fmaf(e_even, inv_p, (float)me0);
+  a.c_odd = -__builtin_fmaf(e_odd, inv_p, (float)mo0);
+  a.n_even = (float)max(me1 - me0 + 1, 0);
+  a.n_odd = (float)max(mo1 - mo0 + 1, 0);
+  return a;
 }
 __device__ __forceinline__ int first_ge(const AxisRange &a, float b) {
-  const int hi = a.lo + a.N;  // exclusive
-  int best = hi;
-  const int me_lo = (a.lo + 1) >> 1, me_hi = (hi - 1) >> 1;  // even n = 2m in [lo, hi)
-  if (me_lo <= me_hi) {
-    const int m = family_first(b, a.e_even, a.inv_p, me_lo, me_hi);
-    if (m <= me_hi) best = min(best, 2 * m);
-  }
-  const int mo_lo = (a.lo + 2) >> 1, mo_hi = hi >> 1;  // odd n = 2m - 1 in [lo, hi)
-  if (mo_lo <= mo_hi) {
-    const int m = family_first(b, a.e_odd, a.inv_p, mo_lo, mo_hi);
-    if (m <= mo_hi) best = min(best, 2 * m - 1);
-  }
-  return best - a.lo;
+  const float ce = fminf(fmaxf(ceilf(__builtin_fmaf(b, a.inv_p, a.c_even)), 0.0f), a.n_even);
+  const float co = fminf(fmaxf(ceilf(__builtin_fmaf(b, a.inv_p, a.c_odd)), 0.0f), a.n_odd);
+  return (int)(ce + co);
 }
 
 // ---------------------------------------------------------------------------
@@ -352,17 +321,15 @@ __device__ __forceinline__ int first_ge(const AxisRange &a, float b) {
 // and hands the queue to a consumer that turns candidates into image
 // parameters (delay, amplitude; lanes = images) and adds their taps.
 //
-// FP32 consumer (lanes = taps): the candidates' parameters are staged in LDS;
-// each half-wave then takes one staged image per step and its 32 lanes add
-// W/32 taps each into the half-wave's own FP32 tile. All addresses of one
-// step are distinct and consecutive, so there are no bank conflicts and no
-// lost updates; steps of a half-wave reach LDS in program order.
+// Tap consumer (lanes = taps, both precisions): the candidates' parameters
+// are staged in LDS; each half-wave then takes one staged image per step and
+// its 32 lanes add W/32 taps each into the half-wave's own FP32 tile. All
+// addresses of one step are distinct and consecutive, so there are no bank
+// conflicts and no lost updates; steps of a half-wave reach LDS in program
+// order. FP32 taps divide by the sinc argument; FP16 taps evaluate a
+// per-tap polynomial in packed FP16.
 //
-// FP16 consumer (lanes = images): each lane adds all taps of its image, one
-// tap per instruction, into the wave's tile; a byte claim per position keeps
-// the active lanes of one instruction on distinct positions.
-//
-// Both end with a fixed-order sum of the tiles, so results are bitwise
+// Items end with a fixed-order sum of the tiles, so results are bitwise
 // reproducible.
 // ---------------------------------------------------------------------------
 constexpr int QCAP = 256;  // per-wave queue of candidate images
@@ -408,11 +375,13 @@ __device__ __forceinline__ ItemGeom item_geom(const RoomArgs &ra, const AxisRang
 
 // Walks the shell of the item. For every filled queue chunk (entries
 // [0, qn) of es.queue, with the column data of the current batch in es.col_*)
-// calls consume(qn), which must use up all qn entries.
+// calls consume(qn), which must use up all qn entries. col_g holds the column's
+// gain factor times gscale.
 template <class Consume>
 __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEntry *__restrict__ tx,
                                                 const AxisEntry *__restrict__ ty, const AxisRange &ay,
-                                                const AxisRange &az, EnumLds &es, Consume &&consume) {
+                                                const AxisRange &az, const float gscale, EnumLds &es,
+                                                Consume &&consume) {
   const int lane = threadIdx.x & 63;
   for (int nx0 = g.nx_a; nx0 < g.nx_b; nx0 += 64) {
     // lanes = x indices: y range of the columns that reach the outer sphere
@@ -454,7 +423,7 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
         fast_two_sum(sh, sl, sh, sl);
         es.col_sh[lane] = sh;
         es.col_sl[lane] = sl;
-        es.col_g[lane] = ex.gain * ey.gain;
+        es.col_g[lane] = (ex.gain * ey.gain) * gscale;
         float rh, rl;
         ff_sub(g.r1h, g.r1l, sh, sl, rh, rl);
         if (rh > 0.0f) {
@@ -465,15 +434,12 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
             ff_sub(g.r0h, g.r0l, sh, sl, hh, hl);
             if (hh > 0.0f) zmin = fmaxf(__builtin_sqrtf(hh) - 1.0f, 0.0f);
           }
-          if (zmin > 0.0f) {
-            z1 = first_ge(az, -zmax);
-            n1 = max(first_ge(az, -zmin) - z1, 0);
-            z2 = first_ge(az, zmin);
-            n2 = max(first_ge(az, zmax) - z2, 0);
-          } else {
-            z1 = first_ge(az, -zmax);
-            n1 = max(first_ge(az, zmax) - z1, 0);
-          }
+          // displacements in [-zmax, -zmin) and [zmin, zmax): two runs of the
+          // table (contiguous when zmin = 0)
+          z1 = first_ge(az, -zmax);
+          n1 = first_ge(az, -zmin) - z1;
+          z2 = first_ge(az, zmin);
+          n2 = first_ge(az, zmax) - z2;
         }
       }
       const int cnt = n1 + n2;
@@ -507,11 +473,17 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 //   FP32: (f, CP, CQ, C/2) with C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W),
 //         CQ = C/2 sin(2 pi f/W);
 //   FP16: (t, t) in packed FP16 with t = f - 1/2, A, A t, base.
+// The column gain in es.col_g carries the constant factor of A: fs / (4 pi c)
+// for FP16, and fs / (4 pi c) / (2 pi) for FP32, whose record holds C/2.
 struct ImageParams {
   bool ok;
   int base;
   f4v rec;
 };
+template <bool HALF>
+__device__ __forceinline__ float column_gain_scale(const RoomArgs &ra) {
+  return HALF ? ra.kappa : ra.kappa * (float)(0.5 / kPi);
+}
 template <int WT, bool HALF>
 __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const ItemGeom &g, const EnumLds &es,
                                                     const AxisEntry ez, uint32_t ent) {
@@ -537,19 +509,20 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
   const int k0 = (int)kf;
   p.base = k0 - g.T0;
   p.ok = (x0 < 1.0e9f) && (uint32_t)p.base < (uint32_t)(g.K1 - g.T0);
-  // Eq. (4) amplitude and the per-image factors of the taps
-  const float A = es.col_g[cl] * ez.gain * ra.kappa * rx;
+  // Eq. (4) amplitude (times the constant factor carried by the column gain)
+  const float A = (es.col_g[cl] * ez.gain) * rx;
   if constexpr (HALF) {
     const float t = fr - 0.5f;
     const half2_t th = {(_Float16)t, (_Float16)t};
     p.rec = f4v{__builtin_bit_cast(float, th), A, A * t, __int_as_float(p.base)};
   } else {
+    // The hardware sine and cosine take the angle in turns; their relative
+    // error (< 1e-6, also for the tiny angles of f near 0 or 1) enters each
+    // tap of the image once. sin(pi f) is taken as sin(pi min(f, 1 - f)).
     const float f = fmaxf(fr, 0x1p-100f);
-    const float Cc = A * sinpi_over_pi(fminf(f, 1.0f - f));
-    float sp, cp;
-    small_sincos(f * ra.two_pi_over_w, sp, cp);
-    const float C2 = 0.5f * Cc;
-    p.rec = f4v{f, C2 * cp, C2 * sp, C2};
+    const float C2 = A * __builtin_amdgcn_sinf(0.5f * fminf(f, 1.0f - f));
+    const float turn = f * (1.0f / (float)WT);
+    p.rec = f4v{f, C2 * __builtin_amdgcn_cosf(turn), C2 * __builtin_amdgcn_sinf(turn), C2};
   }
   return p;
 }
@@ -640,9 +613,9 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   const AxisEntry *__restrict__ tx = tab + ra.off[0];
   const AxisEntry *__restrict__ ty = tab + ra.off[1];
   const AxisEntry *__restrict__ tz = tab + ra.off[2];
-  const AxisRange ax{ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]};
-  const AxisRange ay{ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]};
-  const AxisRange az{ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]};
+  const AxisRange ax = axis_range(ra.lo[0], ra.N[0], ra.inv_period[0], org.e_even[0], org.e_odd[0]);
+  const AxisRange ay = axis_range(ra.lo[1], ra.N[1], ra.inv_period[1], org.e_even[1], org.e_odd[1]);
+  const AxisRange az = axis_range(ra.lo[2], ra.N[2], ra.inv_period[2], org.e_even[2], org.e_odd[2]);
   const ItemGeom g = item_geom(ra, ax, tile_id, C, c);
 
   // per-lane tap constants
@@ -734,7 +707,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   auto pick = [&](const f4v &P, int b) { return HALF ? __float_as_int(P.w) : b; };
 
   int ns = 0;  // staged images (wave-uniform)
-  enumerate_shell(g, tx, ty, ay, az, es, [&](int qn) {
+  enumerate_shell(g, tx, ty, ay, az, column_gain_scale<HALF>(ra), es, [&](int qn) {
     // queue entries and z table rows are read one chunk of 64 ahead
     uint32_t ent = 0;
     AxisEntry ez{0.0f, 0.0f, 0.0f, 0.0f};

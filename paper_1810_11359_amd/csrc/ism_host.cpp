@@ -131,7 +131,6 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, d
   ra.n_tab = off;
   split(q, ra.q_hi, ra.q_lo);
   ra.kappa = (float)(r->fs / (4.0 * kPi * r->c));
-  ra.two_pi_over_w = (float)(2.0 * kPi / W);
   ra.half_w = (float)(W / 2.0);
   ra.n_samples = (int)nS;
   ra.k_end = (int)nS + p.wt / 2 - 1;

@@ -36,7 +36,6 @@ struct RoomArgs {
   int n_tab;               // Nx + Ny + Nz
   float q_hi, q_lo;        // fs / c [samples per metre]
   float kappa;             // fs / (4 pi c): A = gain * kappa / x with x in samples
-  float two_pi_over_w;     // 2 pi / W
   float half_w;            // W / 2
   int n_samples;           // nS
   int k_end;               // nS + W/2 - 1: images with k0 >= k_end add nothing
