@@ -469,9 +469,11 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // Parameters of one image candidate (queue entry ent). ok is false when the
 // tile does not own the image. base = k0 - T0 is the tile-local LDS index of its
 // tap j = 1 - W/2 (the LDS tile starts at sample T0 + 1 - W/2). rec is the
-// staged record of the taps:
-//   FP32: (f, CP, CQ, C/2) with C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W),
-//         CQ = C/2 sin(2 pi f/W);
+// staged record of the taps, which also carries the base:
+//   FP32: (F, CP, CQ, C/2) with F = fq 2^8 + base (bits of a uint32), fq the
+//         fraction in units of 2^-24; the taps use f = float(F) 2^-32, and
+//         C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W), CQ = C/2 sin(2 pi f/W)
+//         follow from that same f;
 //   FP16: (t, t) in packed FP16 with t = f - 1/2, A, A t, base.
 // The column gain in es.col_g carries the constant factor of A: fs / (4 pi c)
 // for FP16, and fs / (4 pi c) / (2 pi) for FP32, whose record holds C/2.
@@ -516,13 +518,18 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
     const half2_t th = {(_Float16)t, (_Float16)t};
     p.rec = f4v{__builtin_bit_cast(float, th), A, A * t, __int_as_float(p.base)};
   } else {
+    // 24-bit fraction fq in [1, 2^24 - 2] (rounding moves the delay by at
+    // most 3e-8 samples) and the base in the low byte; float(F) rounds F to
+    // 24 bits, so f = float(F) 2^-32 lies in [2^-24, 1 - 2^-24].
+    const uint32_t fq = min(max((uint32_t)__builtin_rintf(fr * 0x1p24f), 1u), (1u << 24) - 2u);
+    const uint32_t F = (fq << 8) | ((uint32_t)p.base & 0xffu);
+    const float f = (float)F * 0x1p-32f;
     // The hardware sine and cosine take the angle in turns; their relative
     // error (< 1e-6, also for the tiny angles of f near 0 or 1) enters each
     // tap of the image once. sin(pi f) is taken as sin(pi min(f, 1 - f)).
-    const float f = fmaxf(fr, 0x1p-100f);
     const float C2 = A * __builtin_amdgcn_sinf(0.5f * fminf(f, 1.0f - f));
     const float turn = f * (1.0f / (float)WT);
-    p.rec = f4v{f, C2 * __builtin_amdgcn_cosf(turn), C2 * __builtin_amdgcn_sinf(turn), C2};
+    p.rec = f4v{__uint_as_float(F), C2 * __builtin_amdgcn_cosf(turn), C2 * __builtin_amdgcn_sinf(turn), C2};
   }
   return p;
 }
@@ -594,13 +601,8 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   constexpr int SCAP = 64 + 3 * NQ;
   static_assert(WT % LPG == 0, "window must be a multiple of the lanes per image");
 
-  // FP32 bases of the staged images by lane group and step: image k is slot
-  // k / NQ of group k % NQ, so the two bases of one loop iteration are adjacent
-  constexpr int SLOTS = (SCAP / NQ + 1) & ~1;
-  typedef int int2v __attribute__((ext_vector_type(2)));
   __shared__ float tile[NQ][LSPAN];
-  __shared__ f4v stp[SCAP];                                 // staged records (ImageParams::rec)
-  __shared__ int2v stb[HALF ? 1 : NQ][HALF ? 1 : SLOTS / 2];  // FP32 bases (FP16 records carry the base)
+  __shared__ f4v stp[SCAP];  // staged records (ImageParams::rec)
   __shared__ EnumLds es;
 
   const int lane = threadIdx.x & 63;
@@ -639,7 +641,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     const TapConsts<WT> &K = tap_table<WT>();
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
-      nsg[m] = -K.sig[l + LPG * m];
+      nsg[m] = -K.sig[l + LPG * m] * 0x1p-32f;  // times float(F) = f 2^32
       sgj[m] = K.sig_j[l + LPG * m];
       cth[m] = K.cth[l + LPG * m];
       sth[m] = K.sth[l + LPG * m];
@@ -648,11 +650,12 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   for (int i = lane; i < NQ * LSPAN; i += 64) (&tile[0][0])[i] = 0.0f;
   float *const th = &tile[h][l];
 
-  // One step: staged image (record P, base b) on this lane group, taps l + LPG m.
+  // One step: staged image (record P) on this lane group, taps l + LPG m.
   // The empty asm consumes the record as one 128-bit value where the step
   // starts, which keeps its LDS read a single ds_read_b128 issued ahead.
-  auto step = [&](const f4v P, const int b) {
+  auto step = [&](const f4v P) {
     __asm__ volatile("" ::"v"(P));
+    const int b = HALF ? __float_as_int(P.w) : (int)(__float_as_uint(P.x) & 0xffu);
     float *t = th + b;
     if constexpr (HALF) {
       // tap = A c0 + (A t) q(t), q in packed FP16 two taps at a time
@@ -684,9 +687,10 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
           w[m] = __builtin_fmaf(sth[m], P.z, w[m]);
         }
       }
+      const float fs = (float)__float_as_uint(P.x);  // f 2^32
 #pragma unroll
       for (int m = 0; m < TPL; ++m) {
-        const float u = __builtin_fmaf(nsg[m], P.x, sgj[m]);
+        const float u = __builtin_fmaf(nsg[m], fs, sgj[m]);
         const float r = __builtin_amdgcn_rcpf(u);
         t[LPG * m] = __builtin_fmaf(w[m], r, t[LPG * m]);
       }
@@ -694,17 +698,6 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   };
   // staged record k (read as one 16-byte access: see step)
   auto rec = [&](int k) { return stp[k]; };
-  // bases of this group's images for steps s and s + 1 (s even)
-  auto bases = [&](int s) { return HALF ? int2v{0, 0} : stb[HALF ? 0 : h][HALF ? 0 : s / 2]; };
-  auto set_base = [&](int k, int b) {
-    if constexpr (!HALF) reinterpret_cast<int *>(&stb[k % NQ][0])[k / NQ] = b;
-  };
-  auto get_base = [&](int k) {
-    if constexpr (HALF) return 0;
-    else return reinterpret_cast<const int *>(&stb[k % NQ][0])[k / NQ];
-  };
-  // base of the image with record P whose FP32 base is b
-  auto pick = [&](const f4v &P, int b) { return HALF ? __float_as_int(P.w) : b; };
 
   int ns = 0;  // staged images (wave-uniform)
   enumerate_shell(g, tx, ty, ay, az, column_gain_scale<HALF>(ra), es, [&](int qn) {
@@ -728,40 +721,22 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       if (q + lane < qn) p = image_params<WT, HALF>(ra, g, es, ez_c, ent_c);
       const uint64_t okm = __ballot(p.ok);
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
-      if (p.ok) {
-        stp[ns + rank] = p.rec;
-        set_base(ns + rank, p.base);
-      }
+      if (p.ok) stp[ns + rank] = p.rec;
       ns += __builtin_popcountll(okm);
       wave_sync();
       // lanes = taps: NQ staged images per step, one per lane group; the next
-      // step's parameters are read ahead of this step's tile update. Four
-      // steps per iteration, so the two base pairs alternate without copies
-      // (reads ahead stay inside the stage: record indices < NQ (np + 1) + h,
-      // base slots < np + 4 <= SLOTS)
+      // step's record is read ahead of this step's tile update (reads ahead
+      // stay inside the stage: indices < NQ (np + 1) + h <= SCAP)
       const int np = ns / NQ;
       f4v PA = rec(h);
-      int2v bbA = bases(0);
-      for (int s = 0; s < np; s += 4) {
+      for (int s = 0; s < np; s += 2) {
         const f4v PB = rec(NQ * (s + 1) + h);
-        const int2v bbB = bases(s + 2);
         __builtin_amdgcn_sched_barrier(0);  // keep the read-ahead in front of the step
-        step(PA, pick(PA, bbA.x));
+        step(PA);
         if (s + 1 < np) {
-          const f4v PC = rec(NQ * (s + 2) + h);
+          PA = rec(NQ * (s + 2) + h);
           __builtin_amdgcn_sched_barrier(0);
-          step(PB, pick(PB, bbA.y));
-          if (s + 2 < np) {
-            const f4v PD = rec(NQ * (s + 3) + h);
-            __builtin_amdgcn_sched_barrier(0);
-            step(PC, pick(PC, bbB.x));
-            if (s + 3 < np) {
-              PA = rec(NQ * (s + 4) + h);
-              bbA = bases(s + 4);
-              __builtin_amdgcn_sched_barrier(0);
-              step(PD, pick(PD, bbB.y));
-            }
-          }
+          step(PB);
         }
       }
       // carry the remaining images to the front of the stage (the ranges do
@@ -769,22 +744,15 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       const int rem = ns - NQ * np;
       if (np > 0 && rem > 0) {
         f4v P{};
-        int b = 0;
-        if (lane < rem) {
-          P = stp[NQ * np + lane];
-          b = get_base(NQ * np + lane);
-        }
+        if (lane < rem) P = stp[NQ * np + lane];
         wave_sync();
-        if (lane < rem) {
-          stp[lane] = P;
-          set_base(lane, b);
-        }
+        if (lane < rem) stp[lane] = P;
       }
       ns = rem;
       wave_sync();
     }
   });
-  if (h < ns) step(stp[h], pick(stp[h], get_base(h)));  // last images, fewer than NQ
+  if (h < ns) step(stp[h]);  // last images, fewer than NQ
 
   wave_sync();
   write_item<WT, NQ>(tile, n_own, dst, marg, lane, 64);
