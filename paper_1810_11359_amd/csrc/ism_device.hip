@@ -265,13 +265,16 @@ __global__ __launch_bounds__(256) void tables_batch_kernel(const JobDev *__restr
 // ---------------------------------------------------------------------------
 // Wave-level helpers.
 // ---------------------------------------------------------------------------
+// Inclusive prefix sum over the 64 lanes with DPP lane shifts (no LDS):
+// Hillis-Steele within each row of 16 lanes, then the row totals are carried
+// into the later rows by the row broadcasts of lanes 15 and 31.
 __device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
   return v;
 }
 __device__ __forceinline__ void wave_sync() {
