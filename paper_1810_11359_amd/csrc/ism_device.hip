@@ -20,6 +20,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "ism.h"
 #include "ism_internal.h"
 
 namespace ism {
@@ -341,8 +342,11 @@ constexpr int QCAP = 256;  // per-wave queue of candidate images
 struct EnumLds {
   uint32_t queue[QCAP];  // (column lane << 16) | table index of nz
   float col_sh[64], col_sl[64], col_g[64];
-  int nx_pref[64], nx_nylo[64];
+  // per x lane of the row batch: (first column << 11) | first y table index
+  // (column counts stay below 64 * 2048 = 2^17, table indices below 2^11)
+  uint32_t nx_col[64];
 };
+static_assert(ISM_MAX_N_IMG <= 2048, "nx_col packs y table indices in 11 bits");
 
 // Wave-uniform geometry of one work item.
 struct ItemGeom {
@@ -403,8 +407,7 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
     }
     const int incl_y = wave_incl_scan(ny_cnt);
     const int ncols = __builtin_amdgcn_readlane(incl_y, 63);
-    es.nx_pref[lane] = incl_y - ny_cnt;
-    es.nx_nylo[lane] = ny_lo;
+    es.nx_col[lane] = ((uint32_t)(incl_y - ny_cnt) << 11) | (uint32_t)ny_lo;
     wave_sync();
 
     for (int cb = 0; cb * 64 < ncols; ++cb) {
@@ -412,12 +415,15 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
       const int gcol = cb * 64 + lane;
       int z1 = 0, n1 = 0, z2 = 0, n2 = 0;
       if (gcol < ncols) {
+        // x lane of the column: the last one whose first column is <= gcol
+        const uint32_t key = ((uint32_t)gcol << 11) | 0x7ffu;
         int i = 0;
 #pragma unroll
         for (int step = 32; step > 0; step >>= 1)
-          if (i + step < 64 && es.nx_pref[i + step] <= gcol) i += step;
+          if (i + step < 64 && es.nx_col[i + step] <= key) i += step;
+        const uint32_t xc = es.nx_col[i];
         const AxisEntry ex = tx[nx0 + i];
-        const AxisEntry ey = ty[es.nx_nylo[i] + (gcol - es.nx_pref[i])];
+        const AxisEntry ey = ty[(int)(xc & 0x7ffu) + (gcol - (int)(xc >> 11))];
         float ah, al, bh, bl, sh, sl;
         ff_sq(ex.d_hi, ex.d_lo, ah, al);
         ff_sq(ey.d_hi, ey.d_lo, bh, bl);
@@ -770,7 +776,7 @@ __device__ __forceinline__ uint32_t plan_first_item(const PlanArgs &pa, int pos)
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
 template <int WT, bool HALF, int NQ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
                                                              const int *__restrict__ valid, float *__restrict__ out,
@@ -808,7 +814,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void ac
 
 // Batch launch: every item names its job; the job table carries the room.
 template <int WT, bool HALF, int NQ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
                                                                    const AxisOrigin *__restrict__ origin,
