@@ -205,7 +205,10 @@ __device__ __forceinline__ AxisEntry table_entry(const RoomArgs &ra, const float
   // at 0 and |ceil(n/2)| copies of the wall at L along this axis.
   const int e0 = abs(n >> 1), e1 = abs((n + 1) >> 1);
   const float g = ff_pow(ra.beta[2 * a], e0) * ff_pow(ra.beta[2 * a + 1], e1);
-  return AxisEntry{v, ve, g, 0.0f};
+  // the enumeration only needs the square of the displacement
+  float sq, sqe;
+  ff_sq(v, ve, sq, sqe);
+  return AxisEntry{sq, sqe, g, 0.0f};
 }
 
 // Validity of a pair (both points strictly inside, distinct) and the family
@@ -397,8 +400,7 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
     if (nxi < g.nx_b) {
       const AxisEntry ex = tx[nxi];
       float qh, ql, rh, rl;
-      ff_sq(ex.d_hi, ex.d_lo, qh, ql);
-      ff_sub(g.r1h, g.r1l, qh, ql, rh, rl);
+      ff_sub(g.r1h, g.r1l, ex.sq_hi, ex.sq_lo, rh, rl);
       if (rh > 0.0f) {
         const float R = __builtin_sqrtf(rh) + 1.0f;
         ny_lo = first_ge(ay, -R);
@@ -424,11 +426,9 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
         const uint32_t xc = es.nx_col[i];
         const AxisEntry ex = tx[nx0 + i];
         const AxisEntry ey = ty[(int)(xc & 0x7ffu) + (gcol - (int)(xc >> 11))];
-        float ah, al, bh, bl, sh, sl;
-        ff_sq(ex.d_hi, ex.d_lo, ah, al);
-        ff_sq(ey.d_hi, ey.d_lo, bh, bl);
-        two_sum(ah, bh, sh, sl);
-        sl += al + bl;
+        float sh, sl;
+        two_sum(ex.sq_hi, ey.sq_hi, sh, sl);
+        sl += ex.sq_lo + ey.sq_lo;
         fast_two_sum(sh, sl, sh, sl);
         es.col_sh[lane] = sh;
         es.col_sl[lane] = sl;
@@ -500,16 +500,15 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
                                                     const AxisEntry ez, uint32_t ent) {
   ImageParams p;
   const int cl = (int)(ent >> 16);
-  float ph, pl, s, se, Sh, Sl;
-  ff_sq(ez.d_hi, ez.d_lo, ph, pl);
-  two_sum(es.col_sh[cl], ph, s, se);
-  se += es.col_sl[cl] + pl;
-  fast_two_sum(s, se, Sh, Sl);
+  // S = column part + z part in float-float (Sh + Sl, not renormalised)
+  float Sh, Sl;
+  two_sum(es.col_sh[cl], ez.sq_hi, Sh, Sl);
+  Sl += es.col_sl[cl] + ez.sq_lo;
   // x = sqrt(S) in samples (Eq. (2)-(3)): one Newton correction in float-float
   const float x0 = __builtin_amdgcn_sqrtf(Sh);
   const float rx = __builtin_amdgcn_rcpf(x0);
   const float xl = (__builtin_fmaf(-x0, x0, Sh) + Sl) * (0.5f * rx);
-  // k0 = floor(x), f = x - k0: |xl| is below half an ulp of x0, so the
+  // k0 = floor(x), f = x - k0: |xl| is a few ulps of x0 at most, so the
   // fraction (x0 - floor(x0)) + xl lies in (-1, 2) and one floor moves it into
   // [0, 1); the clamp catches a tiny negative fraction that rounds up to 1.
   float kf = floorf(x0);

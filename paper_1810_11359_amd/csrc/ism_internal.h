@@ -58,11 +58,12 @@ struct PlanArgs {
   uint8_t chunks[MAX_TILES];  // chunks per tile (by tile index)
 };
 
-// Per-RIR table entry for one lattice index of one axis: displacement from
-// the receiver to the image coordinate in samples (float-float) and the axis
-// factor of the reflection gain.
+// Per-RIR table entry for one lattice index of one axis: square of the
+// displacement from the receiver to the image coordinate, in samples^2
+// (float-float, low part not renormalised), and the axis factor of the
+// reflection gain.
 struct AxisEntry {
-  float d_hi, d_lo, gain, pad;
+  float sq_hi, sq_lo, gain, pad;
 };
 
 // Per-RIR offsets of the two image families of each axis, in samples: even
