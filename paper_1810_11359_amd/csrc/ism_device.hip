@@ -839,6 +839,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
 // a fixed order, so results do not depend on scheduling.
 // grid = (rir, dispatch position of the tile, 256-sample segment)
 // ---------------------------------------------------------------------------
+// v + x[0] + x[stride] + ... + x[(n - 1) stride], added in that order; the
+// loads of a group of eight are issued together (the order of the additions,
+// and so the result, does not depend on the grouping).
+__device__ __forceinline__ float ordered_sum(float v, const float *__restrict__ x, size_t stride, int n) {
+  int cc = 0;
+  for (; cc + 8 <= n; cc += 8) {
+    float t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = x[(size_t)(cc + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; cc < n; ++cc) v += x[(size_t)cc * stride];
+  return v;
+}
+
 __global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, const float *__restrict__ part,
                                                      const float *__restrict__ marg, float *__restrict__ out) {
   const int pos = blockIdx.y;
@@ -857,20 +873,19 @@ __global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, c
   float v;
   if (C > 1) {
     const size_t first = (size_t)plan_first_item(pa, pos) + (size_t)rir * C;
-    v = 0.0f;
-    for (int cc = 0; cc < C; ++cc) v += part[(first + cc) * TILE + k];
+    v = ordered_sum(0.0f, part + first * TILE + k, TILE, C);
   } else {
     v = *o;
   }
   if (zl) {  // tile t-1 is dispatched at pos + 1
     const int Cp = pa.chunks[tile_id - 1];
     const size_t first = (size_t)plan_first_item(pa, pos + 1) + (size_t)rir * Cp;
-    for (int cc = 0; cc < Cp; ++cc) v += marg[(first + cc) * W + LM + k];
+    v = ordered_sum(v, marg + first * W + LM + k, W, Cp);
   }
   if (zr) {  // tile t+1 is dispatched at pos - 1
     const int Cn = pa.chunks[tile_id + 1];
     const size_t first = (size_t)plan_first_item(pa, pos - 1) + (size_t)rir * Cn;
-    for (int cc = 0; cc < Cn; ++cc) v += marg[(first + cc) * W + (k - (TILE - LM))];
+    v = ordered_sum(v, marg + first * W + (k - (TILE - LM)), W, Cn);
   }
   *o = v;
 }
@@ -894,15 +909,12 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restr
   float *o = jb.out + (size_t)br.rir * n_samples + T0 + k;
   float v;
   if (br.chunks > 1) {
-    v = 0.0f;
-    for (int cc = 0; cc < br.chunks; ++cc) v += part[((size_t)br.first + cc) * TILE + k];
+    v = ordered_sum(0.0f, part + (size_t)br.first * TILE + k, TILE, br.chunks);
   } else {
     v = *o;
   }
-  if (zl)
-    for (int cc = 0; cc < br.nprev; ++cc) v += marg[((size_t)br.mprev + cc) * MARG_STRIDE + LM + k];
-  if (zr)
-    for (int cc = 0; cc < br.nnext; ++cc) v += marg[((size_t)br.mnext + cc) * MARG_STRIDE + (k - (TILE - LM))];
+  if (zl) v = ordered_sum(v, marg + (size_t)br.mprev * MARG_STRIDE + LM + k, MARG_STRIDE, br.nprev);
+  if (zr) v = ordered_sum(v, marg + (size_t)br.mnext * MARG_STRIDE + (k - (TILE - LM)), MARG_STRIDE, br.nnext);
   *o = v;
 }
 
