@@ -281,6 +281,17 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
   return v;
 }
+// Inclusive running maximum over the 64 lanes of non-negative values, same
+// lane pattern as wave_incl_scan.
+__device__ __forceinline__ int wave_incl_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));
+  return v;
+}
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -339,12 +350,18 @@ __device__ __forceinline__ int first_ge(const AxisRange &a, float b) {
 // Items end with a fixed-order sum of the tiles, so results are bitwise
 // reproducible.
 // ---------------------------------------------------------------------------
-constexpr int QCAP = 256;  // per-wave queue of candidate images
+typedef int int4v __attribute__((ext_vector_type(4)));
+typedef float float2v __attribute__((ext_vector_type(2)));
 
-// Per-wave LDS of the shell enumeration.
+// Per-wave LDS of the shell enumeration. The candidates of a batch of 64
+// columns are numbered 0 .. total-1, column by column; column lane c holds
+// positions [excl_c, excl_c + n1_c + n2_c), its first run of z indices
+// (z1_c ..) then its second (z2_c ..).
 struct EnumLds {
-  uint32_t queue[QCAP];  // (column lane << 16) | table index of nz
-  float col_sh[64], col_sl[64], col_g[64];
+  int mark[64];        // per chunk of 64 positions: column lane + 1 where a column starts
+  int4v col_run[64];   // (excl + n1, z1 - excl, z2 - n1 - excl, gain bits): position p
+                       // of the column has z index p + (p < excl + n1 ? z1 - excl : z2 - n1 - excl)
+  float2v col_s[64];   // column part of the squared distance (float-float)
   // per x lane of the row batch: (first column << 11) | first y table index
   // (column counts stay below 64 * 2048 = 2^17, table indices below 2^11)
   uint32_t nx_col[64];
@@ -383,10 +400,11 @@ __device__ __forceinline__ ItemGeom item_geom(const RoomArgs &ra, const AxisRang
   return g;
 }
 
-// Walks the shell of the item. For every filled queue chunk (entries
-// [0, qn) of es.queue, with the column data of the current batch in es.col_*)
-// calls consume(qn), which must use up all qn entries. col_g holds the column's
-// gain factor times gscale.
+// Walks the shell of the item. For every batch of 64 columns with candidates
+// it fills es.col_run and es.col_s and calls consume(total, excl, cnt): total
+// candidates in the batch, and on column lane c its first position excl and
+// its count cnt. The column gain in col_run is the product of the x and y
+// gain factors times gscale.
 template <class Consume>
 __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEntry *__restrict__ tx,
                                                 const AxisEntry *__restrict__ ty, const AxisRange &ay,
@@ -399,7 +417,7 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
     int ny_lo = 0, ny_cnt = 0;
     if (nxi < g.nx_b) {
       const AxisEntry ex = tx[nxi];
-      float qh, ql, rh, rl;
+      float rh, rl;
       ff_sub(g.r1h, g.r1l, ex.sq_hi, ex.sq_lo, rh, rl);
       if (rh > 0.0f) {
         const float R = __builtin_sqrtf(rh) + 1.0f;
@@ -416,6 +434,7 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
       // lanes = columns (nx, ny): z ranges of the shell
       const int gcol = cb * 64 + lane;
       int z1 = 0, n1 = 0, z2 = 0, n2 = 0;
+      float cg = 0.0f;
       if (gcol < ncols) {
         // x lane of the column: the last one whose first column is <= gcol
         const uint32_t key = ((uint32_t)gcol << 11) | 0x7ffu;
@@ -430,9 +449,8 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
         two_sum(ex.sq_hi, ey.sq_hi, sh, sl);
         sl += ex.sq_lo + ey.sq_lo;
         fast_two_sum(sh, sl, sh, sl);
-        es.col_sh[lane] = sh;
-        es.col_sl[lane] = sl;
-        es.col_g[lane] = (ex.gain * ey.gain) * gscale;
+        es.col_s[lane] = float2v{sh, sl};
+        cg = (ex.gain * ey.gain) * gscale;
         float rh, rl;
         ff_sub(g.r1h, g.r1l, sh, sl, rh, rl);
         if (rh > 0.0f) {
@@ -455,16 +473,10 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
       const int incl = wave_incl_scan(cnt);
       const int total = __builtin_amdgcn_readlane(incl, 63);
       const int excl = incl - cnt;
-
-      for (int q0 = 0; q0 < total; q0 += QCAP) {
-        // lanes write their candidates with wave-wide index in [q0, q0 + QCAP)
-        const int i_lo = max(0, q0 - excl), i_hi = min(cnt, q0 + QCAP - excl);
-        for (int i = i_lo; i < i_hi; ++i) {
-          const int nz = (i < n1) ? z1 + i : z2 + (i - n1);
-          es.queue[excl + i - q0] = ((uint32_t)lane << 16) | (uint32_t)nz;
-        }
+      es.col_run[lane] = int4v{excl + n1, z1 - excl, z2 - n1 - excl, __float_as_int(cg)};
+      if (total > 0) {
         wave_sync();
-        consume(min(QCAP, total - q0));
+        consume(total, excl, cnt);
         wave_sync();
       }
     }
@@ -484,7 +496,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 //         C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W), CQ = C/2 sin(2 pi f/W)
 //         follow from that same f;
 //   FP16: (t, t) in packed FP16 with t = f - 1/2, A, A t, base.
-// The column gain in es.col_g carries the constant factor of A: fs / (4 pi c)
+// The column gain cgain carries the constant factor of A: fs / (4 pi c)
 // for FP16, and fs / (4 pi c) / (2 pi) for FP32, whose record holds C/2.
 struct ImageParams {
   bool ok;
@@ -496,14 +508,13 @@ __device__ __forceinline__ float column_gain_scale(const RoomArgs &ra) {
   return HALF ? ra.kappa : ra.kappa * (float)(0.5 / kPi);
 }
 template <int WT, bool HALF>
-__device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const ItemGeom &g, const EnumLds &es,
-                                                    const AxisEntry ez, uint32_t ent) {
+__device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const ItemGeom &g, const float2v cs,
+                                                    const float cgain, const AxisEntry ez) {
   ImageParams p;
-  const int cl = (int)(ent >> 16);
   // S = column part + z part in float-float (Sh + Sl, not renormalised)
   float Sh, Sl;
-  two_sum(es.col_sh[cl], ez.sq_hi, Sh, Sl);
-  Sl += es.col_sl[cl] + ez.sq_lo;
+  two_sum(cs.x, ez.sq_hi, Sh, Sl);
+  Sl += cs.y + ez.sq_lo;
   // x = sqrt(S) in samples (Eq. (2)-(3)): one Newton correction in float-float
   const float x0 = __builtin_amdgcn_sqrtf(Sh);
   const float rx = __builtin_amdgcn_rcpf(x0);
@@ -520,7 +531,7 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
   p.base = k0 - g.T0;
   p.ok = (x0 < 1.0e9f) && (uint32_t)p.base < (uint32_t)(g.K1 - g.T0);
   // Eq. (4) amplitude (times the constant factor carried by the column gain)
-  const float A = (es.col_g[cl] * ez.gain) * rx;
+  const float A = (cgain * ez.gain) * rx;
   if constexpr (HALF) {
     const float t = fr - 0.5f;
     const half2_t th = {(_Float16)t, (_Float16)t};
@@ -708,25 +719,45 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   auto rec = [&](int k) { return stp[k]; };
 
   int ns = 0;  // staged images (wave-uniform)
-  enumerate_shell(g, tx, ty, ay, az, column_gain_scale<HALF>(ra), es, [&](int qn) {
-    // queue entries and z table rows are read one chunk of 64 ahead
-    uint32_t ent = 0;
+  enumerate_shell(g, tx, ty, ay, az, column_gain_scale<HALF>(ra), es, [&](int total, int excl, int cnt) {
+    // Chunks of 64 candidate positions; lane i takes position q0 + i. Its
+    // column is the last one starting at or before it: each column marks its
+    // first position in the chunk, a running maximum over the lanes carries
+    // the marks forward, and the last lane's column carries into the next
+    // chunk (columns start in increasing order).
+    int carry = 0;
+    auto locate = [&](int q0, int &cl, int &nz, float &cg) {
+      es.mark[lane] = 0;
+      wave_sync();
+      const int r = excl - q0;
+      if (cnt > 0 && (uint32_t)r < 64u) es.mark[r] = lane + 1;
+      wave_sync();
+      const int m = max(wave_incl_max(es.mark[lane]), carry);
+      carry = __builtin_amdgcn_readlane(m, 63);
+      cl = max(m - 1, 0);
+      const int4v cr = es.col_run[cl];
+      const int pos = q0 + lane;
+      nz = min(max(pos + (pos < cr.x ? cr.y : cr.z), 0), ra.N[2] - 1);
+      cg = __int_as_float(cr.w);
+    };
+    // the next chunk's column and z table row are found ahead of its use
+    int cl, nz;
+    float cg;
+    locate(0, cl, nz, cg);
     AxisEntry ez{0.0f, 0.0f, 0.0f, 0.0f};
-    if (lane < qn) {
-      ent = es.queue[lane];
-      ez = tz[ent & 0xffffu];
-    }
-    for (int q = 0; q < qn; q += 64) {
-      const uint32_t ent_c = ent;
+    if (lane < total) ez = tz[nz];
+    for (int q = 0; q < total; q += 64) {
+      const int cl_c = cl;
+      const float cg_c = cg;
       const AxisEntry ez_c = ez;
-      if (q + 64 + lane < qn) {
-        ent = es.queue[q + 64 + lane];
-        ez = tz[ent & 0xffffu];
+      if (q + 64 < total) {
+        locate(q + 64, cl, nz, cg);
+        if (q + 64 + lane < total) ez = tz[nz];
       }
       // lanes = candidates: parameters, then compaction into the stage
       ImageParams p;
       p.ok = false;
-      if (q + lane < qn) p = image_params<WT, HALF>(ra, g, es, ez_c, ent_c);
+      if (q + lane < total) p = image_params<WT, HALF>(ra, g, es.col_s[cl_c], cg_c, ez_c);
       const uint64_t okm = __ballot(p.ok);
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
       if (p.ok) stp[ns + rank] = p.rec;
