@@ -495,22 +495,26 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 //         fraction in units of 2^-24; the taps use f = float(F) 2^-32, and
 //         C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W), CQ = C/2 sin(2 pi f/W)
 //         follow from that same f;
-//   FP16: (t, t) in packed FP16 with t = f - 1/2, A, A t, base.
+//   FP16: (t, A') with t = f - 1/2 in FP32 and A' the amplitude with the
+//         base in its 8 low mantissa bits (relative change < 2^-15).
 // The column gain cgain carries the constant factor of A: fs / (4 pi c)
 // for FP16, and fs / (4 pi c) / (2 pi) for FP32, whose record holds C/2.
+template <bool HALF> struct StageRec { typedef f4v type; };
+template <> struct StageRec<true> { typedef float2v type; };
+template <bool HALF>
 struct ImageParams {
   bool ok;
   int base;
-  f4v rec;
+  typename StageRec<HALF>::type rec;
 };
 template <bool HALF>
 __device__ __forceinline__ float column_gain_scale(const RoomArgs &ra) {
   return HALF ? ra.kappa : ra.kappa * (float)(0.5 / kPi);
 }
 template <int WT, bool HALF>
-__device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const ItemGeom &g, const float2v cs,
-                                                    const float cgain, const AxisEntry ez) {
-  ImageParams p;
+__device__ __forceinline__ ImageParams<HALF> image_params(const RoomArgs &ra, const ItemGeom &g, const float2v cs,
+                                                          const float cgain, const AxisEntry ez) {
+  ImageParams<HALF> p;
   // S = column part + z part in float-float (Sh + Sl, not renormalised)
   float Sh, Sl;
   two_sum(cs.x, ez.sq_hi, Sh, Sl);
@@ -534,8 +538,8 @@ __device__ __forceinline__ ImageParams image_params(const RoomArgs &ra, const It
   const float A = (cgain * ez.gain) * rx;
   if constexpr (HALF) {
     const float t = fr - 0.5f;
-    const half2_t th = {(_Float16)t, (_Float16)t};
-    p.rec = f4v{__builtin_bit_cast(float, th), A, A * t, __int_as_float(p.base)};
+    const uint32_t Ab = (__float_as_uint(A) & ~0xffu) | ((uint32_t)p.base & 0xffu);
+    p.rec = float2v{t, __uint_as_float(Ab)};
   } else {
     // 24-bit fraction fq in [1, 2^24 - 2] (rounding moves the delay by at
     // most 3e-8 samples) and the base in the low byte; float(F) rounds F to
@@ -621,7 +625,8 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   static_assert(WT % LPG == 0, "window must be a multiple of the lanes per image");
 
   __shared__ float tile[NQ][LSPAN];
-  __shared__ f4v stp[SCAP];  // staged records (ImageParams::rec)
+  typedef typename StageRec<HALF>::type Rec;
+  __shared__ Rec stp[SCAP];  // staged records (ImageParams::rec)
   __shared__ EnumLds es;
 
   const int lane = threadIdx.x & 63;
@@ -672,26 +677,23 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   // One step: staged image (record P) on this lane group, taps l + LPG m.
   // The empty asm consumes the record as one 128-bit value where the step
   // starts, which keeps its LDS read a single ds_read_b128 issued ahead.
-  auto step = [&](const f4v P) {
+  auto step = [&](const Rec P) {
     __asm__ volatile("" ::"v"(P));
-    const int b = HALF ? __float_as_int(P.w) : (int)(__float_as_uint(P.x) & 0xffu);
+    const int b = (int)(__float_as_uint(HALF ? P.y : P.x) & 0xffu);
     float *t = th + b;
     if constexpr (HALF) {
-      // tap = A c0 + (A t) q(t), q in packed FP16 two taps at a time
-      const half2_t tt = __builtin_bit_cast(half2_t, P.x);
-      const float A = P.y, At = P.z;
+      // tap = A (c0 + t q(t)), q in packed FP16 two taps at a time, the
+      // rest in FP32 (t q(t) + c0 as one mixed-precision FMA)
+      const float tf = P.x, A = P.y;
+      const half2_t tt = {(_Float16)tf, (_Float16)tf};
 #pragma unroll
       for (int pr = 0; pr < NPAIR; ++pr) {
         half2_t q = pq[pr][SPD - 1];
 #pragma unroll
         for (int k = SPD - 2; k >= 0; --k) q = __builtin_elementwise_fma(q, tt, pq[pr][k]);
         const int m0 = 2 * pr, m1 = 2 * pr + 1;
-        const float o0 = __builtin_fmaf(A, pc0[m0], t[LPG * m0]);
-        t[LPG * m0] = __builtin_fmaf((float)q.x, At, o0);
-        if (m1 < TPL) {
-          const float o1 = __builtin_fmaf(A, pc0[m1], t[LPG * m1]);
-          t[LPG * m1] = __builtin_fmaf((float)q.y, At, o1);
-        }
+        t[LPG * m0] = __builtin_fmaf(A, __builtin_fmaf(tf, (float)q.x, pc0[m0]), t[LPG * m0]);
+        if (m1 < TPL) t[LPG * m1] = __builtin_fmaf(A, __builtin_fmaf(tf, (float)q.y, pc0[m1]), t[LPG * m1]);
       }
     } else {
       // When TPL is even, tap m + TPL/2 sits half a window period after tap
@@ -755,7 +757,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         if (q + 64 + lane < total) ez = tz[nz];
       }
       // lanes = candidates: parameters, then compaction into the stage
-      ImageParams p;
+      ImageParams<HALF> p;
       p.ok = false;
       if (q + lane < total) p = image_params<WT, HALF>(ra, g, es.col_s[cl_c], cg_c, ez_c);
       const uint64_t okm = __ballot(p.ok);
@@ -767,9 +769,9 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       // step's record is read ahead of this step's tile update (reads ahead
       // stay inside the stage: indices < NQ (np + 1) + h <= SCAP)
       const int np = ns / NQ;
-      f4v PA = rec(h);
+      Rec PA = rec(h);
       for (int s = 0; s < np; s += 2) {
-        const f4v PB = rec(NQ * (s + 1) + h);
+        const Rec PB = rec(NQ * (s + 1) + h);
         __builtin_amdgcn_sched_barrier(0);  // keep the read-ahead in front of the step
         step(PA);
         if (s + 1 < np) {
@@ -782,7 +784,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       // not overlap when np > 0)
       const int rem = ns - NQ * np;
       if (np > 0 && rem > 0) {
-        f4v P{};
+        Rec P{};
         if (lane < rem) P = stp[NQ * np + lane];
         wave_sync();
         if (lane < rem) stp[lane] = P;
