@@ -94,8 +94,21 @@ double item_target(double total_taps, int wt, bool half) {
   return std::max(min_taps, total_taps / balance);
 }
 
+// Waves of the accumulate kernel resident on the device at once (256 CUs x
+// 4 SIMDs x 6), and the rounds of them over which the tail is tapered
+// (ISM_TAIL_ROUNDS overrides; 0 disables the taper).
+constexpr double kResidentWaves = 256.0 * 4.0 * 6.0;
+constexpr double kTailRounds = 1.0;
+double tail_taper_rounds() {
+  if (const char *e = std::getenv("ISM_TAIL_ROUNDS")) return std::max(0.0, std::atof(e));
+  return kTailRounds;
+}
+
 // target <= 0: item size chosen from this call's own estimated work.
-int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, double target = 0.0) {
+// taper: cut the items dispatched last (single calls; a batch's tail is the
+// largest-first order over all its jobs' items instead).
+int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, double target = 0.0,
+              bool taper = true) {
   int st = ism_check_room(r);
   if (st != ISM_OK) return st;
   if (n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
@@ -155,14 +168,27 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, d
     p.tile_taps[t] = imgs * W;
     p.total_taps += p.tile_taps[t] * p.n_rir;
   }
-  if (!(target > 0.0)) target = item_target(p.total_taps, p.wt, p.half);
+  // an explicit item size (argument or ISM_TARGET_TAPS) is used as given
+  const bool fixed = target > 0.0 || std::getenv("ISM_TARGET_TAPS") != nullptr;
+  if (!fixed) target = item_target(p.total_taps, p.wt, p.half);
+  // Tail taper: tiles are dispatched last first, and the items of a tile
+  // dispatched when the work left (this tile included) is below tail_rounds
+  // rounds of the resident waves are cut to that work over tail_rounds x the
+  // resident waves, down to target / 8, so the last waves of a launch finish
+  // close together instead of one full-size item after another.
+  const double tail_rounds = (fixed || !taper) ? 0.0 : tail_taper_rounds();
   p.any_split = false;
-  for (int t = 0; t < pa.n_tiles; ++t) {
+  double rem = p.total_taps;
+  for (int pos = 0; pos < pa.n_tiles; ++pos) {
+    const int t = pa.n_tiles - 1 - pos;
     const double taps = p.tile_taps[t];
-    int ch = (int)std::ceil(taps / target);
+    double tt = target;
+    if (tail_rounds > 0.0) tt = std::max(target / 8.0, std::min(target, rem / (tail_rounds * kResidentWaves)));
+    int ch = (int)std::ceil(taps / tt);
     ch = std::max(1, std::min(ch, MAX_CHUNKS));
     pa.chunks[t] = (uint8_t)ch;
     if (ch > 1) p.any_split = true;
+    rem -= taps * p.n_rir;
   }
   uint64_t acc = 0;
   for (int pos = 0; pos < pa.n_tiles; ++pos) {
@@ -406,8 +432,10 @@ int cost_bucket(double cost) {
 int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bool fill) {
   if (!jobs || n_jobs < 1) return ISM_E_INVALID_ARG;
   std::memset(&bp.st, 0, sizeof(bp.st));
-  // Each job is planned exactly as a single call would plan it (items sized
-  // from the job's own work), so a job's result does not depend on the batch.
+  // Each job is planned as a single call would plan it without the tail
+  // taper (items sized from the job's own work), so a job's result does not
+  // depend on the batch; tapering every job would only fragment small jobs,
+  // and the batch's own tail is the largest-first order over all its items.
   std::vector<Plan> plans(n_jobs);
   for (int j = 0; j < n_jobs; ++j)
     if (!jobs[j].src || !jobs[j].rcv || !jobs[j].out) return ISM_E_INVALID_ARG;
@@ -419,7 +447,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
   std::vector<uint64_t> bucket_count((size_t)kMaxClasses * kCostBuckets, 0);
   for (int j = 0; j < n_jobs; ++j) {
     Plan &p = plans[j];
-    const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p);
+    const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, 0.0, false);
     if (stt != ISM_OK) return stt;
     int cls = -1;
     for (int k = 0; k < n_classes; ++k)

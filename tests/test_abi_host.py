@@ -160,3 +160,22 @@ def test_batch_checks_before_any_launch():
     b = ism._Batch()
     assert L.ism_batch_prepare(jobs, 2, 0, None, 0, None, ctypes.byref(b)) == ism.ISM_E_WORKSPACE
     assert L.ism_batch_run(ctypes.byref(ism._Batch()), None) == ism.ISM_E_INVALID_ARG
+
+
+def test_tail_taper_splits_only_single_calls(monkeypatch):
+    """Single calls cut the items dispatched last (more items, hence more
+    margin records in the workspace); a fixed item size or ISM_TAIL_ROUNDS=0
+    turns the taper off, and batches never taper."""
+    from paper_1810_11359_amd import workloads
+
+    w = workloads.room_32_receivers(0)
+    room = ism.room_for(w)
+    tapered = ism.workspace_size(room, 1, 8)
+    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
+    plain = ism.workspace_size(room, 1, 8)
+    assert tapered > plain
+    monkeypatch.setenv("ISM_TAIL_ROUNDS", "1")
+    monkeypatch.setenv("ISM_TARGET_TAPS", "120000")
+    fixed = ism.workspace_size(room, 1, 8)
+    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
+    assert ism.workspace_size(room, 1, 8) == fixed

@@ -10,10 +10,12 @@ from paper_1810_11359_amd.serving import GpuExecutor, Job, Scheduler, replay
 pytestmark = pytest.mark.gpu
 
 
-def test_mixed_stream_equals_jobs_alone():
+def test_mixed_stream_equals_jobs_alone(monkeypatch):
     import torch
 
     assert torch.cuda.is_available()
+    # batches plan each job like a single call without the tail taper
+    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
 
     def feasible(room, t60):
         try:
