@@ -427,21 +427,26 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
     }
     const int incl_y = wave_incl_scan(ny_cnt);
     const int ncols = __builtin_amdgcn_readlane(incl_y, 63);
-    es.nx_col[lane] = ((uint32_t)(incl_y - ny_cnt) << 11) | (uint32_t)ny_lo;
-    wave_sync();
+    const int col0 = incl_y - ny_cnt;  // first column of this x lane
+    es.nx_col[lane] = ((uint32_t)col0 << 11) | (uint32_t)ny_lo;
 
+    int xcarry = 0;
     for (int cb = 0; cb * 64 < ncols; ++cb) {
       // lanes = columns (nx, ny): z ranges of the shell
       const int gcol = cb * 64 + lane;
+      // x lane of the column: the last x lane with columns starting at or
+      // before it (each marks its first column in the batch; a running
+      // maximum carries the marks forward, as for the candidates)
+      es.mark[lane] = 0;
+      wave_sync();
+      if (ny_cnt > 0 && (uint32_t)(col0 - cb * 64) < 64u) es.mark[col0 - cb * 64] = lane + 1;
+      wave_sync();
+      const int xm = max(wave_incl_max(es.mark[lane]), xcarry);
+      xcarry = __builtin_amdgcn_readlane(xm, 63);
       int z1 = 0, n1 = 0, z2 = 0, n2 = 0;
       float cg = 0.0f;
       if (gcol < ncols) {
-        // x lane of the column: the last one whose first column is <= gcol
-        const uint32_t key = ((uint32_t)gcol << 11) | 0x7ffu;
-        int i = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-          if (i + step < 64 && es.nx_col[i + step] <= key) i += step;
+        const int i = max(xm - 1, 0);
         const uint32_t xc = es.nx_col[i];
         const AxisEntry ex = tx[nx0 + i];
         const AxisEntry ey = ty[(int)(xc & 0x7ffu) + (gcol - (int)(xc >> 11))];
