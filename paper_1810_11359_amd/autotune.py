@@ -24,7 +24,7 @@ import numpy as np
 
 from . import ism, workloads
 
-MIN_TAPS = (3.0e4, 6.0e4, 1.2e5, 2.4e5)
+MIN_TAPS = (6.0e4, 1.2e5, 2.4e5, 4.8e5)
 BALANCE = (24576.0, 49152.0, 98304.0, 196608.0)
 
 
