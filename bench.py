@@ -29,9 +29,9 @@ METRIC = "image-source sinc taps/s (G/s) + RIRs/s, FP32 vs FP16; p50/p99 serving
 FLOP_PER_TAP = 18          # frozen accounting of one windowed-sinc tap
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 FLOP/clk)
 # rocprofv3 summaries holding the calibrated HBM traffic of the timed kernel,
-# valid while the kernel sources hash to the value recorded beside it
+# valid while the library bench.py loads hashes to the value recorded beside
+# it (the build is deterministic: edits that leave the code unchanged keep it)
 TRAFFIC_PROFILES = {"room_32_receivers": "profiles/accumulate_kernel_room_4x5x3_32rcv.md"}
-KERNEL_SOURCES = ("ism_device.hip", "ism_host.cpp", "ism_internal.h", "ism_tuning.h")
 
 
 class _HipEvents:
@@ -59,28 +59,37 @@ class _HipEvents:
         self.hip.hipEventDestroy(ctypes.c_void_p(ev))
 
 
-def kernel_sources_sha256() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1810_11359_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+def ism_lib_path() -> str:
+    from paper_1810_11359_amd import ism
+
+    return ism.LIB_PATH
+
+
+def library_sha256() -> str:
+    """sha256 of the libism.so that the package loads (kernels, planner and
+    tuning table compiled in)."""
+    from paper_1810_11359_amd import ism
+
+    with open(ism.LIB_PATH, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
 
 
 def measured_traffic(workload: str, precision: str):
     """HBM bytes per launch of the accumulate kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
-    none for this workload or the kernel sources changed since it was taken."""
+    none for this workload or the library changed since it was taken."""
     rel = TRAFFIC_PROFILES.get(workload) if precision == "fp32" else None
     if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
         return None
     vals = {}
     with open(os.path.join(ROOT, rel)) as fh:
         for line in fh:
-            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_sources_sha256"):
+            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "library_sha256"):
                 k, v = line.split(":", 1)
                 vals[k] = v.strip()
-    if vals.get("kernel_sources_sha256") != kernel_sources_sha256() or "traffic_bytes_per_launch" not in vals:
+    if "traffic_bytes_per_launch" not in vals or not os.path.exists(ism_lib_path()):
+        return None
+    if vals.get("library_sha256") != library_sha256():
         return None
     return int(vals["traffic_bytes_per_launch"])
 

@@ -335,8 +335,8 @@ __device__ __forceinline__ int first_ge(const AxisRange &a, float b) {
 // Kernel 2: enumeration of the image shell of one tile + windowed-sinc taps.
 //
 // Work item = (RIR, output tile, slab of the image shell along x). The wave
-// walks the columns (nx, ny) that cross the shell, queues their z candidates
-// and hands the queue to a consumer that turns candidates into image
+// walks the columns (nx, ny) that cross the shell, numbers their z candidates
+// and hands them to a consumer that turns candidates into image
 // parameters (delay, amplitude; lanes = images) and adds their taps.
 //
 // Tap consumer (lanes = taps, both precisions): the candidates' parameters
@@ -492,7 +492,8 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Parameters of one image candidate (queue entry ent). ok is false when the
+// Parameters of one image candidate (column part cs of the squared distance,
+// column gain cgain, z table row ez). ok is false when the
 // tile does not own the image. base = k0 - T0 is the tile-local LDS index of its
 // tap j = 1 - W/2 (the LDS tile starts at sample T0 + 1 - W/2). rec is the
 // staged record of the taps, which also carries the base:

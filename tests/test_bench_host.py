@@ -13,12 +13,12 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_only_for_the_profiled_kernel_sources(monkeypatch):
+def test_traffic_only_for_the_profiled_library(monkeypatch):
     t = bench.measured_traffic("room_32_receivers", "fp32")
     assert t is None or (isinstance(t, int) and t > 1_433_600)  # at least the output bytes
     assert bench.measured_traffic("batch_rooms", "fp32") is None
     assert bench.measured_traffic("room_32_receivers", "fp16") is None
-    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
+    monkeypatch.setattr(bench, "library_sha256", lambda: "0" * 64)
     assert bench.measured_traffic("room_32_receivers", "fp32") is None
 
 
