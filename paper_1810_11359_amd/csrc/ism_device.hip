@@ -626,7 +626,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   constexpr int LPG = 64 / NQ;          // lanes per image
   constexpr int TPL = WT / LPG;         // taps per lane per step
   constexpr int NPAIR = (TPL + 1) / 2;  // packed FP16 tap pairs per lane
-  // staged images: up to 64 new + NQ - 1 carried, + two steps of read-ahead
+  // staged images: up to 64 new + NQ - 1 carried, + the read-ahead of a step
   constexpr int SCAP = 64 + 3 * NQ;
   static_assert(WT % LPG == 0, "window must be a multiple of the lanes per image");
 
@@ -681,8 +681,9 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   float *const th = &tile[h][l];
 
   // One step: staged image (record P) on this lane group, taps l + LPG m.
-  // The empty asm consumes the record as one 128-bit value where the step
-  // starts, which keeps its LDS read a single ds_read_b128 issued ahead.
+  // The empty asm consumes the record as one value where the step starts,
+  // which keeps its LDS read a single wide read (16 bytes for FP32, 8 for
+  // FP16) issued ahead.
   auto step = [&](const Rec P) {
     __asm__ volatile("" ::"v"(P));
     const int b = (int)(__float_as_uint(HALF ? P.y : P.x) & 0xffu);
