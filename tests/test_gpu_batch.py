@@ -113,6 +113,34 @@ def test_batch_1024_rooms_sampled(oracle_mod):
         assert np.all(err <= TOL_FP32)
 
 
+def test_batch_fp16_sampled(oracle_mod):
+    """FP16 taps through the batch path at the 1024-room size, on sampled
+    rooms (the sparsest, the densest and random ones), within 2e-3 of the peak."""
+    import torch
+
+    ws = workloads.batch_rooms(1024, seed=0, feasible=_feasible(oracle_mod))
+    jobs = [(ism.room_for(w), w.src, w.rcv) for w in ws]
+    _say("1024-room batch, fp16")
+    b = ism.BatchSimulator(jobs, precision="fp16")
+    outs = b.run()
+    torch.cuda.synchronize()
+    dens = np.array([w.t60 ** 3 / np.prod(w.room) for w in ws])
+    pick = [int(np.argmin(dens)), int(np.argmax(dens))] + list(np.random.default_rng(2).choice(len(ws), 2, replace=False))
+    for k in pick:
+        w = ws[k]
+        args = oracle_room_args(oracle_mod, w)
+        got = outs[k].cpu().numpy()
+        assert np.all(np.isfinite(got))
+        nS = got.shape[-1]
+        peak = np.max(np.abs(got), axis=-1)
+        err = np.zeros(peak.shape)
+        for k0, k1 in [(0, min(nS, 1200)), (max(0, nS - 600), nS)]:
+            ref = oracle_mod.rir(*args, w.src, w.rcv, k_begin=k0, k_end=k1)
+            err = np.maximum(err, np.max(np.abs(got[..., k0:k1] - ref), axis=-1) / peak)
+        print("room", k, "fp16 rel err", err.ravel())
+        assert np.all(err <= 2e-3)
+
+
 def test_batch_graph_replay():
     import torch
 
