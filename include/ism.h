@@ -138,6 +138,39 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
                        int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
                        void *ev_stop);
 
+/* ---- Diffuse reverberation tail (Sec. 2.3) ------------------------------------ */
+
+/* Device workspace (bytes) that ism_simulate_diffuse needs; depends only on
+ * these arguments. */
+int ism_diffuse_workspace_size(const ism_room *room, double t_diff, double t60, int n_src, int n_rcv,
+                               int precision, size_t *bytes);
+
+/* RIRs whose early part is the ISM and whose late part is a noise tail with an
+ * exponential power envelope (Sec. 2.3).
+ *   room    t_max is the full RIR length (nS = ism_n_samples(t_max, fs)); n_img
+ *           is the image lattice of the ISM part (ism_n_img_for_time(room, c,
+ *           t_diff) covers every image arriving before t_diff);
+ *   t_diff  switch time [s], 0 < t_diff <= t_max: samples k < k_diff =
+ *           ism_n_samples(t_diff, fs) are the ISM RIR computed as ism_simulate
+ *           with t_max = t_diff (same precision rules);
+ *   t60     reverberation time of the envelope [s], > 0;
+ *   seed    selects the noise streams.
+ * For k >= k_diff, sample k of RIR i (i = source * n_rcv + receiver) is
+ *   z_ik * sqrt(A_i * 10^(-6 (k/fs - t_diff) / t60)),
+ * where A_i is the mean of h_i[k]^2 / 10^(-6 (k/fs - t_diff) / t60) over the
+ * last fifth of the ISM part (samples [k_diff - max(1, k_diff / 5), k_diff)),
+ * and z_ik is the unit-variance logistic variate log(u / (1 - u)) sqrt(3)/pi,
+ * u = (x + 1/2) / 2^32, of the 32-bit word x = word k % 4 of Philox4x32-10
+ * (Salmon et al., SC'11) at counter (k / 4, i, 0, 0) and key (seed low 32 bits,
+ * seed high 32 bits). Draws depend only on (seed, i, k).
+ *   src, rcv, out, ws, stream: as for ism_simulate (out is [n_src][n_rcv][nS]);
+ *   ws of at least ism_diffuse_workspace_size() bytes.
+ * Errors: ISM_E_INVALID_ARG for t_diff or t60 out of range, otherwise as
+ * ism_simulate, all before any launch. Asynchronous. */
+int ism_simulate_diffuse(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
+                         int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
+                         size_t ws_bytes, void *stream);
+
 /* ---- Batches of rooms --------------------------------------------------------- */
 
 /* One job of a batch: one room with its own sources, receivers and output. */

@@ -154,3 +154,101 @@ def count_taps(L, beta, n_img, c, fs, t_max, t_w, src, rcv) -> int:
             rv = np.ascontiguousarray(r)
             total += int(lib().oracle_count_taps(ctypes.byref(room), _dptr(sv), _dptr(rv)))
     return total
+
+
+# ---------------------------------------------------------------------------
+# Diffuse reverberation (Sec. 2.3): the RIR after t_diff is logistic noise
+# times the square root of an exponential power envelope whose level A is
+# estimated from the ISM part. Plain float64 numpy, written from the
+# definitions; the random bits come from the Philox4x32-10 counter-based
+# generator of Salmon et al. (SC'11), implemented from its published
+# definition (the GPU library implements the same definition independently).
+# ---------------------------------------------------------------------------
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)  # round multipliers
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)  # key increments between rounds
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32 with 10 rounds. ctr: four uint32 arrays (broadcastable),
+    key: two uint32 scalars. Returns four uint32 arrays.
+
+    One round maps (c0, c1, c2, c3) with key (k0, k1) to
+    (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)), where hi
+    and lo are the upper and lower 32 bits of the 64-bit product; the key is
+    advanced by the two Weyl increments before every round but the first."""
+    c = [np.asarray(x, dtype=np.uint64) & _MASK32 for x in ctr]
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    m0, m1 = np.uint64(_PHILOX_M[0]), np.uint64(_PHILOX_M[1])
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + _PHILOX_W[0]) & 0xFFFFFFFF
+            k1 = (k1 + _PHILOX_W[1]) & 0xFFFFFFFF
+        p0 = m0 * c[0]
+        p1 = m1 * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ np.uint64(k0), p1 & _MASK32,
+             (p0 >> np.uint64(32)) ^ c[3] ^ np.uint64(k1), p0 & _MASK32]
+    return [x.astype(np.uint32) for x in c]
+
+
+def noise_bits(seed: int, rir_index: int, k: np.ndarray) -> np.ndarray:
+    """Random word of sample k of RIR rir_index: Philox4x32-10 with counter
+    (k // 4, rir_index, 0, 0) and key (low, high 32 bits of seed), word k % 4."""
+    k = np.asarray(k, dtype=np.int64)
+    blk = (k // 4).astype(np.uint64)
+    zero = np.zeros_like(blk)
+    out = philox4x32_10([blk, zero + np.uint64(rir_index), zero, zero], (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    words = np.stack(out, axis=-1)
+    return np.take_along_axis(words, (k % 4)[..., None], axis=-1)[..., 0]
+
+
+def logistic_from_bits(x: np.ndarray) -> np.ndarray:
+    """Unit-variance logistic variate from a uint32 word: the logistic quantile
+    function log(u / (1 - u)) at u = (x + 1/2) / 2^32, scaled by sqrt(3)/pi
+    (a logistic law of scale s has variance s^2 pi^2 / 3)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.log((x + 0.5) / (4294967296.0 - 0.5 - x)) * (np.sqrt(3.0) / np.pi)
+
+
+def envelope(k: np.ndarray, fs: float, t_diff: float, t60: float) -> np.ndarray:
+    """Power envelope shape 10^(-6 (t - t_diff) / T60) at t = k / fs: the power
+    falls by 60 dB in T60 (Sabine), normalised to 1 at t_diff."""
+    t = np.asarray(k, dtype=np.float64) / fs
+    return 10.0 ** (-6.0 * (t - t_diff) / t60)
+
+
+def diffuse_window(k_diff: int) -> tuple:
+    """Samples [k_w, k_diff) of the ISM part that set the envelope level: the
+    last fifth of the ISM part (at least one sample)."""
+    return k_diff - max(1, k_diff // 5), k_diff
+
+
+def envelope_level(h_ism: np.ndarray, fs: float, t_diff: float, t60: float) -> np.ndarray:
+    """A per RIR: the mean of h[k]^2 / envelope(k) over the window of the ISM
+    part h_ism [..., k_diff] (least-squares level of the exponential envelope
+    fitted to the ISM energy there)."""
+    k_diff = h_ism.shape[-1]
+    k0, k1 = diffuse_window(k_diff)
+    k = np.arange(k0, k1)
+    return np.mean(h_ism[..., k0:k1] ** 2 / envelope(k, fs, t_diff, t60), axis=-1)
+
+
+def diffuse_rir(L, beta, n_img, c, fs, t_max, t_w, t_diff, t60, seed, src, rcv) -> np.ndarray:
+    """Full RIRs [n_src, n_rcv, nS(t_max)]: the ISM part (lattice n_img, up to
+    k_diff = nS(t_diff) samples), then for k >= k_diff logistic noise times
+    sqrt(A envelope(k)). RIR index i = source * n_rcv + receiver selects the
+    noise stream."""
+    nS = n_samples(t_max, fs)
+    k_diff = n_samples(t_diff, fs)
+    h_ism = rir(L, beta, n_img, c, fs, t_diff, t_w, src, rcv)
+    n_src, n_rcv = h_ism.shape[:2]
+    A = envelope_level(h_ism, fs, t_diff, t60)
+    out = np.zeros((n_src, n_rcv, nS))
+    out[..., :k_diff] = h_ism
+    k = np.arange(k_diff, nS)
+    env = envelope(k, fs, t_diff, t60)
+    for i in range(n_src * n_rcv):
+        s, r = divmod(i, n_rcv)
+        z = logistic_from_bits(noise_bits(seed, i, k))
+        out[s, r, k_diff:] = z * np.sqrt(A[s, r] * env)
+    return out

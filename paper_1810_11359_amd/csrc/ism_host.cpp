@@ -28,6 +28,8 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
                  bool half, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid,
                  float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
+int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
+                   double t60, uint64_t seed, hipStream_t st);
 }  // namespace ism
 
 using namespace ism;
@@ -367,14 +369,10 @@ int ism_simulate(const ism_room *room, const float *src, int n_src, const float 
   return ism_simulate_timed(room, src, n_src, rcv, n_rcv, precision, out, ws, ws_bytes, stream, nullptr, nullptr);
 }
 
-int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
-                       int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
-                       void *ev_stop) {
-  Plan p;
-  const int st = make_plan(room, n_src, n_rcv, precision, p);
-  if (st != ISM_OK) return st;
-  if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
-  if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
+// Launches the ISM kernels of a plan: tables, taps, completion of the tiles.
+// ws holds at least p.ws_bytes; out is device [n_rir][nS].
+static int run_plan(const Plan &p, const float *src, const float *rcv, float *out, void *ws, void *stream,
+                    void *ev_start, void *ev_stop) {
   hipStream_t s = (hipStream_t)stream;
   char *w = (char *)ws;
   int *valid = (int *)(w + p.off_valid);
@@ -389,6 +387,70 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
   // split tiles and the margins between neighbouring tiles
   if ((p.any_split || p.pa.n_tiles > 1) && launch_reduce(p.ra, p.pa, p.n_rir, part, marg, out, s) != 0)
+    return ISM_E_DEVICE;
+  return ISM_OK;
+}
+
+int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                       int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
+                       void *ev_stop) {
+  Plan p;
+  const int st = make_plan(room, n_src, n_rcv, precision, p);
+  if (st != ISM_OK) return st;
+  if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
+  if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
+  return run_plan(p, src, rcv, out, ws, stream, ev_start, ev_stop);
+}
+
+// ---- Diffuse tail (Sec. 2.3) ------------------------------------------------
+// The ISM part is planned as a call with t_max = t_diff; its RIRs go to the
+// workspace after the plan's own arrays, and the diffuse kernel writes the
+// full RIRs (ISM part copied, tail drawn) to out.
+static int diffuse_plan(const ism_room *r, double t_diff, double t60, int n_src, int n_rcv, int precision, Plan &p,
+                        int64_t &n_full, size_t &off_ism, size_t &ws_bytes) {
+  if (!r) return ISM_E_INVALID_ARG;
+  if (!(t_diff > 0.0) || !(t60 > 0.0) || !std::isfinite(t_diff) || !std::isfinite(t60)) return ISM_E_INVALID_ARG;
+  const int rs = ism_check_room(r);
+  if (rs != ISM_OK) return rs;
+  if (!(t_diff <= r->t_max)) return ISM_E_INVALID_ARG;
+  ism_room ri = *r;
+  ri.t_max = t_diff;
+  const int st = make_plan(&ri, n_src, n_rcv, precision, p);
+  if (st != ISM_OK) return st;
+  n_full = ism_n_samples(r->t_max, r->fs);
+  if (p.ra.n_samples > n_full) return ISM_E_INVALID_ARG;
+  off_ism = align_up(p.ws_bytes);
+  ws_bytes = off_ism + sizeof(float) * (size_t)p.n_rir * (size_t)p.ra.n_samples;
+  return ISM_OK;
+}
+
+int ism_diffuse_workspace_size(const ism_room *room, double t_diff, double t60, int n_src, int n_rcv, int precision,
+                               size_t *bytes) {
+  if (!bytes) return ISM_E_INVALID_ARG;
+  Plan p;
+  int64_t n_full;
+  size_t off_ism, ws;
+  const int st = diffuse_plan(room, t_diff, t60, n_src, n_rcv, precision, p, n_full, off_ism, ws);
+  if (st != ISM_OK) return st;
+  *bytes = ws;
+  return ISM_OK;
+}
+
+int ism_simulate_diffuse(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src, int n_src,
+                         const float *rcv, int n_rcv, int precision, float *out, void *ws, size_t ws_bytes,
+                         void *stream) {
+  Plan p;
+  int64_t n_full;
+  size_t off_ism, need;
+  const int st = diffuse_plan(room, t_diff, t60, n_src, n_rcv, precision, p, n_full, off_ism, need);
+  if (st != ISM_OK) return st;
+  if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
+  if (!ws || ws_bytes < need) return ISM_E_WORKSPACE;
+  float *ism = (float *)((char *)ws + off_ism);
+  const int rs = run_plan(p, src, rcv, ism, ws, stream, nullptr, nullptr);
+  if (rs != ISM_OK) return rs;
+  if (launch_diffuse(ism, p.ra.n_samples, out, (int)n_full, p.n_rir, room->fs, t_diff, t60, seed,
+                     (hipStream_t)stream) != 0)
     return ISM_E_DEVICE;
   return ISM_OK;
 }

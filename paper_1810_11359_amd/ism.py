@@ -34,6 +34,7 @@ EXPORTS = (
     "ism_time_for_attenuation", "ism_n_samples", "ism_check_room", "ism_check_positions",
     "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed",
     "ism_batch_workspace_size", "ism_batch_prepare", "ism_batch_run", "ism_batch_run_timed",
+    "ism_diffuse_workspace_size", "ism_simulate_diffuse",
 )
 
 
@@ -105,6 +106,12 @@ def lib() -> ctypes.CDLL:
         L.ism_simulate_timed.restype = ctypes.c_int
         L.ism_simulate_timed.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
                                          fp, fp, fp]
+        L.ism_diffuse_workspace_size.restype = ctypes.c_int
+        L.ism_diffuse_workspace_size.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.ism_simulate_diffuse.restype = ctypes.c_int
+        L.ism_simulate_diffuse.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp, ctypes.c_int, fp,
+                                           ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t, fp]
         _lib = L
     return _lib
 
@@ -239,6 +246,54 @@ class Simulator:
 def simulate(room: Room, src, rcv, precision: str = "fp32", device: str = "cuda"):
     """RIRs [n_src, n_rcv, nS] (float32, on ``device``) of every source/receiver pair."""
     return Simulator(room, src, rcv, precision, device).run()
+
+
+def diffuse_workspace_size(room: Room, t_diff: float, t60: float, n_src: int, n_rcv: int,
+                           precision: str = "fp32") -> int:
+    rc = room._c()
+    out = ctypes.c_size_t()
+    _check(lib().ism_diffuse_workspace_size(ctypes.byref(rc), float(t_diff), float(t60), int(n_src), int(n_rcv),
+                                            PRECISIONS[precision], ctypes.byref(out)), "ism_diffuse_workspace_size")
+    return out.value
+
+
+class DiffuseSimulator:
+    """Reusable device state for ``ism_simulate_diffuse``: RIRs [n_src, n_rcv, nS(t_max)]
+    with the ISM part up to ``t_diff`` and a logistic-noise tail after it (Sec. 2.3)."""
+
+    def __init__(self, room: Room, src, rcv, t_diff: float, t60: float, seed: int = 0, precision: str = "fp32",
+                 device: str = "cuda", check: bool = True):
+        import torch
+
+        self.torch = torch
+        self.room = room
+        self._room_c = room._c()
+        s, r = _host_pos(src), _host_pos(rcv)
+        if check:
+            check_positions(room, s, r)
+        self.t_diff, self.t60, self.seed = float(t_diff), float(t60), int(seed)
+        self.precision = PRECISIONS[precision]
+        self.src = torch.from_numpy(s).to(device)
+        self.rcv = torch.from_numpy(r).to(device)
+        self.n_src, self.n_rcv = s.shape[0], r.shape[0]
+        self.out = torch.empty((self.n_src, self.n_rcv, room.n_samples), dtype=torch.float32, device=device)
+        nbytes = diffuse_workspace_size(room, t_diff, t60, self.n_src, self.n_rcv, precision)
+        self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        self.ws_bytes = nbytes
+
+    def run(self, stream=None):
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        _check(lib().ism_simulate_diffuse(ctypes.byref(self._room_c), self.t_diff, self.t60, self.seed,
+                                          self.src.data_ptr(), self.n_src, self.rcv.data_ptr(), self.n_rcv,
+                                          self.precision, self.out.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                                          st.cuda_stream), "ism_simulate_diffuse")
+        return self.out
+
+
+def simulate_diffuse(room: Room, src, rcv, t_diff: float, t60: float, seed: int = 0, precision: str = "fp32",
+                     device: str = "cuda"):
+    """RIRs [n_src, n_rcv, nS] with the ISM up to t_diff and the diffuse tail after it."""
+    return DiffuseSimulator(room, src, rcv, t_diff, t60, seed, precision, device).run()
 
 
 def room_for(w) -> Room:

@@ -179,3 +179,14 @@ def test_tail_taper_splits_only_single_calls(monkeypatch):
     fixed = ism.workspace_size(room, 1, 8)
     monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
     assert ism.workspace_size(room, 1, 8) == fixed
+
+
+def test_diffuse_argument_checks():
+    """t_diff and t60 are checked before anything else (no device memory needed)."""
+    r = _room()
+    assert ism.diffuse_workspace_size(r, 0.01, 0.5, 1, 1) > ism.workspace_size(
+        ism.Room(r.room, r.beta, r.n_img, r.c, r.fs, 0.01, r.t_w), 1, 1)
+    for t_diff, t60 in ((0.0, 0.5), (-1.0, 0.5), (r.t_max * 2, 0.5), (0.01, 0.0), (float("nan"), 0.5)):
+        with pytest.raises(ism.IsmError) as e:
+            ism.diffuse_workspace_size(r, t_diff, t60, 1, 1)
+        assert e.value.status == ism.ISM_E_INVALID_ARG
