@@ -138,7 +138,7 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
                        int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
                        void *ev_stop);
 
-/* ---- Diffuse reverberation tail (Sec. 2.3) ------------------------------------ */
+/* ---- Diffuse reverberation tail (Sec. 2.2, Eq. (8); Sec. 3.3) --------------- */
 
 /* Device workspace (bytes) that ism_simulate_diffuse needs; depends only on
  * these arguments. */
@@ -146,7 +146,7 @@ int ism_diffuse_workspace_size(const ism_room *room, double t_diff, double t60, 
                                int precision, size_t *bytes);
 
 /* RIRs whose early part is the ISM and whose late part is a noise tail with an
- * exponential power envelope (Sec. 2.3).
+ * exponential power envelope (Sec. 2.2, Eq. (8); Sec. 3.3).
  *   room    t_max is the full RIR length (nS = ism_n_samples(t_max, fs)); n_img
  *           is the image lattice of the ISM part (ism_n_img_for_time(room, c,
  *           t_diff) covers every image arriving before t_diff);

@@ -157,9 +157,9 @@ def count_taps(L, beta, n_img, c, fs, t_max, t_w, src, rcv) -> int:
 
 
 # ---------------------------------------------------------------------------
-# Diffuse reverberation (Sec. 2.3): the RIR after t_diff is logistic noise
-# times the square root of an exponential power envelope whose level A is
-# estimated from the ISM part. Plain float64 numpy, written from the
+# Diffuse reverberation (Sec. 2.2, Eq. (8); Sec. 3.3): the RIR after t_diff is
+# logistic noise times the square root of an exponential power envelope whose
+# level A is estimated from the ISM part. Plain float64 numpy, written from the
 # definitions; the random bits come from the Philox4x32-10 counter-based
 # generator of Salmon et al. (SC'11), implemented from its published
 # definition (the GPU library implements the same definition independently).

@@ -1,5 +1,5 @@
-// Diffuse reverberation tail (Sec. 2.3): after t_diff the RIR is logistic
-// noise times the square root of an exponential power envelope,
+// Diffuse reverberation tail (Sec. 2.2, Eq. (8); Sec. 3.3): after t_diff the
+// RIR is logistic noise times the square root of an exponential power envelope,
 //   P(t) = A 10^(-6 (t - t_diff) / T60)      (-60 dB of power in T60, Sabine),
 // whose level A is estimated from the ISM part of the same RIR: the mean of
 // h[k]^2 / 10^(-6 (t_k - t_diff) / T60) over the last fifth of the ISM part.

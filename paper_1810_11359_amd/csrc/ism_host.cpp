@@ -402,7 +402,7 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
   return run_plan(p, src, rcv, out, ws, stream, ev_start, ev_stop);
 }
 
-// ---- Diffuse tail (Sec. 2.3) ------------------------------------------------
+// ---- Diffuse tail (Sec. 2.2, Eq. (8); Sec. 3.3) ------------------------------
 // The ISM part is planned as a call with t_max = t_diff; its RIRs go to the
 // workspace after the plan's own arrays, and the diffuse kernel writes the
 // full RIRs (ISM part copied, tail drawn) to out.

@@ -259,7 +259,8 @@ def diffuse_workspace_size(room: Room, t_diff: float, t60: float, n_src: int, n_
 
 class DiffuseSimulator:
     """Reusable device state for ``ism_simulate_diffuse``: RIRs [n_src, n_rcv, nS(t_max)]
-    with the ISM part up to ``t_diff`` and a logistic-noise tail after it (Sec. 2.3)."""
+    with the ISM part up to ``t_diff`` and a logistic-noise tail after it
+    (Sec. 2.2, Eq. (8); Sec. 3.3)."""
 
     def __init__(self, room: Room, src, rcv, t_diff: float, t60: float, seed: int = 0, precision: str = "fp32",
                  device: str = "cuda", check: bool = True):

@@ -1,4 +1,4 @@
-"""Pins of the diffuse-tail oracle (Sec. 2.3) on the CPU.
+"""Pins of the diffuse-tail oracle (Sec. 2.2, Eq. (8); Sec. 3.3) on the CPU.
 
 The noise generator is pinned statistically (uniform, balanced, independent
 words; a single flipped counter bit changes about half of the output bits),
