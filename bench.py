@@ -180,7 +180,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="room_32_receivers",
-                    choices=["room_32_receivers", "single_rir", "large_room_uca", "batch_rooms"])
+                    choices=["room_32_receivers", "single_rir", "large_room_uca", "batch_rooms",
+                             "paper_room_128rir", "paper_room_diffuse_1024rir"])
     ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"],
@@ -221,12 +222,20 @@ def main() -> int:
         w = workloads.WORKLOADS[args.workload](0)
         ws = [w]
         room = ism.room_for(w)
-        sim = ism.Simulator(room, w.src, w.rcv, precision=args.precision)
+        if w.t_diff > 0.0:
+            # ISM part up to t_diff, diffuse tail after it: taps are those of the ISM part
+            sim = ism.DiffuseSimulator(room, w.src, w.rcv, w.t_diff, w.t60, seed=0, precision=args.precision)
+            ism_room = ism.Room(room.room, room.beta, room.n_img, room.c, room.fs, w.t_diff, room.t_w)
+            taps = ism.count_taps(ism_room, w.src, w.rcv)
+        else:
+            sim = ism.Simulator(room, w.src, w.rcv, precision=args.precision)
+            taps = ism.count_taps(room, w.src, w.rcv)
         n_rir = sim.n_src * sim.n_rcv
-        taps = ism.count_taps(room, w.src, w.rcv)
         config = {"workload": w.name, "room_m": list(map(float, w.room)), "t60_s": w.t60, "fs": w.fs,
                   "t_w_s": w.t_w, "n_src": int(sim.n_src), "n_rcv": int(sim.n_rcv), "n_samples": room.n_samples,
                   "n_img": list(room.n_img), "taps_per_step": int(taps), "parallelism": "single GPU"}
+        if w.t_diff > 0.0:
+            config["t_diff_s"] = w.t_diff
     hip = _HipEvents()
     ev_a = [hip.create() for _ in range(args.steps)]
     ev_b = [hip.create() for _ in range(args.steps)]
@@ -276,7 +285,7 @@ def main() -> int:
                      "kernel_ms_mean": kmean,
                      "kernel_ms_p50": float(np.median(kern_ms)), "flop_per_tap": FLOP_PER_TAP},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and all(getattr(x, "t_diff", 0.0) == 0.0 for x in ws):
         res = sim.outs if args.workload == "batch_rooms" else [sim.out]
         gpu_outs = [o.cpu().numpy() for o in res[:args.cpu_sample]]
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_sample, gpu_outs)

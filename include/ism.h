@@ -171,6 +171,13 @@ int ism_simulate_diffuse(const ism_room *room, double t_diff, double t60, uint64
                          int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
                          size_t ws_bytes, void *stream);
 
+/* ism_simulate_diffuse, plus the events of ism_simulate_timed recorded around
+ * the tap accumulation kernel of the ISM part. Same arguments, checks and
+ * results as ism_simulate_diffuse. */
+int ism_simulate_diffuse_timed(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
+                               int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
+                               size_t ws_bytes, void *stream, void *ev_start, void *ev_stop);
+
 /* ---- Batches of rooms --------------------------------------------------------- */
 
 /* One job of a batch: one room with its own sources, receivers and output. */

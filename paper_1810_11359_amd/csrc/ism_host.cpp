@@ -439,6 +439,13 @@ int ism_diffuse_workspace_size(const ism_room *room, double t_diff, double t60, 
 int ism_simulate_diffuse(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src, int n_src,
                          const float *rcv, int n_rcv, int precision, float *out, void *ws, size_t ws_bytes,
                          void *stream) {
+  return ism_simulate_diffuse_timed(room, t_diff, t60, seed, src, n_src, rcv, n_rcv, precision, out, ws, ws_bytes,
+                                    stream, nullptr, nullptr);
+}
+
+int ism_simulate_diffuse_timed(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
+                               int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
+                               size_t ws_bytes, void *stream, void *ev_start, void *ev_stop) {
   Plan p;
   int64_t n_full;
   size_t off_ism, need;
@@ -447,7 +454,7 @@ int ism_simulate_diffuse(const ism_room *room, double t_diff, double t60, uint64
   if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
   if (!ws || ws_bytes < need) return ISM_E_WORKSPACE;
   float *ism = (float *)((char *)ws + off_ism);
-  const int rs = run_plan(p, src, rcv, ism, ws, stream, nullptr, nullptr);
+  const int rs = run_plan(p, src, rcv, ism, ws, stream, ev_start, ev_stop);
   if (rs != ISM_OK) return rs;
   if (launch_diffuse(ism, p.ra.n_samples, out, (int)n_full, p.n_rir, room->fs, t_diff, t60, seed,
                      (hipStream_t)stream) != 0)

@@ -34,7 +34,7 @@ EXPORTS = (
     "ism_time_for_attenuation", "ism_n_samples", "ism_check_room", "ism_check_positions",
     "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed",
     "ism_batch_workspace_size", "ism_batch_prepare", "ism_batch_run", "ism_batch_run_timed",
-    "ism_diffuse_workspace_size", "ism_simulate_diffuse",
+    "ism_diffuse_workspace_size", "ism_simulate_diffuse", "ism_simulate_diffuse_timed",
 )
 
 
@@ -112,6 +112,10 @@ def lib() -> ctypes.CDLL:
         L.ism_simulate_diffuse.restype = ctypes.c_int
         L.ism_simulate_diffuse.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp, ctypes.c_int, fp,
                                            ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t, fp]
+        L.ism_simulate_diffuse_timed.restype = ctypes.c_int
+        L.ism_simulate_diffuse_timed.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp,
+                                                 ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
+                                                 fp, fp, fp]
         _lib = L
     return _lib
 
@@ -282,12 +286,15 @@ class DiffuseSimulator:
         self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
         self.ws_bytes = nbytes
 
-    def run(self, stream=None):
+    def run(self, stream=None, ev_start=None, ev_stop=None):
+        """Launch on ``stream`` (default: torch's current stream); ``ev_start``/``ev_stop``
+        are optional raw hipEvent_t handles recorded around the tap kernel of the ISM part."""
         st = stream if stream is not None else self.torch.cuda.current_stream()
-        _check(lib().ism_simulate_diffuse(ctypes.byref(self._room_c), self.t_diff, self.t60, self.seed,
-                                          self.src.data_ptr(), self.n_src, self.rcv.data_ptr(), self.n_rcv,
-                                          self.precision, self.out.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
-                                          st.cuda_stream), "ism_simulate_diffuse")
+        _check(lib().ism_simulate_diffuse_timed(ctypes.byref(self._room_c), self.t_diff, self.t60, self.seed,
+                                                self.src.data_ptr(), self.n_src, self.rcv.data_ptr(), self.n_rcv,
+                                                self.precision, self.out.data_ptr(), self.ws.data_ptr(),
+                                                self.ws_bytes, st.cuda_stream, ev_start, ev_stop),
+               "ism_simulate_diffuse_timed")
         return self.out
 
 
@@ -300,11 +307,12 @@ def simulate_diffuse(room: Room, src, rcv, t_diff: float, t60: float, seed: int 
 def room_for(w) -> Room:
     """Room of a ``workloads.Workload`` built with this library's helpers: Sabine
     beta for the workload's T60 (times its per-wall jitter, capped at 0.999) and
-    the lattice that keeps every image closer than c * T_max."""
+    the lattice that keeps every image closer than c * T_max (c * t_diff for a
+    workload with a diffuse tail, whose ISM part ends there)."""
     beta = beta_from_t60(w.room, w.t60)
     if w.beta_jitter is not None:
         beta = np.minimum(beta * np.asarray(w.beta_jitter), 0.999)
-    n = n_img_for_time(w.room, w.c, w.t_max)
+    n = n_img_for_time(w.room, w.c, w.t_diff if getattr(w, "t_diff", 0.0) > 0.0 else w.t_max)
     return Room(list(map(float, w.room)), list(map(float, beta)), n, w.c, w.fs, w.t_max, w.t_w)
 
 

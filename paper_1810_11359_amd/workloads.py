@@ -29,6 +29,7 @@ class Workload:
     t_max: float = 0.0        # RIR length [s]
     t_w: float = 0.004        # window length [s]
     beta_jitter: Optional[np.ndarray] = None  # [6] multiplicative factors, or None for uniform beta
+    t_diff: float = 0.0       # > 0: ISM up to t_diff, diffuse tail after it (Sec. 2.2, Eq. (8))
 
 
 def _uniform_positions(rng, room, n, margin=0.5) -> np.ndarray:
@@ -90,10 +91,32 @@ def batch_rooms(n_rooms: int = 1024, seed: int = 0,
     return out
 
 
+def paper_room_128rir(seed: int = 0) -> Workload:
+    """The full-ISM case of the paper's Table 4 and Fig. 4: a 3 x 4 x 2.5 m room,
+    T60 = T_max = 0.7 s, 128 RIRs (1 source, 128 receivers, uniform >= 0.5 m from
+    the walls). The paper does not state fs, T_w or positions: 16 kHz and 4 ms here."""
+    rng = np.random.default_rng(seed)
+    room = np.array([3.0, 4.0, 2.5])
+    return Workload("room_3x4x2.5_t60_0.7_128rcv", room, 0.7, _uniform_positions(rng, room, 1),
+                    _uniform_positions(rng, room, 128), t_max=0.7)
+
+
+def paper_room_diffuse_1024rir(seed: int = 0) -> Workload:
+    """The diffuse-model case of the paper's Table 4 (1024 RIRs, T60 0.7 s, same
+    room): ISM up to the 13 dB attenuation time (T60 13/60, the switch the paper
+    compares with in Sec. 5), diffuse tail to T_max = T60. 1 source, 1024 receivers."""
+    rng = np.random.default_rng(seed)
+    room = np.array([3.0, 4.0, 2.5])
+    return Workload("room_3x4x2.5_t60_0.7_1024rcv_diffuse", room, 0.7, _uniform_positions(rng, room, 1),
+                    _uniform_positions(rng, room, 1024), t_max=0.7, t_diff=0.7 * 13.0 / 60.0)
+
+
 WORKLOADS = {
     "single_rir": single_rir,
     "room_32_receivers": room_32_receivers,
     "large_room_uca": large_room_uca,
+    "paper_room_128rir": paper_room_128rir,
+    "paper_room_diffuse_1024rir": paper_room_diffuse_1024rir,
 }
 
 
