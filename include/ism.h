@@ -178,6 +178,25 @@ int ism_simulate_diffuse_timed(const ism_room *room, double t_diff, double t60, 
                                int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
                                size_t ws_bytes, void *stream, void *ev_start, void *ev_stop);
 
+/* ---- Moving source (Sec. 3.4) -------------------------------------------------- */
+
+/* Filters a source signal through the RIRs of a trajectory by overlap-add:
+ * x is cut into n_pos segments of seg_len = ceil(n_x / n_pos) samples
+ * (segment p = samples [p seg_len, min((p+1) seg_len, n_x))), segment p is
+ * convolved with the RIR of trajectory point p to each microphone and added
+ * at its offset, i.e. y[m][n] = sum_k x[n - k] rir[p(n - k)][m][k] with
+ * p(i) = floor(i / seg_len).
+ *   x    device float32 [n_x];
+ *   rir  device float32 [n_pos][n_mic][n_rir] (the output layout of
+ *        ism_simulate with the trajectory points as sources and the
+ *        microphones as receivers);
+ *   y    device float32 [n_mic][n_x + n_rir - 1], fully overwritten.
+ * 1 <= n_pos <= n_x, n_mic <= 65535, n_rir >= 1. Allocates nothing; the sum
+ * order is fixed (bitwise reproducible). Asynchronous on stream.
+ * Errors: ISM_E_INVALID_ARG, ISM_E_TOO_LARGE before any launch. */
+int ism_filter_trajectory(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
+                          void *stream);
+
 /* ---- Batches of rooms --------------------------------------------------------- */
 
 /* One job of a batch: one room with its own sources, receivers and output. */

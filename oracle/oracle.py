@@ -252,3 +252,27 @@ def diffuse_rir(L, beta, n_img, c, fs, t_max, t_w, t_diff, t60, seed, src, rcv) 
         z = logistic_from_bits(noise_bits(seed, i, k))
         out[s, r, k_diff:] = z * np.sqrt(A[s, r] * env)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Moving source (Sec. 3.4): overlap-add of the source signal's segments, each
+# convolved (numpy's direct convolution, float64) with the RIR of its
+# trajectory point.
+# ---------------------------------------------------------------------------
+def filter_trajectory(x, rirs) -> np.ndarray:
+    """x [n_x], rirs [n_pos, n_mic, n_rir] -> y [n_mic, n_x + n_rir - 1]:
+    segment p = x[p L : (p + 1) L] with L = ceil(n_x / n_pos) is convolved with
+    rirs[p, m] and added at offset p L."""
+    x = np.asarray(x, dtype=np.float64)
+    rirs = np.asarray(rirs, dtype=np.float64)
+    n_pos, n_mic, n_rir = rirs.shape
+    n_x = x.shape[0]
+    seg = -(-n_x // n_pos)
+    y = np.zeros((n_mic, n_x + n_rir - 1))
+    for p in range(n_pos):
+        xs = x[p * seg:(p + 1) * seg]
+        if xs.size == 0:
+            continue
+        for m in range(n_mic):
+            y[m, p * seg:p * seg + xs.size + n_rir - 1] += np.convolve(xs, rirs[p, m])
+    return y

@@ -1,0 +1,90 @@
+// Moving-source filtering (Sec. 3.4): a source signal x is cut into n_pos
+// consecutive segments of seg_len = ceil(n_x / n_pos) samples (the last one
+// shorter when n_pos does not divide n_x); segment p is convolved with the RIR
+// of trajectory point p to each microphone and the results are added at the
+// segment's offset (overlap-add). Equivalently, for microphone m,
+//   y_m[n] = sum_k x[n - k] h_{p(n - k), m}[k],   p(i) = floor(i / seg_len),
+// a filter that changes with the segment of the input sample. The paper runs
+// this with batched FFTs; here it is a direct sum: the RIRs of one point are
+// short next to the signal, the sum has no plan or work area, and every
+// output is added in a fixed order (bitwise reproducible).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace ism {
+
+constexpr int FT = 256;       // threads per block
+constexpr int FR = 4;         // consecutive outputs per thread
+constexpr int FN = FT * FR;   // outputs per block
+constexpr int FK = 256;       // filter taps per chunk
+constexpr int XPAD = 4;       // zero slots in front of the staged input window
+
+// grid = (ceil(n_y / FN), n_mic). For each chunk of FK taps and each segment
+// the chunk's input window touches, the block stages the window (input
+// samples of other segments zeroed) and the segment's FK taps in LDS; a
+// thread keeps its 4 outputs in registers and slides a 4-sample input window
+// down the taps (4 new input reads and one 16-byte tap read per 16 FMAs).
+__global__ __launch_bounds__(FT) void filter_kernel(const float *__restrict__ x, int n_x,
+                                                    const float *__restrict__ rir, int n_mic, int n_rir,
+                                                    int seg_len, float *__restrict__ y, int n_y) {
+  const int m = blockIdx.y;
+  const int n0 = blockIdx.x * FN;
+  const int tid = threadIdx.x;
+  __shared__ float xs[XPAD + FN + FK];
+  __shared__ __attribute__((aligned(16))) float hs[FK];
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  if (tid < XPAD) xs[tid] = 0.0f;
+  // input index of window slot w: i = n0 - kc - FK + 1 + w; output n = n0 + FR tid + r
+  // with tap k = kc + j reads slot FR tid + r + FK - 1 - j
+  const int base = XPAD + FR * tid + FK - 1;
+  for (int kc = 0; kc < n_rir; kc += FK) {
+    const int i_lo = n0 - kc - FK + 1;
+    const int lo = max(i_lo, 0), hi = min(n0 + FN - 1 - kc, n_x - 1);
+    if (lo > hi) continue;  // uniform over the block
+    for (int p = lo / seg_len; p <= hi / seg_len; ++p) {
+      const int s0 = p * seg_len, s1 = min(s0 + seg_len, n_x);
+      __syncthreads();  // the previous segment's window is used up
+      for (int w = tid; w < FN + FK - 1; w += FT) {
+        const int i = i_lo + w;
+        xs[XPAD + w] = (i >= s0 && i < s1) ? x[i] : 0.0f;
+      }
+      const float *h = rir + ((size_t)p * n_mic + m) * n_rir;
+      for (int j = tid; j < FK; j += FT) hs[j] = (kc + j < n_rir) ? h[kc + j] : 0.0f;
+      __syncthreads();
+      float v0 = xs[base], v1 = xs[base + 1], v2 = xs[base + 2], v3 = xs[base + 3];
+      for (int j = 0; j < FK; j += 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 t = *reinterpret_cast<const f4 *>(&hs[j]);
+        const float u1 = xs[base - j - 1], u2 = xs[base - j - 2], u3 = xs[base - j - 3], u4 = xs[base - j - 4];
+        a0 = __builtin_fmaf(v0, t.x, a0); a0 = __builtin_fmaf(u1, t.y, a0);
+        a0 = __builtin_fmaf(u2, t.z, a0); a0 = __builtin_fmaf(u3, t.w, a0);
+        a1 = __builtin_fmaf(v1, t.x, a1); a1 = __builtin_fmaf(v0, t.y, a1);
+        a1 = __builtin_fmaf(u1, t.z, a1); a1 = __builtin_fmaf(u2, t.w, a1);
+        a2 = __builtin_fmaf(v2, t.x, a2); a2 = __builtin_fmaf(v1, t.y, a2);
+        a2 = __builtin_fmaf(v0, t.z, a2); a2 = __builtin_fmaf(u1, t.w, a2);
+        a3 = __builtin_fmaf(v3, t.x, a3); a3 = __builtin_fmaf(v2, t.y, a3);
+        a3 = __builtin_fmaf(v1, t.z, a3); a3 = __builtin_fmaf(v0, t.w, a3);
+        v3 = u1; v2 = u2; v1 = u3; v0 = u4;
+      }
+    }
+  }
+  const int nb = n0 + FR * tid;
+  float *ym = y + (size_t)m * n_y;
+  if (nb < n_y) ym[nb] = a0;
+  if (nb + 1 < n_y) ym[nb + 1] = a1;
+  if (nb + 2 < n_y) ym[nb + 2] = a2;
+  if (nb + 3 < n_y) ym[nb + 3] = a3;
+}
+
+int launch_filter(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
+                  hipStream_t st) {
+  const int seg_len = (n_x + n_pos - 1) / n_pos;
+  const int n_y = n_x + n_rir - 1;
+  const unsigned gx = (unsigned)((n_y + FN - 1) / FN);
+  hipLaunchKernelGGL(filter_kernel, dim3(gx, (unsigned)n_mic), dim3(FT), 0, st, x, n_x, rir, n_mic, n_rir, seg_len,
+                     y, n_y);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ism

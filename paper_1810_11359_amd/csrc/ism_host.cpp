@@ -30,6 +30,8 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
                  float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
                    double t60, uint64_t seed, hipStream_t st);
+int launch_filter(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
+                  hipStream_t st);
 }  // namespace ism
 
 using namespace ism;
@@ -691,3 +693,13 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
 }
 
 }  // extern "C"
+
+// ---- Moving-source filtering (Sec. 3.4) --------------------------------------
+int ism_filter_trajectory(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
+                          void *stream) {
+  if (!x || !rir || !y) return ISM_E_INVALID_ARG;
+  if (n_x < 1 || n_pos < 1 || n_mic < 1 || n_rir < 1 || n_pos > n_x) return ISM_E_INVALID_ARG;
+  if (n_mic > 65535 || (int64_t)n_x + n_rir - 1 > (int64_t)0x7fffffff) return ISM_E_TOO_LARGE;
+  if (launch_filter(x, n_x, rir, n_pos, n_mic, n_rir, y, (hipStream_t)stream) != 0) return ISM_E_DEVICE;
+  return ISM_OK;
+}

@@ -35,6 +35,7 @@ EXPORTS = (
     "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed",
     "ism_batch_workspace_size", "ism_batch_prepare", "ism_batch_run", "ism_batch_run_timed",
     "ism_diffuse_workspace_size", "ism_simulate_diffuse", "ism_simulate_diffuse_timed",
+    "ism_filter_trajectory",
 )
 
 
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
         L.ism_simulate_diffuse.restype = ctypes.c_int
         L.ism_simulate_diffuse.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp, ctypes.c_int, fp,
                                            ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t, fp]
+        L.ism_filter_trajectory.restype = ctypes.c_int
+        L.ism_filter_trajectory.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, fp]
         L.ism_simulate_diffuse_timed.restype = ctypes.c_int
         L.ism_simulate_diffuse_timed.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp,
                                                  ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
@@ -302,6 +305,24 @@ def simulate_diffuse(room: Room, src, rcv, t_diff: float, t60: float, seed: int 
                      device: str = "cuda"):
     """RIRs [n_src, n_rcv, nS] with the ISM up to t_diff and the diffuse tail after it."""
     return DiffuseSimulator(room, src, rcv, t_diff, t60, seed, precision, device).run()
+
+
+def filter_trajectory(x, rirs, stream=None):
+    """Moving source (Sec. 3.4): x [n_x] float32 device tensor, rirs [n_pos, n_mic,
+    n_rir] float32 device tensor (ism_simulate output with the trajectory points as
+    sources). Returns y [n_mic, n_x + n_rir - 1] on the same device."""
+    import torch
+
+    if x.dtype != torch.float32 or rirs.dtype != torch.float32 or x.dim() != 1 or rirs.dim() != 3:
+        raise IsmError(ISM_E_INVALID_ARG, "filter_trajectory")
+    x = x.contiguous()
+    rirs = rirs.contiguous()
+    n_pos, n_mic, n_rir = rirs.shape
+    y = torch.empty((n_mic, x.shape[0] + n_rir - 1), dtype=torch.float32, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().ism_filter_trajectory(x.data_ptr(), int(x.shape[0]), rirs.data_ptr(), int(n_pos), int(n_mic),
+                                       int(n_rir), y.data_ptr(), st.cuda_stream), "ism_filter_trajectory")
+    return y
 
 
 def room_for(w) -> Room:
