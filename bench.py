@@ -174,6 +174,52 @@ def serve(args) -> int:
     return 0
 
 
+def bench_moving_source(args) -> int:
+    """Moving-source filtering (ism_filter_trajectory): a 10 s signal at 16 kHz
+    through the RIRs of 100 trajectory points to an 8-mic array in a 4 x 5 x 3 m
+    room at T60 0.5 s (RIRs of 8000 samples, computed once by ism_simulate,
+    outside the timed region). One step = one filter call; value in G MAC/s
+    (n_x x n_rir x n_mic multiply-adds), roofline against the FP32 vector peak
+    at 2 FLOP per multiply-add."""
+    import torch
+
+    from paper_1810_11359_amd import ism
+
+    L, t60, fs = [4.0, 5.0, 3.0], 0.5, 16000.0
+    room = ism.Room(L, list(ism.beta_from_t60(L, t60)), ism.n_img_for_time(L, 343.0, t60), 343.0, fs, t60, 0.004)
+    rng = np.random.default_rng(0)
+    pts = np.linspace([0.8, 0.8, 1.6], [3.2, 4.2, 1.6], 100).astype(np.float32)
+    mics = (np.array([2.0, 2.5, 1.2]) + 0.05 * np.stack([np.cos(np.arange(8) * np.pi / 4),
+                                                          np.sin(np.arange(8) * np.pi / 4), np.zeros(8)], 1))
+    rirs = ism.simulate(room, pts, mics.astype(np.float32))
+    x = torch.from_numpy(rng.standard_normal(int(10 * fs)).astype(np.float32)).cuda()
+    n_pos, n_mic, n_rir = rirs.shape
+    macs = x.shape[0] * n_rir * n_mic
+    for _ in range(args.warmup):
+        ism.filter_trajectory(x, rirs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        ism.filter_trajectory(x, rirs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    achieved = 2.0 * macs / (ms_step / 1e3) / 1e12
+    out = {"metric": "moving-source filter multiply-adds/s (G/s)", "value": macs / (ms_step / 1e3) / 1e9,
+           "unit": "G MAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": "moving_source_10s_16k_100pts_8mics", "n_x": int(x.shape[0]), "n_pos": n_pos,
+                      "n_mic": n_mic, "n_rir": n_rir, "macs_per_step": macs, "parallelism": "single GPU"},
+           "wall_s_timed": time.perf_counter() - wall0,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+                        "frac": achieved / FP32_VECTOR_PEAK, "traffic": None, "kernel": "filter_kernel (whole call)",
+                        "kernel_ms_mean": ms_step, "flop_per_mac": 2}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,7 +227,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="room_32_receivers",
                     choices=["room_32_receivers", "single_rir", "large_room_uca", "batch_rooms",
-                             "paper_room_128rir", "paper_room_diffuse_1024rir"])
+                             "paper_room_128rir", "paper_room_diffuse_1024rir", "moving_source_10s"])
     ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"],
@@ -202,6 +248,8 @@ def main() -> int:
 
     if args.rate > 0:
         return serve(args)
+    if args.workload == "moving_source_10s":
+        return bench_moving_source(args)
     if args.workload == "batch_rooms":
         def feasible(room, t60):
             try:
