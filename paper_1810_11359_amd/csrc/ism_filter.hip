@@ -14,30 +14,40 @@
 
 namespace ism {
 
-constexpr int FT = 256;       // threads per block
+constexpr int FT = 128;       // threads per block
 constexpr int FR = 4;         // consecutive outputs per thread
 constexpr int FN = FT * FR;   // outputs per block
 constexpr int FK = 256;       // filter taps per chunk
-constexpr int XPAD = 4;       // zero slots in front of the staged input window
+constexpr int FJ = 64;        // taps per sub-chunk (the unit a wave skips)
+constexpr int FW = 64 * FR;   // outputs per wave
+constexpr int XPAD = 1;       // zero slot in front of the staged input window (aligns the 16-byte reads)
 
 // grid = (ceil(n_y / FN), n_mic). For each chunk of FK taps and each segment
 // the chunk's input window touches, the block stages the window (input
 // samples of other segments zeroed) and the segment's FK taps in LDS; a
 // thread keeps its 4 outputs in registers and slides a 4-sample input window
-// down the taps (4 new input reads and one 16-byte tap read per 16 FMAs).
+// down the taps (one 16-byte input read and one 16-byte tap read per 16
+// FMAs). A wave skips each sub-chunk of FJ taps whose inputs, for its FW
+// outputs, all lie outside the staged segment (or whose taps are past the
+// RIR's end): those products are all zero, so skipping them leaves every sum
+// unchanged and removes most of the work on zeroed samples, since a wave's
+// input range is short next to a segment.
 __global__ __launch_bounds__(FT) void filter_kernel(const float *__restrict__ x, int n_x,
                                                     const float *__restrict__ rir, int n_mic, int n_rir,
                                                     int seg_len, float *__restrict__ y, int n_y) {
   const int m = blockIdx.y;
   const int n0 = blockIdx.x * FN;
   const int tid = threadIdx.x;
-  __shared__ float xs[XPAD + FN + FK];
+  __shared__ __attribute__((aligned(16))) float xs[XPAD + FN + FK];
   __shared__ __attribute__((aligned(16))) float hs[FK];
   float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
   if (tid < XPAD) xs[tid] = 0.0f;
   // input index of window slot w: i = n0 - kc - FK + 1 + w; output n = n0 + FR tid + r
   // with tap k = kc + j reads slot FR tid + r + FK - 1 - j
   const int base = XPAD + FR * tid + FK - 1;
+  // first output of this thread's wave (uniform over the wave)
+  const int nw = __builtin_amdgcn_readfirstlane(n0 + FW * (tid / 64));
+  typedef float f4 __attribute__((ext_vector_type(4)));
   for (int kc = 0; kc < n_rir; kc += FK) {
     const int i_lo = n0 - kc - FK + 1;
     const int lo = max(i_lo, 0), hi = min(n0 + FN - 1 - kc, n_x - 1);
@@ -52,20 +62,27 @@ __global__ __launch_bounds__(FT) void filter_kernel(const float *__restrict__ x,
       const float *h = rir + ((size_t)p * n_mic + m) * n_rir;
       for (int j = tid; j < FK; j += FT) hs[j] = (kc + j < n_rir) ? h[kc + j] : 0.0f;
       __syncthreads();
-      float v0 = xs[base], v1 = xs[base + 1], v2 = xs[base + 2], v3 = xs[base + 3];
-      for (int j = 0; j < FK; j += 4) {
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        const f4 t = *reinterpret_cast<const f4 *>(&hs[j]);
-        const float u1 = xs[base - j - 1], u2 = xs[base - j - 2], u3 = xs[base - j - 3], u4 = xs[base - j - 4];
-        a0 = __builtin_fmaf(v0, t.x, a0); a0 = __builtin_fmaf(u1, t.y, a0);
-        a0 = __builtin_fmaf(u2, t.z, a0); a0 = __builtin_fmaf(u3, t.w, a0);
-        a1 = __builtin_fmaf(v1, t.x, a1); a1 = __builtin_fmaf(v0, t.y, a1);
-        a1 = __builtin_fmaf(u1, t.z, a1); a1 = __builtin_fmaf(u2, t.w, a1);
-        a2 = __builtin_fmaf(v2, t.x, a2); a2 = __builtin_fmaf(v1, t.y, a2);
-        a2 = __builtin_fmaf(v0, t.z, a2); a2 = __builtin_fmaf(u1, t.w, a2);
-        a3 = __builtin_fmaf(v3, t.x, a3); a3 = __builtin_fmaf(v2, t.y, a3);
-        a3 = __builtin_fmaf(v1, t.z, a3); a3 = __builtin_fmaf(v0, t.w, a3);
-        v3 = u1; v2 = u2; v1 = u3; v0 = u4;
+      for (int jb = 0; jb < FK; jb += FJ) {
+        // the wave's outputs [nw, nw + FW) read inputs [ilo, ihi] for these taps
+        const int ilo = nw - kc - jb - FJ + 1, ihi = nw + FW - 1 - kc - jb;
+        if (ihi < s0 || ilo >= s1 || kc + jb >= n_rir) continue;  // uniform over the wave
+        const f4 v = *reinterpret_cast<const f4 *>(&xs[base - jb]);
+        float v0 = v.x, v1 = v.y, v2 = v.z, v3 = v.w;
+#pragma unroll 4
+        for (int j = jb; j < jb + FJ; j += 4) {
+          const f4 t = *reinterpret_cast<const f4 *>(&hs[j]);
+          // u.w, u.z, u.y, u.x = inputs one, two, three, four slots before v0
+          const f4 u = *reinterpret_cast<const f4 *>(&xs[base - j - 4]);
+          a0 = __builtin_fmaf(v0, t.x, a0); a0 = __builtin_fmaf(u.w, t.y, a0);
+          a0 = __builtin_fmaf(u.z, t.z, a0); a0 = __builtin_fmaf(u.y, t.w, a0);
+          a1 = __builtin_fmaf(v1, t.x, a1); a1 = __builtin_fmaf(v0, t.y, a1);
+          a1 = __builtin_fmaf(u.w, t.z, a1); a1 = __builtin_fmaf(u.z, t.w, a1);
+          a2 = __builtin_fmaf(v2, t.x, a2); a2 = __builtin_fmaf(v1, t.y, a2);
+          a2 = __builtin_fmaf(v0, t.z, a2); a2 = __builtin_fmaf(u.w, t.w, a2);
+          a3 = __builtin_fmaf(v3, t.x, a3); a3 = __builtin_fmaf(v2, t.y, a3);
+          a3 = __builtin_fmaf(v1, t.z, a3); a3 = __builtin_fmaf(v0, t.w, a3);
+          v3 = u.w; v2 = u.z; v1 = u.y; v0 = u.x;
+        }
       }
     }
   }
