@@ -102,11 +102,12 @@ def _oracle_args(orc, w):
     return (w.room, beta, n, w.c, w.fs, w.t_max, w.t_w)
 
 
-def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None):
+def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None, lut_q: int = 0):
     """FP64 oracle on a bounded sample: the first ``n_rcv_sample`` receivers of a
     single-room workload, or the first rooms of a batch up to that many RIRs.
     With ``gpu_outs`` (host arrays [n_src, n_rcv, nS] per workload) it also
-    reports the largest max|h_gpu - h_oracle| / max|h_oracle| over the sample."""
+    reports the largest max|h_gpu - h_oracle| / max|h_oracle| over the sample.
+    lut_q > 0: the oracle's table taps (Eq. (9)) at lut_q points per sample."""
     from oracle import oracle as orc
 
     orc.build()
@@ -120,7 +121,8 @@ def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None):
     threads = max(1, min(os.cpu_count() or 1, 16, sum(r.shape[0] for _, r in jobs)))
     taps = sum(orc.count_taps(*_oracle_args(orc, w), w.src, r) for w, r in jobs)
     t0 = time.perf_counter()
-    refs = [orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=min(threads, r.shape[0])) for w, r in jobs]
+    refs = [orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=min(threads, r.shape[0]), lut_q=lut_q)
+            for w, r in jobs]
     dt = time.perf_counter() - t0
     n = sum(r.shape[0] for _, r in jobs)
     out = {"value": taps / dt / 1e9, "unit": "G taps/s", "cores": threads, "kind": "oracle",
@@ -230,8 +232,9 @@ def main() -> int:
                              "paper_room_128rir", "paper_room_diffuse_1024rir", "moving_source_10s"])
     ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"],
-                    help="tap arithmetic (accumulation is FP32 in both)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "lut"],
+                    help="tap arithmetic (accumulation is FP32 in all): FP32, packed FP16, or FP32 "
+                         "interpolation in a table of the windowed sinc (single-room workloads)")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving mode: replay a Poisson stream of mixed RIR jobs at this many jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving mode: jobs in the stream")
@@ -336,7 +339,7 @@ def main() -> int:
     if not args.no_cpu_baseline and all(getattr(x, "t_diff", 0.0) == 0.0 for x in ws):
         res = sim.outs if args.workload == "batch_rooms" else [sim.out]
         gpu_outs = [o.cpu().numpy() for o in res[:args.cpu_sample]]
-        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_sample, gpu_outs)
+        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_sample, gpu_outs, lut_q=16 if args.precision == "lut" else 0)
         out["max_err_vs_oracle"] = out["cpu_baseline"].pop("max_err_vs_oracle")
     print(json.dumps(out), flush=True)
     return 0

@@ -8,7 +8,9 @@
  *   Sec. 2.1  lattice of images, Eq. (1) positions, Eq. (2)-(3) distance and
  *             delay, Eq. (4) amplitude, Eq. (5) RIR as a sum of delayed impulses;
  *   Sec. 2.2  Eq. (6) Hann-windowed sinc replacing the impulse (cut-off fs/2),
- *             signed reflection coefficients, Eq. (7) Sabine's formula.
+ *             signed reflection coefficients, Eq. (7) Sabine's formula;
+ *   Sec. 3.5  Eq. (9) the windowed sinc tabulated at Q points per sample and
+ *             read by linear interpolation (the lookup-table variant).
  * Readings where the paper is silent (wall exponents, grid size, taps before
  * t = 0) are stated at the function that takes them.
  *
@@ -113,11 +115,52 @@ static double windowed_sinc(double v, double W) {
   return hann * sinc;
 }
 
+/* Eq. (9): LUT[n] = 0.5 (1 + cos(2 pi n / (Q W))) sinc(pi n / Q) for
+ * n = -QW/2 .. QW/2, i.e. Eq. (6) at v = n / Q; sinc(pi u) = sin(pi u)/(pi u).
+ * Stored at index n + QW/2. Returns NULL when QW/2 is not an integer. */
+static double *make_lut(double W, int q) {
+  const double half = q * W / 2.0;
+  const int64_t h = (int64_t)llround(half);
+  if (q < 1 || h < 1 || fabs(half - (double)h) > 1e-9 * half) return NULL;
+  double *lut = (double *)malloc(sizeof(double) * (size_t)(2 * h + 1));
+  if (!lut) return NULL;
+  for (int64_t n = -h; n <= h; ++n) {
+    double hann = 0.5 * (1.0 + cos(2.0 * PI * (double)n / (q * W)));
+    double u = (double)n / q;
+    double sinc = (n == 0) ? 1.0 : sin(PI * u) / (PI * u);
+    lut[n + h] = hann * sinc;
+  }
+  return lut;
+}
+
+/* Sec. 3.5: the tap at v (|v| < W/2) by linear interpolation between the two
+ * table entries around v Q: n0 = floor(v Q), a = v Q - n0,
+ * tap = LUT[n0] + a (LUT[n0 + 1] - LUT[n0]). */
+static double lut_tap(const double *lut, double W, int q, double v) {
+  const int64_t h = (int64_t)llround(q * W / 2.0);
+  const double p = v * q;
+  int64_t n0 = (int64_t)floor(p);
+  if (n0 < -h) n0 = -h;          /* only p = -QW/2 exactly */
+  if (n0 > h - 1) n0 = h - 1;    /* only p = +QW/2 exactly */
+  const double a = p - (double)n0;
+  return lut[n0 + h] + a * (lut[n0 + 1 + h] - lut[n0 + h]);
+}
+
+int oracle_lut_taps(const double *v, int64_t n, double W, int q, double *out) {
+  double *lut = make_lut(W, q);
+  if (!lut) return -1;
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = (fabs(v[i]) < W / 2.0) ? lut_tap(lut, W, q, v[i]) : 0.0;
+  free(lut);
+  return 0;
+}
+
 /* Eq. (5) with Eq. (6) in place of the impulse, restricted to k in
  * [k_begin, k_end). Taps that would fall before k = 0 or after the last sample
- * are dropped (reading: no wrap-around, no shift). */
-int oracle_rir_window(const oracle_room *room, const double src[3], const double rcv[3],
-                      int64_t k_begin, int64_t k_end, double *out) {
+ * are dropped (reading: no wrap-around, no shift). With lut != NULL each tap
+ * is read from the table of Eq. (9) (q points per sample) instead. */
+static int rir_window(const oracle_room *room, const double src[3], const double rcv[3], int64_t k_begin,
+                      int64_t k_end, const double *lut, int q, double *out) {
   const double W = room->t_w * room->fs;
   for (int64_t k = k_begin; k < k_end; ++k) out[k - k_begin] = 0.0;
   for (int nx = lat_lo(room->n[0]); nx < lat_hi(room->n[0]); ++nx)
@@ -131,10 +174,16 @@ int oracle_rir_window(const oracle_room *room, const double src[3], const double
         if (last > k_end - 1) last = k_end - 1;
         for (int64_t k = first; k <= last; ++k) {
           double v = (double)k - im.x;
-          if (fabs(v) < W / 2.0) out[k - k_begin] += im.A * windowed_sinc(v, W);
+          if (fabs(v) < W / 2.0)
+            out[k - k_begin] += im.A * (lut ? lut_tap(lut, W, q, v) : windowed_sinc(v, W));
         }
       }
   return 0;
+}
+
+int oracle_rir_window(const oracle_room *room, const double src[3], const double rcv[3],
+                      int64_t k_begin, int64_t k_end, double *out) {
+  return rir_window(room, src, rcv, k_begin, k_end, NULL, 0, out);
 }
 
 typedef struct {
@@ -142,6 +191,8 @@ typedef struct {
   const double *src, *rcv;
   int n_src, n_rcv;
   int64_t k_begin, k_end;
+  const double *lut;
+  int q;
   double *out;
   int next, status;
   pthread_mutex_t lock;
@@ -156,8 +207,8 @@ static void *batch_worker(void *arg) {
     pthread_mutex_unlock(&b->lock);
     if (p >= b->n_src * b->n_rcv) break;
     int s = p / b->n_rcv, r = p % b->n_rcv;
-    int st = oracle_rir_window(b->room, b->src + 3 * s, b->rcv + 3 * r, b->k_begin, b->k_end,
-                               b->out + (int64_t)p * len);
+    int st = rir_window(b->room, b->src + 3 * s, b->rcv + 3 * r, b->k_begin, b->k_end, b->lut, b->q,
+                        b->out + (int64_t)p * len);
     if (st != 0) {
       pthread_mutex_lock(&b->lock);
       if (b->status == 0) b->status = st;
@@ -167,11 +218,18 @@ static void *batch_worker(void *arg) {
   return NULL;
 }
 
-int oracle_rir_batch(const oracle_room *room, const double *src, int n_src, const double *rcv,
-                     int n_rcv, int64_t k_begin, int64_t k_end, int n_threads, double *out) {
-  if (n_src < 0 || n_rcv < 0 || k_begin < 0 || k_end < k_begin) return -1;
+int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, const double *rcv,
+                         int n_rcv, int64_t k_begin, int64_t k_end, int q, int n_threads, double *out) {
+  if (n_src < 0 || n_rcv < 0 || k_begin < 0 || k_end < k_begin || q < 0) return -1;
   if (n_threads < 1) n_threads = 1;
+  double *lut = NULL;
+  if (q > 0) {
+    lut = make_lut(room->t_w * room->fs, q);
+    if (!lut) return -1;
+  }
   batch_t b;
+  b.lut = lut;
+  b.q = q;
   b.room = room;
   b.src = src;
   b.rcv = rcv;
@@ -190,8 +248,14 @@ int oracle_rir_batch(const oracle_room *room, const double *src, int n_src, cons
   if (started == 0) batch_worker(&b);
   for (int i = 0; i < started; ++i) pthread_join(th[i], NULL);
   free(th);
+  free(lut);
   pthread_mutex_destroy(&b.lock);
   return b.status;
+}
+
+int oracle_rir_batch(const oracle_room *room, const double *src, int n_src, const double *rcv,
+                     int n_rcv, int64_t k_begin, int64_t k_end, int n_threads, double *out) {
+  return oracle_rir_batch_lut(room, src, n_src, rcv, n_rcv, k_begin, k_end, 0, n_threads, out);
 }
 
 int64_t oracle_image_list(const oracle_room *room, const double src[3], const double rcv[3],

@@ -61,6 +61,17 @@ int oracle_rir_batch(const oracle_room *room, const double *src, int n_src,
                      const double *rcv, int n_rcv, int64_t k_begin, int64_t k_end,
                      int n_threads, double *out);
 
+/* As oracle_rir_batch, with every tap read from the table of Eq. (9) at q
+ * points per sample by linear interpolation (Sec. 3.5) when q > 0 (q = 0: the
+ * exact Eq. (6)). Returns -1 when q W / 2 is not an integer. */
+int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, const double *rcv,
+                         int n_rcv, int64_t k_begin, int64_t k_end, int q, int n_threads, double *out);
+
+/* Table taps of Sec. 3.5 at the offsets v[0..n) (v = k - x in samples, 0 for
+ * |v| >= W/2), table of Eq. (9) at q points per sample. Returns -1 when
+ * q W / 2 is not an integer. */
+int oracle_lut_taps(const double *v, int64_t n, double W, int q, double *out);
+
 /* Every lattice image in the order nx, ny, nz (outermost first). When idx/vals
  * are non-null, writes up to cap entries: idx[3*i..] = (nx, ny, nz) and
  * vals[4*i..] = (gain, distance d [m], delay x = d*fs/c [samples],

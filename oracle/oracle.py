@@ -60,6 +60,11 @@ def lib():
         L.oracle_rir_batch.restype = ctypes.c_int
         L.oracle_rir_batch.argtypes = [ctypes.POINTER(_Room), dp, ctypes.c_int, dp, ctypes.c_int,
                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp]
+        L.oracle_rir_batch_lut.restype = ctypes.c_int
+        L.oracle_rir_batch_lut.argtypes = [ctypes.POINTER(_Room), dp, ctypes.c_int, dp, ctypes.c_int,
+                                           ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, dp]
+        L.oracle_lut_taps.restype = ctypes.c_int
+        L.oracle_lut_taps.argtypes = [dp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_image_list.restype = ctypes.c_int64
         L.oracle_image_list.argtypes = [ctypes.POINTER(_Room), dp, dp, ctypes.POINTER(ctypes.c_int32), dp,
                                         ctypes.c_int64]
@@ -114,8 +119,11 @@ def time_for_attenuation(t60: float, att_db: float) -> float:
 
 
 def rir(L, beta, n_img, c, fs, t_max, t_w, src, rcv, k_begin: int = 0, k_end: int | None = None,
-        n_threads: int | None = None) -> np.ndarray:
-    """RIRs [n_src, n_rcv, k_end - k_begin] in float64 (default: the whole RIR)."""
+        n_threads: int | None = None, lut_q: int = 0) -> np.ndarray:
+    """RIRs [n_src, n_rcv, k_end - k_begin] in float64 (default: the whole RIR).
+
+    lut_q > 0: every tap from the table of Eq. (9) at lut_q points per sample
+    with linear interpolation (Sec. 3.5) instead of Eq. (6) itself."""
     room = _room(L, beta, n_img, c, fs, t_max, t_w)
     nS = n_samples(t_max, fs)
     if k_end is None:
@@ -124,10 +132,20 @@ def rir(L, beta, n_img, c, fs, t_max, t_w, src, rcv, k_begin: int = 0, k_end: in
     r = _pos(rcv)
     out = np.zeros((s.shape[0], r.shape[0], k_end - k_begin))
     nt = n_threads or max(1, min(os.cpu_count() or 1, s.shape[0] * r.shape[0]))
-    st = lib().oracle_rir_batch(ctypes.byref(room), _dptr(s), s.shape[0], _dptr(r), r.shape[0],
-                                int(k_begin), int(k_end), int(nt), _dptr(out))
+    st = lib().oracle_rir_batch_lut(ctypes.byref(room), _dptr(s), s.shape[0], _dptr(r), r.shape[0],
+                                    int(k_begin), int(k_end), int(lut_q), int(nt), _dptr(out))
     if st != 0:
         raise ValueError(f"oracle_rir_batch failed with status {st}")
+    return out
+
+
+def lut_taps(v, W: float, q: int = 16) -> np.ndarray:
+    """Table taps of Sec. 3.5 (Eq. (9) table, q points per sample, linear
+    interpolation) at offsets v = k - x in samples; 0 where |v| >= W/2."""
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).ravel())
+    out = np.zeros_like(v)
+    if lib().oracle_lut_taps(_dptr(v), v.size, float(W), int(q), _dptr(out)) != 0:
+        raise ValueError("q W / 2 must be an integer")
     return out
 
 

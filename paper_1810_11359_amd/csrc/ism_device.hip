@@ -174,6 +174,48 @@ constexpr SincPoly<WT> make_sinc_poly() {
   return P;
 }
 
+// Lookup-table taps (Eq. (9)): the windowed sinc of Eq. (6) tabulated at Q
+// points per sample, L[n] = (1 + cos(2 pi n / (Q W))) / 2 sinc(n / Q) for
+// n = -QW/2 .. QW/2, and each tap interpolated linearly between the two
+// entries around its delay. For tap j of an image with fraction f = (fl + fr)/Q
+// (fl an integer in [0, Q), fr in [0, 1)), v = j - f lies between entries
+// n0 = Q j - fl - 1 and n0 + 1, with weight 1 - fr on the upper one. All taps
+// of one image share fl, so the table is stored phase-major: entry
+// (ph, m) = (L[i], L[i + 1] - L[i]) with i = n0 + QW/2 = Q m + ph,
+// ph = Q - 1 - fl and m = j + W/2 - 1; the lanes of an image read consecutive
+// entries of one row.
+constexpr int kLutQ = 16;
+template <int WT>
+struct alignas(16) LutPairs {
+  float p[kLutQ][WT][2];
+};
+constexpr double lut_entry(int i, int wt) {  // L[i - QW/2]
+  const int n = i - kLutQ * wt / 2;
+  const double hann = 0.5 * (1.0 + cx_cos(2.0 * kPi * n / (kLutQ * wt)));  // angle in [-pi, pi]
+  if (n == 0) return hann;
+  // sin(pi n / Q) with n = Q m + r, 0 <= r < Q: (-1)^m sin(pi r / Q), keeping
+  // the series argument in [0, pi)
+  const int r = ((n % kLutQ) + kLutQ) % kLutQ;
+  const int m = (n - r) / kLutQ;
+  const double s = ((m & 1) ? -1.0 : 1.0) * cx_sin(kPi * r / kLutQ);
+  const double v = (double)n / kLutQ;
+  return hann * s / (kPi * v);
+}
+template <int WT>
+constexpr LutPairs<WT> make_lut_pairs() {
+  LutPairs<WT> t{};
+  double L[kLutQ * WT + 1] = {};
+  for (int i = 0; i <= kLutQ * WT; ++i) L[i] = lut_entry(i, WT);
+  L[kLutQ * WT] = 0.0;  // the window's end (1 + cos(pi) = 0)
+  for (int ph = 0; ph < kLutQ; ++ph)
+    for (int m = 0; m < WT; ++m) {
+      const int i = kLutQ * m + ph;
+      t.p[ph][m][0] = (float)L[i];
+      t.p[ph][m][1] = (float)(L[i + 1] - L[i]);
+    }
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 1: per-RIR axis tables.
 // ---------------------------------------------------------------------------
@@ -502,9 +544,10 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 //         C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W), CQ = C/2 sin(2 pi f/W)
 //         follow from that same f;
 //   FP16: (t, A') with t = f - 1/2 in FP32 and A' the amplitude with the
-//         base in its 8 low mantissa bits (relative change < 2^-15).
+//         base in its 8 low mantissa bits (relative change < 2^-15);
+//   LUT:  (F, A) with F = fq 2^8 + base as for FP32 and A in FP32.
 // The column gain cgain carries the constant factor of A: fs / (4 pi c)
-// for FP16, and fs / (4 pi c) / (2 pi) for FP32, whose record holds C/2.
+// for FP16 and LUT, and fs / (4 pi c) / (2 pi) for FP32, whose record holds C/2.
 template <bool HALF> struct StageRec { typedef f4v type; };
 template <> struct StageRec<true> { typedef float2v type; };
 template <bool HALF>
@@ -517,10 +560,11 @@ template <bool HALF>
 __device__ __forceinline__ float column_gain_scale(const RoomArgs &ra) {
   return HALF ? ra.kappa : ra.kappa * (float)(0.5 / kPi);
 }
-template <int WT, bool HALF>
-__device__ __forceinline__ ImageParams<HALF> image_params(const RoomArgs &ra, const ItemGeom &g, const float2v cs,
-                                                          const float cgain, const AxisEntry ez) {
-  ImageParams<HALF> p;
+template <int WT, bool HALF, bool LUT>
+__device__ __forceinline__ ImageParams<HALF || LUT> image_params(const RoomArgs &ra, const ItemGeom &g,
+                                                                 const float2v cs, const float cgain,
+                                                                 const AxisEntry ez) {
+  ImageParams<HALF || LUT> p;
   // S = column part + z part in float-float (Sh + Sl, not renormalised)
   float Sh, Sl;
   two_sum(cs.x, ez.sq_hi, Sh, Sl);
@@ -546,6 +590,11 @@ __device__ __forceinline__ ImageParams<HALF> image_params(const RoomArgs &ra, co
     const float t = fr - 0.5f;
     const uint32_t Ab = (__float_as_uint(A) & ~0xffu) | ((uint32_t)p.base & 0xffu);
     p.rec = float2v{t, __uint_as_float(Ab)};
+  } else if constexpr (LUT) {
+    // 24-bit fraction (as in the FP32 record) with the base in the low byte;
+    // its top 4 bits are the table phase, the next 20 the interpolation weight
+    const uint32_t fq = min((uint32_t)__builtin_rintf(fr * 0x1p24f), (1u << 24) - 1u);
+    p.rec = float2v{__uint_as_float((fq << 8) | ((uint32_t)p.base & 0xffu)), A};
   } else {
     // 24-bit fraction fq in [1, 2^24 - 2] (rounding moves the delay by at
     // most 3e-8 samples) and the base in the low byte; float(F) rounds F to
@@ -582,6 +631,31 @@ template <> __device__ __forceinline__ const SincPoly<32> &poly_table<32>() { re
 template <> __device__ __forceinline__ const SincPoly<64> &poly_table<64>() { return kPoly64; }
 template <> __device__ __forceinline__ const SincPoly<96> &poly_table<96>() { return kPoly96; }
 template <> __device__ __forceinline__ const SincPoly<128> &poly_table<128>() { return kPoly128; }
+// Compile-time checks of the tables: entries within [-0.25, 1], 1 at v = 0,
+// and 0 (to FP32 rounding) at the other integers, where the sinc vanishes.
+template <int WT>
+constexpr bool lut_sane(const LutPairs<WT> &t) {
+  for (int ph = 0; ph < kLutQ; ++ph)
+    for (int m = 0; m < WT; ++m) {
+      const double e = t.p[ph][m][0];
+      if (!(e >= -0.25 && e <= 1.0)) return false;
+      const int n = kLutQ * m + ph - kLutQ * WT / 2;
+      if (n == 0 && e != 1.0) return false;
+      if (n != 0 && n % kLutQ == 0 && (e > 1e-7 || e < -1e-7)) return false;
+    }
+  return true;
+}
+static_assert(lut_sane(make_lut_pairs<32>()) && lut_sane(make_lut_pairs<64>()), "table of Eq. (9)");
+static_assert(lut_sane(make_lut_pairs<96>()) && lut_sane(make_lut_pairs<128>()), "table of Eq. (9)");
+__constant__ LutPairs<32> kLut32 = make_lut_pairs<32>();
+__constant__ LutPairs<64> kLut64 = make_lut_pairs<64>();
+__constant__ LutPairs<96> kLut96 = make_lut_pairs<96>();
+__constant__ LutPairs<128> kLut128 = make_lut_pairs<128>();
+template <int WT> __device__ __forceinline__ const LutPairs<WT> &lut_table();
+template <> __device__ __forceinline__ const LutPairs<32> &lut_table<32>() { return kLut32; }
+template <> __device__ __forceinline__ const LutPairs<64> &lut_table<64>() { return kLut64; }
+template <> __device__ __forceinline__ const LutPairs<96> &lut_table<96>() { return kLut96; }
+template <> __device__ __forceinline__ const LutPairs<128> &lut_table<128>() { return kLut128; }
 
 
 // Output of a work item whose taps are in LDS tiles t0 (+ t1): the tile's own
@@ -616,9 +690,9 @@ __device__ __forceinline__ void write_invalid(int n_own, float *__restrict__ dst
 // one per group of LPG = 64 / NQ lanes; lane l of group g adds the taps
 // j = 1 - W/2 + l + LPG m (m < TPL = W / LPG) of its image into the group's
 // own LDS tile. dst receives the own samples of the tile (or a partial tile
-// when C > 1), marg the margins. HALF selects the FP16 tap arithmetic;
-// accumulation is FP32 in both.
-template <int WT, bool HALF, int NQ>
+// when C > 1), marg the margins. HALF selects the FP16 tap arithmetic, LUT
+// the table taps; accumulation is FP32 in all modes.
+template <int WT, bool HALF, int NQ, bool LUT = false>
 __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                 const AxisEntry *__restrict__ tab, const AxisOrigin &org,
                                                 const bool valid, float *__restrict__ dst, float *__restrict__ marg) {
@@ -631,7 +705,9 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   static_assert(WT % LPG == 0, "window must be a multiple of the lanes per image");
 
   __shared__ float tile[NQ][LSPAN];
-  typedef typename StageRec<HALF>::type Rec;
+  static_assert(!(HALF && LUT), "one tap mode");
+  constexpr bool NARROW = HALF || LUT;  // 8-byte stage record
+  typedef typename StageRec<NARROW>::type Rec;
   __shared__ Rec stp[SCAP];  // staged records (ImageParams::rec)
   __shared__ EnumLds es;
 
@@ -667,7 +743,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         const float b = m1 < TPL ? P.c[k + 1][l + LPG * m1] : 0.0f;
         pq[pr][k] = half2_t{(_Float16)a, (_Float16)b};
       }
-  } else {
+  } else if constexpr (!LUT) {
     const TapConsts<WT> &K = tap_table<WT>();
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
@@ -679,6 +755,8 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   }
   for (int i = lane; i < NQ * LSPAN; i += 64) (&tile[0][0])[i] = 0.0f;
   float *const th = &tile[h][l];
+  // LUT taps: this lane's first entry of row 0 (rows are WT pairs apart)
+  const float *const lrow = &lut_table<WT>().p[0][l][0];
 
   // One step: staged image (record P) on this lane group, taps l + LPG m.
   // The empty asm consumes the record as one value where the step starts,
@@ -701,6 +779,18 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         const int m0 = 2 * pr, m1 = 2 * pr + 1;
         t[LPG * m0] = __builtin_fmaf(A, __builtin_fmaf(tf, (float)q.x, pc0[m0]), t[LPG * m0]);
         if (m1 < TPL) t[LPG * m1] = __builtin_fmaf(A, __builtin_fmaf(tf, (float)q.y, pc0[m1]), t[LPG * m1]);
+      }
+    } else if constexpr (LUT) {
+      // tap = A (L[i] + (1 - fr) (L[i + 1] - L[i])) from row ph of the table
+      const uint32_t F = __float_as_uint(P.x);
+      const float A = P.y;
+      const int ph = (kLutQ - 1) - (int)(F >> 28);
+      const float al = 1.0f - (float)((F >> 8) & 0xfffffu) * 0x1p-20f;
+      const float *const row = lrow + 2 * WT * ph;
+#pragma unroll
+      for (int m = 0; m < TPL; ++m) {
+        const float2v e = *reinterpret_cast<const float2v *>(row + 2 * LPG * m);
+        t[LPG * m] = __builtin_fmaf(A, __builtin_fmaf(al, e.y, e.x), t[LPG * m]);
       }
     } else {
       // When TPL is even, tap m + TPL/2 sits half a window period after tap
@@ -728,7 +818,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   auto rec = [&](int k) { return stp[k]; };
 
   int ns = 0;  // staged images (wave-uniform)
-  enumerate_shell(g, tx, ty, ay, az, column_gain_scale<HALF>(ra), es, [&](int total, int excl, int cnt) {
+  enumerate_shell(g, tx, ty, ay, az, column_gain_scale<NARROW>(ra), es, [&](int total, int excl, int cnt) {
     // Chunks of 64 candidate positions; lane i takes position q0 + i. Its
     // column is the last one starting at or before it: each column marks its
     // first position in the chunk, a running maximum over the lanes carries
@@ -764,9 +854,9 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         if (q + 64 + lane < total) ez = tz[nz];
       }
       // lanes = candidates: parameters, then compaction into the stage
-      ImageParams<HALF> p;
+      ImageParams<NARROW> p;
       p.ok = false;
-      if (q + lane < total) p = image_params<WT, HALF>(ra, g, es.col_s[cl_c], cg_c, ez_c);
+      if (q + lane < total) p = image_params<WT, HALF, LUT>(ra, g, es.col_s[cl_c], cg_c, ez_c);
       const uint64_t okm = __ballot(p.ok);
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
       if (p.ok) stp[ns + rank] = p.rec;
@@ -814,7 +904,7 @@ __device__ __forceinline__ uint32_t plan_first_item(const PlanArgs &pa, int pos)
 }
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
-template <int WT, bool HALF, int NQ>
+template <int WT, bool HALF, int NQ, bool LUT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
@@ -847,8 +937,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
   // (for a tile past nS, dst is never written: the tile has no own samples)
   float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
   const AxisOrigin org = origin[rir];
-  accumulate_item<WT, HALF, NQ>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0, dst,
-                                marg + (size_t)item * WT);
+  accumulate_item<WT, HALF, NQ, LUT>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0,
+                                     dst, marg + (size_t)item * WT);
 }
 
 // Batch launch: every item names its job; the job table carries the room.
@@ -975,24 +1065,25 @@ int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEn
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int WT, bool HALF>
+template <int WT, bool HALF, bool LUT>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                         const AxisOrigin *origin, const int *valid, float *out, float *part, float *marg,
                         hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF)>), dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin,
-                     valid, out, part, marg);
+  hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF), LUT>), dim3(n_items), dim3(64), 0, st,
+                     ra, pa, tab, origin, valid, out, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt == 128; }
 
-int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
+int launch_accumulate(int wt, bool half, bool lut, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
                       const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
                       float *marg, hipStream_t st) {
-#define ISM_ACC(W)                                                                                 \
-  case W:                                                                                          \
-    return half ? launch_acc_w<W, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)  \
-                : launch_acc_w<W, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st);
+#define ISM_ACC(W)                                                                                        \
+  case W:                                                                                                 \
+    return half  ? launch_acc_w<W, true, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st) \
+           : lut ? launch_acc_w<W, false, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st) \
+                 : launch_acc_w<W, false, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st);
   switch (wt) {
     ISM_ACC(32)
     ISM_ACC(64)

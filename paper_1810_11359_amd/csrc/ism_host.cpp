@@ -18,7 +18,7 @@
 namespace ism {
 int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
                   int *valid, int n_rir, hipStream_t st);
-int launch_accumulate(int wt, bool half, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
+int launch_accumulate(int wt, bool half, bool lut, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
                       const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
                       float *marg, hipStream_t st);
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, const float *marg,
@@ -70,6 +70,7 @@ struct Plan {
   double total_taps;            // over all RIRs
   int wt;
   bool half;
+  bool lut;  // table taps (Eq. (9)); FP32 arithmetic otherwise
   int n_rir;
   uint32_t n_items;
   bool any_split;
@@ -117,9 +118,10 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, d
   if (st != ISM_OK) return st;
   if (n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
   if ((int64_t)n_src * n_rcv > ISM_MAX_PAIRS) return ISM_E_TOO_LARGE;
-  if (precision != ISM_FP32 && precision != ISM_FP16)
+  if (precision != ISM_FP32 && precision != ISM_FP16 && precision != ISM_FP32_LUT)
     return precision == ISM_BF16 ? ISM_E_UNSUPPORTED : ISM_E_INVALID_ARG;
   p.half = precision == ISM_FP16;
+  p.lut = precision == ISM_FP32_LUT;
   p.wt = even_window(*r);
   if (p.wt == 0 || !supported_window(p.wt)) return ISM_E_UNSUPPORTED;
   const int64_t nS = ism_n_samples(r->t_max, r->fs);
@@ -384,7 +386,7 @@ static int run_plan(const Plan &p, const float *src, const float *rcv, float *ou
   float *marg = (float *)(w + p.off_marg);
   if (launch_tables(p.ra, src, rcv, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, s) != hipSuccess) return ISM_E_DEVICE;
-  if (launch_accumulate(p.wt, p.half, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, marg, s) != 0)
+  if (launch_accumulate(p.wt, p.half, p.lut, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, marg, s) != 0)
     return ISM_E_DEVICE;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
   // split tiles and the margins between neighbouring tiles
@@ -502,6 +504,7 @@ int cost_bucket(double cost) {
 // item and reduce tables are built as well (ism_batch_prepare).
 int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bool fill) {
   if (!jobs || n_jobs < 1) return ISM_E_INVALID_ARG;
+  if (precision == ISM_FP32_LUT) return ISM_E_UNSUPPORTED;  // table taps: single-room calls only
   std::memset(&bp.st, 0, sizeof(bp.st));
   // Each job is planned as a single call would plan it without the tail
   // taper (items sized from the job's own work), so a job's result does not

@@ -26,7 +26,7 @@ ISM_E_DEVICE = -5
 ISM_E_TOO_LARGE = -6
 ISM_E_UNSUPPORTED = -7
 
-PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2}
+PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "lut": 3}
 
 # Every symbol include/ism.h declares.
 EXPORTS = (

@@ -111,6 +111,8 @@ def test_unsupported_requests():
         ism.workspace_size(_room(), 1, 1, precision="bf16")
     assert e.value.status == ism.ISM_E_UNSUPPORTED
     assert ism.workspace_size(_room(), 1, 1, precision="fp16") > 0
+    # table taps (Eq. (9)): single-room calls plan like FP32
+    assert ism.workspace_size(_room(), 1, 1, precision="lut") == ism.workspace_size(_room(), 1, 1)
 
 
 def test_position_checks():
@@ -157,6 +159,7 @@ def test_batch_checks_before_any_launch():
     jobs[1].out = None
     assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_E_INVALID_ARG
     jobs[1].out = fake
+    assert L.ism_batch_workspace_size(jobs, 2, ism.PRECISIONS["lut"], ctypes.byref(n)) == ism.ISM_E_UNSUPPORTED
     b = ism._Batch()
     assert L.ism_batch_prepare(jobs, 2, 0, None, 0, None, ctypes.byref(b)) == ism.ISM_E_WORKSPACE
     assert L.ism_batch_run(ctypes.byref(ism._Batch()), None) == ism.ISM_E_INVALID_ARG

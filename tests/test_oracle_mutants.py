@@ -1,8 +1,8 @@
 """Plant plausible mistakes in a copy of the oracle and check that the pins catch them.
 
 Each mutant is a one-expression edit of oracle/ism_oracle.c compiled into a
-temporary library; the pins of test_oracle_pins.py are then run against it and
-at least one must fail. The oracle itself is never modified.
+temporary library; the pins of test_oracle_pins.py and test_oracle_lut.py are
+then run against it and at least one must fail. The oracle itself is never modified.
 """
 import inspect
 import os
@@ -12,6 +12,7 @@ import pytest
 
 from oracle import oracle as oracle_module
 
+import tests.test_oracle_lut as lut_pins
 import tests.test_oracle_pins as pins
 
 MUTANTS = {
@@ -23,7 +24,7 @@ MUTANTS = {
     "sinc_cutoff_fs": ("sin(PI * v) / (PI * v)", "sin(2.0 * PI * v) / (2.0 * PI * v)"),
     "exponent_floor_ceil": ("int e0 = abs((int)floor(n / 2.0));", "int e0 = abs((int)ceil(n / 2.0));"),
     "distance_to_source": ("double diff = rcv[a] - p;", "double diff = rcv[a] - src[a];"),
-    "window_drops_edges": ("if (fabs(v) < W / 2.0) out", "if (fabs(v) < W / 2.0 - 1.0) out"),
+    "window_drops_edges": ("if (fabs(v) < W / 2.0)\n", "if (fabs(v) < W / 2.0 - 1.0)\n"),
     "lattice_upper_floor": ("static int lat_hi(int N) { return (int)ceil(N / 2.0); }",
                             "static int lat_hi(int N) { return (int)floor(N / 2.0); }"),
     "zero_pow_zero": ("for (int i = 0; i < e; ++i) r *= b;", "for (int i = 0; i <= e; ++i) r *= b;"),
@@ -33,12 +34,18 @@ MUTANTS = {
     "n_img_formula": ("n_out[a] = 4 * (int)ceil(c * t / (2.0 * L[a])) + 2;",
                       "n_out[a] = 2 * (int)ceil(c * t / (2.0 * L[a])) + 2;"),
     "sign_of_odd_image": ("return (n + 1) * L - s;", "return (n + 1) * L + s;"),
+    # table taps (Sec. 3.5, Eq. (9))
+    "lut_nearest_entry": ("int64_t n0 = (int64_t)floor(p);", "int64_t n0 = (int64_t)floor(p + 0.5);"),
+    "lut_weight_flipped": ("const double a = p - (double)n0;", "const double a = 1.0 - (p - (double)n0);"),
+    "lut_window_width": ("cos(2.0 * PI * (double)n / (q * W))", "cos(2.0 * PI * (double)n / W)"),
+    "lut_sinc_scale": ("double u = (double)n / q;", "double u = (double)n / (q - 1);"),
 }
 
 
 def _pin_functions():
     out = []
-    for name, fn in inspect.getmembers(pins, inspect.isfunction):
+    members = inspect.getmembers(pins, inspect.isfunction) + inspect.getmembers(lut_pins, inspect.isfunction)
+    for name, fn in members:
         if not name.startswith("test_"):
             continue
         params = getattr(fn, "pytestmark", [])
