@@ -144,6 +144,26 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
                        int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
                        void *ev_stop);
 
+/* ism_simulate with directional receivers (the paper's library takes each
+ * receiver's polar pattern and orientation, Sec. 4; it gives no formula).
+ * Reading: the first-order pattern family, each image's amplitude (Eq. (4))
+ * times a + (1 - a) cos(theta), theta the angle between the receiver's
+ * orientation and the direction from the receiver to the image. a = 1 is
+ * omnidirectional (same result as ism_simulate), 0.75 subcardioid, 0.5
+ * cardioid, 0.25 hypercardioid, 0 bidirectional (figure of eight).
+ *   orient: device float32 [n_rcv][3], one orientation per receiver in room
+ *           axes; need not be unit length (normalised here); a zero vector
+ *           gives NaN RIRs for that receiver;
+ *   pattern: a in [0, 1], the same for every receiver;
+ *   precision: ISM_FP32 only (others: ISM_E_UNSUPPORTED);
+ *   the other arguments, the workspace (ism_workspace_size with the same
+ *   room, counts and precision) and the errors as for ism_simulate, all
+ *   checked before any launch; ISM_E_INVALID_ARG for a null orient or a
+ *   pattern outside [0, 1]. Asynchronous. */
+int ism_simulate_polar(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                       const float *orient, double pattern, int precision, float *out, void *ws, size_t ws_bytes,
+                       void *stream);
+
 /* ---- Diffuse reverberation tail (Sec. 2.2, Eq. (8); Sec. 3.3) --------------- */
 
 /* Device workspace (bytes) that ism_simulate_diffuse needs; depends only on

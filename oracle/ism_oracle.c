@@ -10,7 +10,9 @@
  *   Sec. 2.2  Eq. (6) Hann-windowed sinc replacing the impulse (cut-off fs/2),
  *             signed reflection coefficients, Eq. (7) Sabine's formula;
  *   Sec. 3.5  Eq. (9) the windowed sinc tabulated at Q points per sample and
- *             read by linear interpolation (the lookup-table variant).
+ *             read by linear interpolation (the lookup-table variant);
+ *   Sec. 4    directional receivers (pattern and orientation; no formula in
+ *             the paper: the first-order family a + (1 - a) cos(theta)).
  * Readings where the paper is silent (wall exponents, grid size, taps before
  * t = 0) are stated at the function that takes them.
  *
@@ -85,6 +87,7 @@ static double axis_gain(int n, double b0, double b1) {
 
 typedef struct {
   double gain, d, x, A;
+  double to_image[3]; /* p_n - p_r: from the receiver to the image */
 } image_t;
 
 /* One image: Eq. (1) position, Eq. (2) distance (reading: the norm is taken to
@@ -98,6 +101,7 @@ static image_t make_image(const oracle_room *room, const double src[3], const do
     double p = image_coord(n[a], room->L[a], src[a]);
     double diff = rcv[a] - p;
     d2 += diff * diff;
+    im.to_image[a] = -diff;
     g *= axis_gain(n[a], room->beta[2 * a], room->beta[2 * a + 1]);
   }
   im.gain = g;
@@ -158,16 +162,32 @@ int oracle_lut_taps(const double *v, int64_t n, double W, int q, double *out) {
 /* Eq. (5) with Eq. (6) in place of the impulse, restricted to k in
  * [k_begin, k_end). Taps that would fall before k = 0 or after the last sample
  * are dropped (reading: no wrap-around, no shift). With lut != NULL each tap
- * is read from the table of Eq. (9) (q points per sample) instead. */
+ * is read from the table of Eq. (9) (q points per sample) instead. With
+ * orient != NULL the receiver is directional (the library of Sec. 4 takes a
+ * polar pattern and an orientation; the paper gives no formula). Reading: the
+ * first-order family, each image's amplitude times a + (1 - a) cos(theta),
+ * theta the angle between orient and the direction from the receiver to the
+ * image. */
 static int rir_window(const oracle_room *room, const double src[3], const double rcv[3], int64_t k_begin,
-                      int64_t k_end, const double *lut, int q, double *out) {
+                      int64_t k_end, const double *lut, int q, const double *orient, double pattern_a,
+                      double *out) {
   const double W = room->t_w * room->fs;
+  double onorm = 0.0;
+  if (orient) {
+    onorm = sqrt(orient[0] * orient[0] + orient[1] * orient[1] + orient[2] * orient[2]);
+    if (!(onorm > 0.0)) return -1;
+  }
   for (int64_t k = k_begin; k < k_end; ++k) out[k - k_begin] = 0.0;
   for (int nx = lat_lo(room->n[0]); nx < lat_hi(room->n[0]); ++nx)
     for (int ny = lat_lo(room->n[1]); ny < lat_hi(room->n[1]); ++ny)
       for (int nz = lat_lo(room->n[2]); nz < lat_hi(room->n[2]); ++nz) {
         image_t im = make_image(room, src, rcv, nx, ny, nz);
         if (!(im.d > 0.0)) return -1;
+        if (orient) {
+          double cos_theta = (im.to_image[0] * orient[0] + im.to_image[1] * orient[1] +
+                              im.to_image[2] * orient[2]) / (im.d * onorm);
+          im.A *= pattern_a + (1.0 - pattern_a) * cos_theta;
+        }
         int64_t first = (int64_t)floor(im.x - W / 2.0) + 1; /* smallest k > x - W/2 */
         int64_t last = (int64_t)ceil(im.x + W / 2.0) - 1;   /* largest k < x + W/2  */
         if (first < k_begin) first = k_begin;
@@ -183,7 +203,7 @@ static int rir_window(const oracle_room *room, const double src[3], const double
 
 int oracle_rir_window(const oracle_room *room, const double src[3], const double rcv[3],
                       int64_t k_begin, int64_t k_end, double *out) {
-  return rir_window(room, src, rcv, k_begin, k_end, NULL, 0, out);
+  return rir_window(room, src, rcv, k_begin, k_end, NULL, 0, NULL, 1.0, out);
 }
 
 typedef struct {
@@ -193,6 +213,8 @@ typedef struct {
   int64_t k_begin, k_end;
   const double *lut;
   int q;
+  const double *orient; /* [n_rcv][3] or NULL */
+  double pattern_a;
   double *out;
   int next, status;
   pthread_mutex_t lock;
@@ -208,7 +230,7 @@ static void *batch_worker(void *arg) {
     if (p >= b->n_src * b->n_rcv) break;
     int s = p / b->n_rcv, r = p % b->n_rcv;
     int st = rir_window(b->room, b->src + 3 * s, b->rcv + 3 * r, b->k_begin, b->k_end, b->lut, b->q,
-                        b->out + (int64_t)p * len);
+                        b->orient ? b->orient + 3 * r : NULL, b->pattern_a, b->out + (int64_t)p * len);
     if (st != 0) {
       pthread_mutex_lock(&b->lock);
       if (b->status == 0) b->status = st;
@@ -218,8 +240,9 @@ static void *batch_worker(void *arg) {
   return NULL;
 }
 
-int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, const double *rcv,
-                         int n_rcv, int64_t k_begin, int64_t k_end, int q, int n_threads, double *out) {
+static int rir_batch(const oracle_room *room, const double *src, int n_src, const double *rcv, int n_rcv,
+                     int64_t k_begin, int64_t k_end, int q, const double *orient, double pattern_a,
+                     int n_threads, double *out) {
   if (n_src < 0 || n_rcv < 0 || k_begin < 0 || k_end < k_begin || q < 0) return -1;
   if (n_threads < 1) n_threads = 1;
   double *lut = NULL;
@@ -230,6 +253,8 @@ int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, 
   batch_t b;
   b.lut = lut;
   b.q = q;
+  b.orient = orient;
+  b.pattern_a = pattern_a;
   b.room = room;
   b.src = src;
   b.rcv = rcv;
@@ -253,9 +278,21 @@ int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, 
   return b.status;
 }
 
+int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, const double *rcv,
+                         int n_rcv, int64_t k_begin, int64_t k_end, int q, int n_threads, double *out) {
+  return rir_batch(room, src, n_src, rcv, n_rcv, k_begin, k_end, q, NULL, 1.0, n_threads, out);
+}
+
 int oracle_rir_batch(const oracle_room *room, const double *src, int n_src, const double *rcv,
                      int n_rcv, int64_t k_begin, int64_t k_end, int n_threads, double *out) {
-  return oracle_rir_batch_lut(room, src, n_src, rcv, n_rcv, k_begin, k_end, 0, n_threads, out);
+  return rir_batch(room, src, n_src, rcv, n_rcv, k_begin, k_end, 0, NULL, 1.0, n_threads, out);
+}
+
+int oracle_rir_batch_polar(const oracle_room *room, const double *src, int n_src, const double *rcv,
+                           int n_rcv, const double *orient, double pattern_a, int64_t k_begin, int64_t k_end,
+                           int n_threads, double *out) {
+  if (!orient || !(pattern_a >= 0.0 && pattern_a <= 1.0)) return -1;
+  return rir_batch(room, src, n_src, rcv, n_rcv, k_begin, k_end, 0, orient, pattern_a, n_threads, out);
 }
 
 int64_t oracle_image_list(const oracle_room *room, const double src[3], const double rcv[3],

@@ -67,6 +67,15 @@ int oracle_rir_batch(const oracle_room *room, const double *src, int n_src,
 int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, const double *rcv,
                          int n_rcv, int64_t k_begin, int64_t k_end, int q, int n_threads, double *out);
 
+/* As oracle_rir_batch with directional receivers: every image's amplitude
+ * times a + (1 - a) cos(theta), theta the angle between orient[r] (the
+ * receiver's orientation, [n_rcv][3], any nonzero length) and the direction
+ * from the receiver to the image; a = pattern_a in [0, 1]. Returns -1 for a
+ * null orient, a pattern outside [0, 1] or a zero orientation. */
+int oracle_rir_batch_polar(const oracle_room *room, const double *src, int n_src, const double *rcv,
+                           int n_rcv, const double *orient, double pattern_a, int64_t k_begin, int64_t k_end,
+                           int n_threads, double *out);
+
 /* Table taps of Sec. 3.5 at the offsets v[0..n) (v = k - x in samples, 0 for
  * |v| >= W/2), table of Eq. (9) at q points per sample. Returns -1 when
  * q W / 2 is not an integer. */

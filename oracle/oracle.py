@@ -63,6 +63,9 @@ def lib():
         L.oracle_rir_batch_lut.restype = ctypes.c_int
         L.oracle_rir_batch_lut.argtypes = [ctypes.POINTER(_Room), dp, ctypes.c_int, dp, ctypes.c_int,
                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, dp]
+        L.oracle_rir_batch_polar.restype = ctypes.c_int
+        L.oracle_rir_batch_polar.argtypes = [ctypes.POINTER(_Room), dp, ctypes.c_int, dp, ctypes.c_int, dp,
+                                             ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp]
         L.oracle_lut_taps.restype = ctypes.c_int
         L.oracle_lut_taps.argtypes = [dp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_image_list.restype = ctypes.c_int64
@@ -136,6 +139,26 @@ def rir(L, beta, n_img, c, fs, t_max, t_w, src, rcv, k_begin: int = 0, k_end: in
                                     int(k_begin), int(k_end), int(lut_q), int(nt), _dptr(out))
     if st != 0:
         raise ValueError(f"oracle_rir_batch failed with status {st}")
+    return out
+
+
+def rir_polar(L, beta, n_img, c, fs, t_max, t_w, src, rcv, orient, pattern_a: float, k_begin: int = 0,
+              k_end: int | None = None, n_threads: int | None = None) -> np.ndarray:
+    """RIRs [n_src, n_rcv, k_end - k_begin] with directional receivers: each image's
+    amplitude times a + (1 - a) cos(theta), theta between orient[r] and the
+    direction from the receiver to the image (first-order pattern family)."""
+    room = _room(L, beta, n_img, c, fs, t_max, t_w)
+    if k_end is None:
+        k_end = n_samples(t_max, fs)
+    s, r, o = _pos(src), _pos(rcv), _pos(orient)
+    if o.shape != r.shape:
+        raise ValueError("orient must be [n_rcv, 3]")
+    out = np.zeros((s.shape[0], r.shape[0], k_end - k_begin))
+    nt = n_threads or max(1, min(os.cpu_count() or 1, s.shape[0] * r.shape[0]))
+    st = lib().oracle_rir_batch_polar(ctypes.byref(room), _dptr(s), s.shape[0], _dptr(r), r.shape[0], _dptr(o),
+                                      float(pattern_a), int(k_begin), int(k_end), int(nt), _dptr(out))
+    if st != 0:
+        raise ValueError(f"oracle_rir_batch_polar failed with status {st}")
     return out
 
 

@@ -221,7 +221,8 @@ constexpr LutPairs<WT> make_lut_pairs() {
 // ---------------------------------------------------------------------------
 // Table entry e (axis a, lattice index n) of the RIR with source s, receiver r.
 __device__ __forceinline__ AxisEntry table_entry(const RoomArgs &ra, const float *__restrict__ s3,
-                                                 const float *__restrict__ r3, int e) {
+                                                 const float *__restrict__ r3, int e,
+                                                 const float *__restrict__ o3 = nullptr) {
   const int a = e < ra.off[1] ? 0 : (e < ra.off[2] ? 1 : 2);
   const int n = ra.lo[a] + (e - ra.off[a]);
   const float s = s3[ra.perm[a]], r = r3[ra.perm[a]];
@@ -250,7 +251,15 @@ __device__ __forceinline__ AxisEntry table_entry(const RoomArgs &ra, const float
   // the enumeration only needs the square of the displacement
   float sq, sqe;
   ff_sq(v, ve, sq, sqe);
-  return AxisEntry{sq, sqe, g, 0.0f};
+  // receiver orientation (polar calls): the displacement's share of the
+  // projection onto the unit orientation, whose three shares add up to
+  // |d| cos(theta) in samples
+  float proj = 0.0f;
+  if (o3) {
+    const float inv = __builtin_amdgcn_rsqf(o3[0] * o3[0] + o3[1] * o3[1] + o3[2] * o3[2]);
+    proj = v * (o3[ra.perm[a]] * inv);
+  }
+  return AxisEntry{sq, sqe, g, proj};
 }
 
 // Validity of a pair (both points strictly inside, distinct) and the family
@@ -269,7 +278,8 @@ __device__ __forceinline__ int rir_header(const RoomArgs &ra, const float *__res
 }
 
 __global__ __launch_bounds__(256) void tables_kernel(RoomArgs ra, const float *__restrict__ src,
-                                                     const float *__restrict__ rcv, AxisEntry *__restrict__ tab,
+                                                     const float *__restrict__ rcv,
+                                                     const float *__restrict__ orient, AxisEntry *__restrict__ tab,
                                                      AxisOrigin *__restrict__ origin, int *__restrict__ valid,
                                                      int n_rir) {
   const int64_t total = (int64_t)n_rir * ra.n_tab;
@@ -279,7 +289,7 @@ __global__ __launch_bounds__(256) void tables_kernel(RoomArgs ra, const float *_
     const int e = (int)(gid % ra.n_tab);
     const float *s3 = src + 3 * (rir / ra.n_rcv);
     const float *r3 = rcv + 3 * (rir % ra.n_rcv);
-    tab[gid] = table_entry(ra, s3, r3, e);
+    tab[gid] = table_entry(ra, s3, r3, e, orient ? orient + 3 * (rir % ra.n_rcv) : nullptr);
     if (e == 0) {
       AxisOrigin o;
       valid[rir] = rir_header(ra, s3, r3, o);
@@ -447,11 +457,11 @@ __device__ __forceinline__ ItemGeom item_geom(const RoomArgs &ra, const AxisRang
 // candidates in the batch, and on column lane c its first position excl and
 // its count cnt. The column gain in col_run is the product of the x and y
 // gain factors times gscale.
-template <class Consume>
+template <bool POLAR, class Consume>
 __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEntry *__restrict__ tx,
                                                 const AxisEntry *__restrict__ ty, const AxisRange &ay,
                                                 const AxisRange &az, const float gscale, EnumLds &es,
-                                                Consume &&consume) {
+                                                float *__restrict__ col_p, Consume &&consume) {
   const int lane = threadIdx.x & 63;
   for (int nx0 = g.nx_a; nx0 < g.nx_b; nx0 += 64) {
     // lanes = x indices: y range of the columns that reach the outer sphere
@@ -497,6 +507,7 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
         sl += ex.sq_lo + ey.sq_lo;
         fast_two_sum(sh, sl, sh, sl);
         es.col_s[lane] = float2v{sh, sl};
+        if constexpr (POLAR) col_p[lane] = ex.proj + ey.proj;  // column part of |d| cos(theta)
         cg = (ex.gain * ey.gain) * gscale;
         float rh, rl;
         ff_sub(g.r1h, g.r1l, sh, sl, rh, rl);
@@ -560,10 +571,10 @@ template <bool HALF>
 __device__ __forceinline__ float column_gain_scale(const RoomArgs &ra) {
   return HALF ? ra.kappa : ra.kappa * (float)(0.5 / kPi);
 }
-template <int WT, bool HALF, bool LUT>
+template <int WT, bool HALF, bool LUT, bool POLAR>
 __device__ __forceinline__ ImageParams<HALF || LUT> image_params(const RoomArgs &ra, const ItemGeom &g,
                                                                  const float2v cs, const float cgain,
-                                                                 const AxisEntry ez) {
+                                                                 const AxisEntry ez, const float cp) {
   ImageParams<HALF || LUT> p;
   // S = column part + z part in float-float (Sh + Sl, not renormalised)
   float Sh, Sl;
@@ -585,7 +596,9 @@ __device__ __forceinline__ ImageParams<HALF || LUT> image_params(const RoomArgs 
   p.base = k0 - g.T0;
   p.ok = (x0 < 1.0e9f) && (uint32_t)p.base < (uint32_t)(g.K1 - g.T0);
   // Eq. (4) amplitude (times the constant factor carried by the column gain)
-  const float A = (cgain * ez.gain) * rx;
+  float A = (cgain * ez.gain) * rx;
+  // receiver polar pattern a + b cos(theta), cos(theta) = (d . o) / |d|
+  if constexpr (POLAR) A *= __builtin_fmaf(ra.dir_b, (cp + ez.proj) * rx, ra.dir_a);
   if constexpr (HALF) {
     const float t = fr - 0.5f;
     const uint32_t Ab = (__float_as_uint(A) & ~0xffu) | ((uint32_t)p.base & 0xffu);
@@ -692,7 +705,7 @@ __device__ __forceinline__ void write_invalid(int n_own, float *__restrict__ dst
 // own LDS tile. dst receives the own samples of the tile (or a partial tile
 // when C > 1), marg the margins. HALF selects the FP16 tap arithmetic, LUT
 // the table taps; accumulation is FP32 in all modes.
-template <int WT, bool HALF, int NQ, bool LUT = false>
+template <int WT, bool HALF, int NQ, bool LUT = false, bool POLAR = false>
 __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                 const AxisEntry *__restrict__ tab, const AxisOrigin &org,
                                                 const bool valid, float *__restrict__ dst, float *__restrict__ marg) {
@@ -710,6 +723,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   typedef typename StageRec<NARROW>::type Rec;
   __shared__ Rec stp[SCAP];  // staged records (ImageParams::rec)
   __shared__ EnumLds es;
+  __shared__ float col_p[POLAR ? 64 : 1];  // polar calls: column part of |d| cos(theta)
 
   const int lane = threadIdx.x & 63;
   const int h = lane / LPG, l = lane % LPG;  // image group, lane within it
@@ -818,7 +832,8 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   auto rec = [&](int k) { return stp[k]; };
 
   int ns = 0;  // staged images (wave-uniform)
-  enumerate_shell(g, tx, ty, ay, az, column_gain_scale<NARROW>(ra), es, [&](int total, int excl, int cnt) {
+  enumerate_shell<POLAR>(g, tx, ty, ay, az, column_gain_scale<NARROW>(ra), es, col_p, [&](int total, int excl,
+                                                                                        int cnt) {
     // Chunks of 64 candidate positions; lane i takes position q0 + i. Its
     // column is the last one starting at or before it: each column marks its
     // first position in the chunk, a running maximum over the lanes carries
@@ -856,7 +871,8 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       // lanes = candidates: parameters, then compaction into the stage
       ImageParams<NARROW> p;
       p.ok = false;
-      if (q + lane < total) p = image_params<WT, HALF, LUT>(ra, g, es.col_s[cl_c], cg_c, ez_c);
+      if (q + lane < total)
+        p = image_params<WT, HALF, LUT, POLAR>(ra, g, es.col_s[cl_c], cg_c, ez_c, POLAR ? col_p[cl_c] : 0.0f);
       const uint64_t okm = __ballot(p.ok);
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
       if (p.ok) stp[ns + rank] = p.rec;
@@ -904,7 +920,7 @@ __device__ __forceinline__ uint32_t plan_first_item(const PlanArgs &pa, int pos)
 }
 
 // Single-room launch: the item index decodes through the per-tile chunk counts.
-template <int WT, bool HALF, int NQ, bool LUT>
+template <int WT, bool HALF, int NQ, bool LUT, bool POLAR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
@@ -937,8 +953,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
   // (for a tile past nS, dst is never written: the tile has no own samples)
   float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
   const AxisOrigin org = origin[rir];
-  accumulate_item<WT, HALF, NQ, LUT>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org, valid[rir] != 0,
-                                     dst, marg + (size_t)item * WT);
+  accumulate_item<WT, HALF, NQ, LUT, POLAR>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org,
+                                            valid[rir] != 0, dst, marg + (size_t)item * WT);
 }
 
 // Batch launch: every item names its job; the job table carries the room.
@@ -1055,35 +1071,38 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restr
 // the measured best: four images per step halve the broadcast reads per tap
 // but need four LDS tiles and more registers per wave, and ran 12 % slower.
 constexpr int images_per_step(int wt, bool half) { return (void)wt, (void)half, 2; }
-int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
-                  int *valid, int n_rir, hipStream_t st) {
+int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, const float *orient, AxisEntry *tab,
+                  AxisOrigin *origin, int *valid, int n_rir, hipStream_t st) {
   const int64_t total = (int64_t)n_rir * ra.n_tab;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65535) blocks = 65535;
-  hipLaunchKernelGGL(tables_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ra, src, rcv, tab, origin, valid,
-                     n_rir);
+  hipLaunchKernelGGL(tables_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ra, src, rcv, orient, tab, origin,
+                     valid, n_rir);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int WT, bool HALF, bool LUT>
+template <int WT, bool HALF, bool LUT, bool POLAR = false>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                         const AxisOrigin *origin, const int *valid, float *out, float *part, float *marg,
                         hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF), LUT>), dim3(n_items), dim3(64), 0, st,
-                     ra, pa, tab, origin, valid, out, part, marg);
+  hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR>), dim3(n_items), dim3(64),
+                     0, st, ra, pa, tab, origin, valid, out, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt == 128; }
 
-int launch_accumulate(int wt, bool half, bool lut, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
-                      const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
-                      float *marg, hipStream_t st) {
-#define ISM_ACC(W)                                                                                        \
-  case W:                                                                                                 \
-    return half  ? launch_acc_w<W, true, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st) \
-           : lut ? launch_acc_w<W, false, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st) \
-                 : launch_acc_w<W, false, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st);
+// polar: FP32 taps only (the host rejects other precisions first).
+int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &ra, const PlanArgs &pa,
+                      uint32_t n_items, const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out,
+                      float *part, float *marg, hipStream_t st) {
+  if (polar && (half || lut)) return -2;
+#define ISM_ACC(W)                                                                                              \
+  case W:                                                                                                       \
+    return half    ? launch_acc_w<W, true, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)     \
+           : lut   ? launch_acc_w<W, false, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)     \
+           : polar ? launch_acc_w<W, false, false, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st) \
+                   : launch_acc_w<W, false, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st);
   switch (wt) {
     ISM_ACC(32)
     ISM_ACC(64)

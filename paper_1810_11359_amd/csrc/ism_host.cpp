@@ -16,11 +16,11 @@
 #include "ism_tuning.h"
 
 namespace ism {
-int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, AxisEntry *tab, AxisOrigin *origin,
-                  int *valid, int n_rir, hipStream_t st);
-int launch_accumulate(int wt, bool half, bool lut, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items,
-                      const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out, float *part,
-                      float *marg, hipStream_t st);
+int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, const float *orient, AxisEntry *tab,
+                  AxisOrigin *origin, int *valid, int n_rir, hipStream_t st);
+int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &ra, const PlanArgs &pa,
+                      uint32_t n_items, const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out,
+                      float *part, float *marg, hipStream_t st);
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, const float *marg,
                   float *out, hipStream_t st);
 bool supported_window(int wt);
@@ -375,8 +375,10 @@ int ism_simulate(const ism_room *room, const float *src, int n_src, const float 
 
 // Launches the ISM kernels of a plan: tables, taps, completion of the tiles.
 // ws holds at least p.ws_bytes; out is device [n_rir][nS].
+// orient: device [n_rcv][3] receiver orientations for a polar call (p.ra.dir_a,
+// dir_b set), else null.
 static int run_plan(const Plan &p, const float *src, const float *rcv, float *out, void *ws, void *stream,
-                    void *ev_start, void *ev_stop) {
+                    void *ev_start, void *ev_stop, const float *orient = nullptr) {
   hipStream_t s = (hipStream_t)stream;
   char *w = (char *)ws;
   int *valid = (int *)(w + p.off_valid);
@@ -384,9 +386,10 @@ static int run_plan(const Plan &p, const float *src, const float *rcv, float *ou
   AxisEntry *tab = (AxisEntry *)(w + p.off_tab);
   float *part = p.any_split ? (float *)(w + p.off_part) : nullptr;
   float *marg = (float *)(w + p.off_marg);
-  if (launch_tables(p.ra, src, rcv, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
+  if (launch_tables(p.ra, src, rcv, orient, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, s) != hipSuccess) return ISM_E_DEVICE;
-  if (launch_accumulate(p.wt, p.half, p.lut, p.ra, p.pa, p.n_items, tab, origin, valid, out, part, marg, s) != 0)
+  if (launch_accumulate(p.wt, p.half, p.lut, orient != nullptr, p.ra, p.pa, p.n_items, tab, origin, valid, out, part,
+                        marg, s) != 0)
     return ISM_E_DEVICE;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
   // split tiles and the margins between neighbouring tiles
@@ -404,6 +407,21 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
   if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
   if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
   return run_plan(p, src, rcv, out, ws, stream, ev_start, ev_stop);
+}
+
+int ism_simulate_polar(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                       const float *orient, double pattern, int precision, float *out, void *ws, size_t ws_bytes,
+                       void *stream) {
+  Plan p;
+  const int st = make_plan(room, n_src, n_rcv, precision, p);
+  if (st != ISM_OK) return st;
+  if (precision != ISM_FP32) return ISM_E_UNSUPPORTED;
+  if (!src || !rcv || !out || !orient) return ISM_E_INVALID_ARG;
+  if (!(pattern >= 0.0 && pattern <= 1.0)) return ISM_E_INVALID_ARG;
+  if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
+  p.ra.dir_a = (float)pattern;
+  p.ra.dir_b = (float)(1.0 - pattern);
+  return run_plan(p, src, rcv, out, ws, stream, nullptr, nullptr, orient);
 }
 
 // ---- Diffuse tail (Sec. 2.2, Eq. (8); Sec. 3.3) ------------------------------

@@ -42,6 +42,7 @@ struct RoomArgs {
   int n_src, n_rcv;
   float period[3];         // 2 L q: displacement step between images of one parity [samples]
   float inv_period[3];     // 1 / period
+  float dir_a, dir_b;      // receiver polar pattern a + b cos(theta) (b = 1 - a); polar calls only
 };
 
 // Work decomposition of one call. Items are ordered by tile (last tile first,
@@ -60,10 +61,11 @@ struct PlanArgs {
 
 // Per-RIR table entry for one lattice index of one axis: square of the
 // displacement from the receiver to the image coordinate, in samples^2
-// (float-float, low part not renormalised), and the axis factor of the
-// reflection gain.
+// (float-float, low part not renormalised), the axis factor of the
+// reflection gain, and (polar calls) the displacement times the receiver's
+// unit orientation along this axis, in samples (0 otherwise).
 struct AxisEntry {
-  float sq_hi, sq_lo, gain, pad;
+  float sq_hi, sq_lo, gain, proj;
 };
 
 // Per-RIR offsets of the two image families of each axis, in samples: even

@@ -32,7 +32,7 @@ PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "lut": 3}
 EXPORTS = (
     "ism_status_string", "ism_abi_version", "ism_beta_from_t60", "ism_n_img_for_time",
     "ism_time_for_attenuation", "ism_n_samples", "ism_check_room", "ism_check_positions",
-    "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed",
+    "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed", "ism_simulate_polar",
     "ism_batch_workspace_size", "ism_batch_prepare", "ism_batch_run", "ism_batch_run_timed",
     "ism_diffuse_workspace_size", "ism_simulate_diffuse", "ism_simulate_diffuse_timed",
     "ism_filter_trajectory",
@@ -107,6 +107,9 @@ def lib() -> ctypes.CDLL:
         L.ism_simulate_timed.restype = ctypes.c_int
         L.ism_simulate_timed.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
                                          fp, fp, fp]
+        L.ism_simulate_polar.restype = ctypes.c_int
+        L.ism_simulate_polar.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, fp, ctypes.c_double, ctypes.c_int,
+                                         fp, fp, ctypes.c_size_t, fp]
         L.ism_diffuse_workspace_size.restype = ctypes.c_int
         L.ism_diffuse_workspace_size.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
@@ -253,6 +256,35 @@ class Simulator:
 def simulate(room: Room, src, rcv, precision: str = "fp32", device: str = "cuda"):
     """RIRs [n_src, n_rcv, nS] (float32, on ``device``) of every source/receiver pair."""
     return Simulator(room, src, rcv, precision, device).run()
+
+
+# First-order receiver patterns a + (1 - a) cos(theta) (ism_simulate_polar).
+PATTERNS = {"omni": 1.0, "subcardioid": 0.75, "cardioid": 0.5, "hypercardioid": 0.25, "bidirectional": 0.0}
+
+
+def simulate_polar(room: Room, src, rcv, orient, pattern="cardioid", device: str = "cuda", check: bool = True):
+    """RIRs [n_src, n_rcv, nS] with directional receivers: ``orient`` [n_rcv, 3]
+    orientations (normalised by the library), ``pattern`` a name of PATTERNS
+    or the coefficient a in [0, 1]. FP32 taps."""
+    import torch
+
+    a = PATTERNS[pattern] if isinstance(pattern, str) else float(pattern)
+    s, r = _host_pos(src), _host_pos(rcv)
+    o = _host_pos(orient)
+    if o.shape != r.shape:
+        raise ValueError(f"orient must be [n_rcv, 3] = {r.shape}, got {o.shape}")
+    if check:
+        check_positions(room, s, r)
+    rc = room._c()
+    nbytes = workspace_size(room, s.shape[0], r.shape[0], "fp32")
+    src_d, rcv_d, o_d = (torch.from_numpy(x).to(device) for x in (s, r, o))
+    out = torch.empty((s.shape[0], r.shape[0], room.n_samples), dtype=torch.float32, device=device)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+    st = torch.cuda.current_stream()
+    _check(lib().ism_simulate_polar(ctypes.byref(rc), src_d.data_ptr(), s.shape[0], rcv_d.data_ptr(), r.shape[0],
+                                    o_d.data_ptr(), a, PRECISIONS["fp32"], out.data_ptr(), ws.data_ptr(), nbytes,
+                                    st.cuda_stream), "ism_simulate_polar")
+    return out
 
 
 def diffuse_workspace_size(room: Room, t_diff: float, t60: float, n_src: int, n_rcv: int,

@@ -142,6 +142,23 @@ def test_simulate_rejects_bad_arguments_before_launch():
     assert L.ism_simulate(ctypes.byref(rc), fake, 1, fake, 1, 7, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
 
 
+def test_polar_checks_before_any_launch():
+    r = _room()
+    rc = r._c()
+    L = ism.lib()
+    fake = ctypes.c_void_p(0x1000)
+    need = ism.workspace_size(r, 1, 1)
+    ok = L.ism_simulate_polar
+    assert ok(ctypes.byref(rc), fake, 1, fake, 1, None, 0.5, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
+    for bad in (-0.1, 1.5, float("nan")):
+        assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, bad, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
+    assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, 0.5, 1, fake, fake, need, None) == ism.ISM_E_UNSUPPORTED
+    assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, 0.5, 3, fake, fake, need, None) == ism.ISM_E_UNSUPPORTED
+    assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, 0.5, 0, fake, fake, need - 1, None) == ism.ISM_E_WORKSPACE
+    assert ok(ctypes.byref(rc), fake, 0, fake, 1, fake, 0.5, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
+    assert set(ism.PATTERNS.values()) <= {0.0, 0.25, 0.5, 0.75, 1.0}
+
+
 def test_batch_checks_before_any_launch():
     r = _room()
     fake = 0x1000

@@ -1,8 +1,8 @@
 """Plant plausible mistakes in a copy of the oracle and check that the pins catch them.
 
 Each mutant is a one-expression edit of oracle/ism_oracle.c compiled into a
-temporary library; the pins of test_oracle_pins.py and test_oracle_lut.py are
-then run against it and at least one must fail. The oracle itself is never modified.
+temporary library; the pins of test_oracle_pins.py, test_oracle_lut.py and
+test_oracle_polar.py are then run against it and at least one must fail. The oracle itself is never modified.
 """
 import inspect
 import os
@@ -14,6 +14,7 @@ from oracle import oracle as oracle_module
 
 import tests.test_oracle_lut as lut_pins
 import tests.test_oracle_pins as pins
+import tests.test_oracle_polar as polar_pins
 
 MUTANTS = {
     "swap_wall_x0_x1": ("return ipow(b0, e0) * ipow(b1, e1);", "return ipow(b1, e0) * ipow(b0, e1);"),
@@ -39,12 +40,17 @@ MUTANTS = {
     "lut_weight_flipped": ("const double a = p - (double)n0;", "const double a = 1.0 - (p - (double)n0);"),
     "lut_window_width": ("cos(2.0 * PI * (double)n / (q * W))", "cos(2.0 * PI * (double)n / W)"),
     "lut_sinc_scale": ("double u = (double)n / q;", "double u = (double)n / (q - 1);"),
+    # directional receivers
+    "polar_direction_sign": ("im.to_image[a] = -diff;", "im.to_image[a] = diff;"),
+    "polar_coefficients_swapped": ("im.A *= pattern_a + (1.0 - pattern_a) * cos_theta;",
+                                   "im.A *= (1.0 - pattern_a) + pattern_a * cos_theta;"),
+    "polar_no_normalisation": ("/ (im.d * onorm);", "/ im.d;"),
 }
 
 
 def _pin_functions():
     out = []
-    members = inspect.getmembers(pins, inspect.isfunction) + inspect.getmembers(lut_pins, inspect.isfunction)
+    members = [m for mod in (pins, lut_pins, polar_pins) for m in inspect.getmembers(mod, inspect.isfunction)]
     for name, fn in members:
         if not name.startswith("test_"):
             continue
