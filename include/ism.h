@@ -155,7 +155,9 @@ int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const 
  *           axes; need not be unit length (normalised here); a zero vector
  *           gives NaN RIRs for that receiver;
  *   pattern: a in [0, 1], the same for every receiver;
- *   precision: ISM_FP32 only (others: ISM_E_UNSUPPORTED);
+ *   precision: ISM_FP32, ISM_FP16 or ISM_FP32_LUT (the pattern scales each
+ *           image's amplitude before its taps, in FP32; ISM_BF16 returns
+ *           ISM_E_UNSUPPORTED as for ism_simulate);
  *   the other arguments, the workspace (ism_workspace_size with the same
  *   room, counts and precision) and the errors as for ism_simulate, all
  *   checked before any launch; ISM_E_INVALID_ARG for a null orient or a

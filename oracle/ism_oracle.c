@@ -290,9 +290,9 @@ int oracle_rir_batch(const oracle_room *room, const double *src, int n_src, cons
 
 int oracle_rir_batch_polar(const oracle_room *room, const double *src, int n_src, const double *rcv,
                            int n_rcv, const double *orient, double pattern_a, int64_t k_begin, int64_t k_end,
-                           int n_threads, double *out) {
+                           int q, int n_threads, double *out) {
   if (!orient || !(pattern_a >= 0.0 && pattern_a <= 1.0)) return -1;
-  return rir_batch(room, src, n_src, rcv, n_rcv, k_begin, k_end, 0, orient, pattern_a, n_threads, out);
+  return rir_batch(room, src, n_src, rcv, n_rcv, k_begin, k_end, q, orient, pattern_a, n_threads, out);
 }
 
 int64_t oracle_image_list(const oracle_room *room, const double src[3], const double rcv[3],

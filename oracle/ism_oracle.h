@@ -71,10 +71,11 @@ int oracle_rir_batch_lut(const oracle_room *room, const double *src, int n_src, 
  * times a + (1 - a) cos(theta), theta the angle between orient[r] (the
  * receiver's orientation, [n_rcv][3], any nonzero length) and the direction
  * from the receiver to the image; a = pattern_a in [0, 1]. Returns -1 for a
- * null orient, a pattern outside [0, 1] or a zero orientation. */
+ * null orient, a pattern outside [0, 1] or a zero orientation. q > 0: table
+ * taps as for oracle_rir_batch_lut. */
 int oracle_rir_batch_polar(const oracle_room *room, const double *src, int n_src, const double *rcv,
                            int n_rcv, const double *orient, double pattern_a, int64_t k_begin, int64_t k_end,
-                           int n_threads, double *out);
+                           int q, int n_threads, double *out);
 
 /* Table taps of Sec. 3.5 at the offsets v[0..n) (v = k - x in samples, 0 for
  * |v| >= W/2), table of Eq. (9) at q points per sample. Returns -1 when

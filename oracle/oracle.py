@@ -65,7 +65,8 @@ def lib():
                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, dp]
         L.oracle_rir_batch_polar.restype = ctypes.c_int
         L.oracle_rir_batch_polar.argtypes = [ctypes.POINTER(_Room), dp, ctypes.c_int, dp, ctypes.c_int, dp,
-                                             ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp]
+                                             ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                             ctypes.c_int, dp]
         L.oracle_lut_taps.restype = ctypes.c_int
         L.oracle_lut_taps.argtypes = [dp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_image_list.restype = ctypes.c_int64
@@ -143,10 +144,11 @@ def rir(L, beta, n_img, c, fs, t_max, t_w, src, rcv, k_begin: int = 0, k_end: in
 
 
 def rir_polar(L, beta, n_img, c, fs, t_max, t_w, src, rcv, orient, pattern_a: float, k_begin: int = 0,
-              k_end: int | None = None, n_threads: int | None = None) -> np.ndarray:
+              k_end: int | None = None, n_threads: int | None = None, lut_q: int = 0) -> np.ndarray:
     """RIRs [n_src, n_rcv, k_end - k_begin] with directional receivers: each image's
     amplitude times a + (1 - a) cos(theta), theta between orient[r] and the
-    direction from the receiver to the image (first-order pattern family)."""
+    direction from the receiver to the image (first-order pattern family).
+    lut_q > 0: table taps as in ``rir``."""
     room = _room(L, beta, n_img, c, fs, t_max, t_w)
     if k_end is None:
         k_end = n_samples(t_max, fs)
@@ -156,7 +158,7 @@ def rir_polar(L, beta, n_img, c, fs, t_max, t_w, src, rcv, orient, pattern_a: fl
     out = np.zeros((s.shape[0], r.shape[0], k_end - k_begin))
     nt = n_threads or max(1, min(os.cpu_count() or 1, s.shape[0] * r.shape[0]))
     st = lib().oracle_rir_batch_polar(ctypes.byref(room), _dptr(s), s.shape[0], _dptr(r), r.shape[0], _dptr(o),
-                                      float(pattern_a), int(k_begin), int(k_end), int(nt), _dptr(out))
+                                      float(pattern_a), int(k_begin), int(k_end), int(lut_q), int(nt), _dptr(out))
     if st != 0:
         raise ValueError(f"oracle_rir_batch_polar failed with status {st}")
     return out

@@ -1101,17 +1101,17 @@ static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items
 
 bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt == 128; }
 
-// polar: FP32 taps only (the host rejects other precisions first).
+// polar: directional receivers (any tap mode; half and lut exclusive).
 int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &ra, const PlanArgs &pa,
                       uint32_t n_items, const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out,
                       float *part, float *marg, hipStream_t st) {
-  if (polar && (half || lut)) return -2;
-#define ISM_ACC(W)                                                                                              \
-  case W:                                                                                                       \
-    return half    ? launch_acc_w<W, true, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)     \
-           : lut   ? launch_acc_w<W, false, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)     \
-           : polar ? launch_acc_w<W, false, false, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st) \
-                   : launch_acc_w<W, false, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st);
+  if (half && lut) return -2;
+#define ISM_ACC_M(W, H, L)                                                                                   \
+  (polar ? launch_acc_w<W, H, L, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)             \
+         : launch_acc_w<W, H, L, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st))
+#define ISM_ACC(W) \
+  case W:          \
+    return half ? ISM_ACC_M(W, true, false) : lut ? ISM_ACC_M(W, false, true) : ISM_ACC_M(W, false, false);
   switch (wt) {
     ISM_ACC(32)
     ISM_ACC(64)
@@ -1120,6 +1120,7 @@ int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &r
     default: return -2;
   }
 #undef ISM_ACC
+#undef ISM_ACC_M
 }
 
 template <int WT, bool HALF>

@@ -415,7 +415,6 @@ int ism_simulate_polar(const ism_room *room, const float *src, int n_src, const 
   Plan p;
   const int st = make_plan(room, n_src, n_rcv, precision, p);
   if (st != ISM_OK) return st;
-  if (precision != ISM_FP32) return ISM_E_UNSUPPORTED;
   if (!src || !rcv || !out || !orient) return ISM_E_INVALID_ARG;
   if (!(pattern >= 0.0 && pattern <= 1.0)) return ISM_E_INVALID_ARG;
   if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;

@@ -262,10 +262,11 @@ def simulate(room: Room, src, rcv, precision: str = "fp32", device: str = "cuda"
 PATTERNS = {"omni": 1.0, "subcardioid": 0.75, "cardioid": 0.5, "hypercardioid": 0.25, "bidirectional": 0.0}
 
 
-def simulate_polar(room: Room, src, rcv, orient, pattern="cardioid", device: str = "cuda", check: bool = True):
+def simulate_polar(room: Room, src, rcv, orient, pattern="cardioid", precision: str = "fp32", device: str = "cuda",
+                   check: bool = True):
     """RIRs [n_src, n_rcv, nS] with directional receivers: ``orient`` [n_rcv, 3]
     orientations (normalised by the library), ``pattern`` a name of PATTERNS
-    or the coefficient a in [0, 1]. FP32 taps."""
+    or the coefficient a in [0, 1]; ``precision`` as for ``simulate``."""
     import torch
 
     a = PATTERNS[pattern] if isinstance(pattern, str) else float(pattern)
@@ -276,13 +277,13 @@ def simulate_polar(room: Room, src, rcv, orient, pattern="cardioid", device: str
     if check:
         check_positions(room, s, r)
     rc = room._c()
-    nbytes = workspace_size(room, s.shape[0], r.shape[0], "fp32")
+    nbytes = workspace_size(room, s.shape[0], r.shape[0], precision)
     src_d, rcv_d, o_d = (torch.from_numpy(x).to(device) for x in (s, r, o))
     out = torch.empty((s.shape[0], r.shape[0], room.n_samples), dtype=torch.float32, device=device)
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
     st = torch.cuda.current_stream()
     _check(lib().ism_simulate_polar(ctypes.byref(rc), src_d.data_ptr(), s.shape[0], rcv_d.data_ptr(), r.shape[0],
-                                    o_d.data_ptr(), a, PRECISIONS["fp32"], out.data_ptr(), ws.data_ptr(), nbytes,
+                                    o_d.data_ptr(), a, PRECISIONS[precision], out.data_ptr(), ws.data_ptr(), nbytes,
                                     st.cuda_stream), "ism_simulate_polar")
     return out
 

@@ -152,8 +152,7 @@ def test_polar_checks_before_any_launch():
     assert ok(ctypes.byref(rc), fake, 1, fake, 1, None, 0.5, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
     for bad in (-0.1, 1.5, float("nan")):
         assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, bad, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
-    assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, 0.5, 1, fake, fake, need, None) == ism.ISM_E_UNSUPPORTED
-    assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, 0.5, 3, fake, fake, need, None) == ism.ISM_E_UNSUPPORTED
+    assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, 0.5, 2, fake, fake, need, None) == ism.ISM_E_UNSUPPORTED
     assert ok(ctypes.byref(rc), fake, 1, fake, 1, fake, 0.5, 0, fake, fake, need - 1, None) == ism.ISM_E_WORKSPACE
     assert ok(ctypes.byref(rc), fake, 0, fake, 1, fake, 0.5, 0, fake, fake, need, None) == ism.ISM_E_INVALID_ARG
     assert set(ism.PATTERNS.values()) <= {0.0, 0.25, 0.5, 0.75, 1.0}

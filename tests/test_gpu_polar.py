@@ -91,3 +91,24 @@ def test_polar_workload_sampled(oracle_mod):
     err = rel_err(got[:, pick], ref)
     print("polar 32rcv rel err", err)
     assert np.all(err <= TOL)
+
+
+@pytest.mark.parametrize("precision,tol,lut_q", [("fp16", 2e-3, 0), ("lut", 1e-5, 16)])
+@pytest.mark.parametrize("case", [CASES[1], CASES[2]], ids=[CASES[1][0], CASES[2][0]])
+def test_polar_other_tap_modes(oracle_mod, case, precision, tol, lut_q):
+    """The pattern scales each image's amplitude before its taps, so it composes
+    with the FP16 taps (their 2e-3 bound) and the table taps (compared with the
+    oracle's table taps, 1e-5)."""
+    import torch
+
+    name, L, beta, n, fs, t_max, t_w, src, rcv = case
+    room = ism.Room(L, beta, n, 343.0, fs, t_max, t_w)
+    o = _orients(len(rcv), 3)
+    _say(f"polar {precision} {name}")
+    got = ism.simulate_polar(room, src, rcv, o, "hypercardioid", precision=precision)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.float64)
+    ref = oracle_mod.rir_polar(L, beta, n, 343.0, fs, t_max, t_w, src, rcv, o, 0.25, lut_q=lut_q)
+    err = rel_err(got, ref)
+    print(name, precision, "polar rel err", err)
+    assert np.all(err <= tol)
