@@ -73,3 +73,32 @@ def test_diffuse_streams_differ_by_seed_and_pair():
     assert np.array_equal(a[0, 0, :k], a[0, 1, :k])      # same position: same ISM part
     assert not np.allclose(a[0, 0, k:], a[0, 1, k:])     # but its own noise stream
     assert not np.allclose(a[0, 0, k:], c[0, 0, k:])     # and another seed, another tail
+
+
+@pytest.mark.parametrize("precision", ["fp16", "lut"])
+def test_diffuse_other_tap_modes(precision):
+    """The diffuse call plans its ISM part like a single call with
+    T_max = t_diff, so with FP16 or table taps that part equals ism_simulate's
+    result bit for bit; the tail draws the same words as the FP32 call, so it
+    is the FP32 tail times one constant per RIR, sqrt(A_mode / A_fp32)."""
+    import torch
+
+    name, L, t60, fs, t_w, t_diff, t_max, src, rcv, seed = CASES[0]
+    beta = ism.beta_from_t60(L, t60)
+    n = ism.n_img_for_time(L, 343.0, t_diff)
+    room = ism.Room(L, list(beta), n, 343.0, fs, t_max, t_w)
+    room_ism = ism.Room(L, list(beta), n, 343.0, fs, t_diff, t_w)
+    _say(f"diffuse {precision} {name}")
+    got = ism.simulate_diffuse(room, src, rcv, t_diff, t60, seed, precision=precision).cpu().numpy()
+    ism_part = ism.simulate(room_ism, src, rcv, precision=precision).cpu().numpy()
+    ref32 = ism.simulate_diffuse(room, src, rcv, t_diff, t60, seed).cpu().numpy()
+    torch.cuda.synchronize()
+    k_diff = ism.n_samples(t_diff, fs)
+    assert np.array_equal(got[..., :k_diff], ism_part)
+    tail, tail32 = got[..., k_diff:].astype(np.float64), ref32[..., k_diff:].astype(np.float64)
+    for i in np.ndindex(tail.shape[:-1]):
+        big = np.abs(tail32[i]) > 1e-3 * np.max(np.abs(tail32[i]))
+        ratio = tail[i][big] / tail32[i][big]
+        c = np.median(ratio)
+        assert 0.9 < c < 1.1  # the level moves with the tap mode's small error only
+        assert np.max(np.abs(ratio - c)) <= 1e-5 * abs(c)
