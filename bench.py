@@ -245,6 +245,11 @@ def main() -> int:
               "shard across GPUs.", file=sys.stderr)
         return 2
 
+    if args.precision == "lut" and (args.workload == "batch_rooms" or args.rate > 0):
+        print("table taps (--precision lut) are a single-room mode: batches and the serving loop "
+              "take fp32 or fp16", file=sys.stderr)
+        return 2
+
     import torch
 
     from paper_1810_11359_amd import ism, workloads
