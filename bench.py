@@ -245,9 +245,8 @@ def main() -> int:
               "shard across GPUs.", file=sys.stderr)
         return 2
 
-    if args.precision == "lut" and (args.workload == "batch_rooms" or args.rate > 0):
-        print("table taps (--precision lut) are a single-room mode: batches and the serving loop "
-              "take fp32 or fp16", file=sys.stderr)
+    if args.precision == "lut" and args.rate > 0:
+        print("the serving loop takes fp32 or fp16 taps, not table taps (--precision lut)", file=sys.stderr)
         return 2
 
     import torch

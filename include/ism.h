@@ -47,8 +47,7 @@ enum {
  *   at Q = 16 points per sample (Eq. (9), Sec. 3.5) and interpolated linearly
  *   between the two entries around its delay, in FP32. The interpolation
  *   moves a tap by at most 1.6e-3 of its amplitude from Eq. (6) (the linear
- *   interpolation bound h^2/8 max|s''| with h = 1/16). Single-room and diffuse
- *   calls only; ism_batch_* return ISM_E_UNSUPPORTED for it. */
+ *   interpolation bound h^2/8 max|s''| with h = 1/16). All calls accept it. */
 typedef enum { ISM_FP32 = 0, ISM_FP16 = 1, ISM_BF16 = 2, ISM_FP32_LUT = 3 } ism_precision;
 
 /* One shoebox room and its simulation parameters (Sec. 2.1, Sec. 4). */

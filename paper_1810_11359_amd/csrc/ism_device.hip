@@ -967,7 +967,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
 }
 
 // Batch launch: every item names its job; the job table carries the room.
-template <int WT, bool HALF, int NQ>
+template <int WT, bool HALF, int NQ, bool LUT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
@@ -981,8 +981,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
   float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
                                         : part + (size_t)it.slot * TILE;
   const AxisOrigin org = origin[grir];
-  accumulate_item<WT, HALF, NQ>(ra, it.tile, it.chunks, it.chunk, tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab,
-                                org, valid[grir] != 0, dst, marg + (size_t)it.mslot * MARG_STRIDE);
+  accumulate_item<WT, HALF, NQ, LUT>(ra, it.tile, it.chunks, it.chunk,
+                                     tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org, valid[grir] != 0, dst,
+                                     marg + (size_t)it.mslot * MARG_STRIDE);
 }
 
 // ---------------------------------------------------------------------------
@@ -1123,17 +1124,18 @@ int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &r
 #undef ISM_ACC_M
 }
 
-template <int WT, bool HALF>
+template <int WT, bool HALF, bool LUT>
 static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
                               const AxisOrigin *origin, const int *valid, float *part, float *marg, hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF)>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
+  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF), LUT>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
                      origin, valid, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 bool half, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid,
+                 bool half, bool lut, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin,
+                 int *valid,
                  float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
   if (hipGetLastError() != hipSuccess) return -1;
@@ -1142,10 +1144,11 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
     if (class_count[k] == 0) continue;
     const BatchItem *it = items + class_first[k];
     int rc = -2;
-#define ISM_BACC(W)                                                                                     \
-  case W:                                                                                               \
-    rc = half ? launch_acc_batch_w<W, true>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)   \
-              : launch_acc_batch_w<W, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st); \
+#define ISM_BACC(W)                                                                                           \
+  case W:                                                                                                     \
+    rc = half  ? launch_acc_batch_w<W, true, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)  \
+         : lut ? launch_acc_batch_w<W, false, true>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)  \
+               : launch_acc_batch_w<W, false, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st); \
     break;
     switch (class_wt[k]) {
       ISM_BACC(32)

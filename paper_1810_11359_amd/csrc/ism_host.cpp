@@ -26,7 +26,8 @@ int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float
 bool supported_window(int wt);
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 bool half, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid,
+                 bool half, bool lut, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin,
+                 int *valid,
                  float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
                    double t60, uint64_t seed, hipStream_t st);
@@ -492,7 +493,7 @@ constexpr int kMaxClasses = 4;
 struct BatchState {  // stored in ism_batch::opaque
   uint64_t ws;
   uint64_t off_jobs, off_rirs, off_items, off_red, off_valid, off_origin, off_tab, off_part, off_marg;
-  uint32_t n_rir, n_red, n_classes, half;
+  uint32_t n_rir, n_red, n_classes, mode;  // mode: 0 FP32, 1 FP16, 2 table taps
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
   int32_t class_wt[kMaxClasses];
 };
@@ -521,7 +522,6 @@ int cost_bucket(double cost) {
 // item and reduce tables are built as well (ism_batch_prepare).
 int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bool fill) {
   if (!jobs || n_jobs < 1) return ISM_E_INVALID_ARG;
-  if (precision == ISM_FP32_LUT) return ISM_E_UNSUPPORTED;  // table taps: single-room calls only
   std::memset(&bp.st, 0, sizeof(bp.st));
   // Each job is planned as a single call would plan it without the tail
   // taper (items sized from the job's own work), so a job's result does not
@@ -574,7 +574,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
     bp.st.class_wt[k] = class_wt[k];
   }
   bp.st.n_classes = (uint32_t)n_classes;
-  bp.st.half = precision == ISM_FP16 ? 1u : 0u;
+  bp.st.mode = precision == ISM_FP16 ? 1u : precision == ISM_FP32_LUT ? 2u : 0u;
   bp.st.n_rir = (uint32_t)n_rir;
   bp.st.n_red = (uint32_t)n_red;
   size_t o = 0;
@@ -704,7 +704,7 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
   char *w = (char *)(uintptr_t)b.ws;
   const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (const BatchRir *)(w + b.off_rirs), b.n_rir,
                               (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_wt,
-                              (int)b.n_classes, b.half != 0, (const BatchReduce *)(w + b.off_red), b.n_red,
+                              (int)b.n_classes, b.mode == 1, b.mode == 2, (const BatchReduce *)(w + b.off_red), b.n_red,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
                               (int *)(w + b.off_valid), (float *)(w + b.off_part), (float *)(w + b.off_marg),
                               (hipStream_t)stream,

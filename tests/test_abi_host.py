@@ -175,7 +175,10 @@ def test_batch_checks_before_any_launch():
     jobs[1].out = None
     assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_E_INVALID_ARG
     jobs[1].out = fake
-    assert L.ism_batch_workspace_size(jobs, 2, ism.PRECISIONS["lut"], ctypes.byref(n)) == ism.ISM_E_UNSUPPORTED
+    n_lut = ctypes.c_size_t()
+    assert L.ism_batch_workspace_size(jobs, 2, ism.PRECISIONS["lut"], ctypes.byref(n_lut)) == ism.ISM_OK
+    assert n_lut.value == n.value  # table taps plan like FP32
+    assert L.ism_batch_workspace_size(jobs, 2, ism.PRECISIONS["bf16"], ctypes.byref(n)) == ism.ISM_E_UNSUPPORTED
     b = ism._Batch()
     assert L.ism_batch_prepare(jobs, 2, 0, None, 0, None, ctypes.byref(b)) == ism.ISM_E_WORKSPACE
     assert L.ism_batch_run(ctypes.byref(ism._Batch()), None) == ism.ISM_E_INVALID_ARG

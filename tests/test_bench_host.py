@@ -13,11 +13,11 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_table_taps_refused_for_batches():
-    r = subprocess.run([sys.executable, "bench.py", "--workload", "batch_rooms", "--precision", "lut"],
+def test_table_taps_refused_for_serving():
+    r = subprocess.run([sys.executable, "bench.py", "--rate", "100", "--precision", "lut"],
                        cwd=bench.ROOT, capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
-    assert "single-room" in r.stderr
+    assert "serving loop" in r.stderr
 
 
 def test_traffic_only_for_the_profiled_library(monkeypatch):

@@ -71,6 +71,23 @@ def test_batch_equals_single_room_calls(oracle_mod, monkeypatch):
         assert np.all(err <= TOL_FP32)
 
 
+def test_batch_table_taps_equal_single_calls(monkeypatch):
+    """Table taps (Eq. (9)) through the batch path: each job bitwise equal to
+    its own single-room call with the same precision."""
+    import torch
+
+    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
+    jobs = _mixed_jobs()
+    _say("mixed batch, table taps")
+    b = ism.BatchSimulator(jobs, precision="lut")
+    outs = [o.clone() for o in b.run()]
+    torch.cuda.synchronize()
+    for (room, src, rcv), o in zip(jobs, outs):
+        single = ism.simulate(room, src, rcv, precision="lut")
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), f"batch differs from single-room call for {room.room}"
+
+
 def _feasible(oracle_mod):
     def ok(room, t60):
         try:
