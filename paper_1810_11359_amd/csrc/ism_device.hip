@@ -4,17 +4,22 @@
 //   tables_kernel      per (RIR, axis, lattice index): displacement of the image
 //                      coordinate from the receiver in samples (float-float) and
 //                      the axis factor of the reflection gain (Sec. 2.1, Eq. (1)
-//                      and the gain rule below it). Also flags invalid pairs.
+//                      and the gain rule below it); for directional receivers
+//                      also the displacement's share of the projection onto the
+//                      receiver's orientation. Also flags invalid pairs.
 //   accumulate_kernel  per work item (RIR, output tile, slab of the image shell):
 //                      enumerates exactly the lattice images whose window can
 //                      reach the tile, computes each image's delay and amplitude
-//                      (Eq. (2)-(4)) and adds its Hann-windowed-sinc taps (Eq. (6))
-//                      into wave-private FP32 LDS tiles (Eq. (5)).
+//                      (Eq. (2)-(4), times the receiver's polar pattern when
+//                      directional) and adds its Hann-windowed-sinc taps
+//                      (Eq. (6): FP32, packed FP16, or read from the table of
+//                      Eq. (9)) into wave-private FP32 LDS tiles (Eq. (5)).
 //   reduce_kernel      sums, in a fixed order, the partial tiles of tiles that
 //                      were split over several work items.
 //
-// Arithmetic is FP32 only; delays use error-free transformations so that the
-// fractional delay keeps ~1e-7 sample accuracy at 1e5-sample distances.
+// Geometry and accumulation are FP32 only; delays use error-free
+// transformations so that the fractional delay keeps ~1e-7 sample accuracy at
+// 1e5-sample distances.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
