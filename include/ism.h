@@ -205,6 +205,18 @@ int ism_simulate_diffuse_timed(const ism_room *room, double t_diff, double t60, 
                                int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
                                size_t ws_bytes, void *stream, void *ev_start, void *ev_stop);
 
+/* ism_simulate_diffuse with directional receivers (Sec. 4; pattern and
+ * orientation as for ism_simulate_polar). The ISM part is the directional RIR
+ * that ism_simulate_polar gives for T_max = t_diff; the tail is drawn as for
+ * ism_simulate_diffuse, at the level A estimated from that directional ISM
+ * part (reading: the diffuse field itself is not directional).
+ *   orient, pattern: as for ism_simulate_polar; the other arguments, the
+ *   workspace (ism_diffuse_workspace_size) and the errors as for
+ *   ism_simulate_diffuse, all checked before any launch. Asynchronous. */
+int ism_simulate_diffuse_polar(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
+                               int n_src, const float *rcv, int n_rcv, const float *orient, double pattern,
+                               int precision, float *out, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- Moving source (Sec. 3.4) -------------------------------------------------- */
 
 /* Filters a source signal through the RIRs of a trajectory by overlap-add:

@@ -465,23 +465,45 @@ int ism_simulate_diffuse(const ism_room *room, double t_diff, double t60, uint64
                                     stream, nullptr, nullptr);
 }
 
-int ism_simulate_diffuse_timed(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
-                               int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
-                               size_t ws_bytes, void *stream, void *ev_start, void *ev_stop) {
+// Diffuse RIRs; orient != null makes the receivers directional (pattern a).
+static int simulate_diffuse(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
+                            int n_src, const float *rcv, int n_rcv, const float *orient, double pattern,
+                            int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
+                            void *ev_stop) {
   Plan p;
   int64_t n_full;
   size_t off_ism, need;
   const int st = diffuse_plan(room, t_diff, t60, n_src, n_rcv, precision, p, n_full, off_ism, need);
   if (st != ISM_OK) return st;
   if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
+  if (orient && !(pattern >= 0.0 && pattern <= 1.0)) return ISM_E_INVALID_ARG;
   if (!ws || ws_bytes < need) return ISM_E_WORKSPACE;
+  if (orient) {
+    p.ra.dir_a = (float)pattern;
+    p.ra.dir_b = (float)(1.0 - pattern);
+  }
   float *ism = (float *)((char *)ws + off_ism);
-  const int rs = run_plan(p, src, rcv, ism, ws, stream, ev_start, ev_stop);
+  const int rs = run_plan(p, src, rcv, ism, ws, stream, ev_start, ev_stop, orient);
   if (rs != ISM_OK) return rs;
   if (launch_diffuse(ism, p.ra.n_samples, out, (int)n_full, p.n_rir, room->fs, t_diff, t60, seed,
                      (hipStream_t)stream) != 0)
     return ISM_E_DEVICE;
   return ISM_OK;
+}
+
+int ism_simulate_diffuse_timed(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
+                               int n_src, const float *rcv, int n_rcv, int precision, float *out, void *ws,
+                               size_t ws_bytes, void *stream, void *ev_start, void *ev_stop) {
+  return simulate_diffuse(room, t_diff, t60, seed, src, n_src, rcv, n_rcv, nullptr, 1.0, precision, out, ws,
+                          ws_bytes, stream, ev_start, ev_stop);
+}
+
+int ism_simulate_diffuse_polar(const ism_room *room, double t_diff, double t60, uint64_t seed, const float *src,
+                               int n_src, const float *rcv, int n_rcv, const float *orient, double pattern,
+                               int precision, float *out, void *ws, size_t ws_bytes, void *stream) {
+  if (!orient) return ISM_E_INVALID_ARG;
+  return simulate_diffuse(room, t_diff, t60, seed, src, n_src, rcv, n_rcv, orient, pattern, precision, out, ws,
+                          ws_bytes, stream, nullptr, nullptr);
 }
 
 // ---- batches ------------------------------------------------------------------

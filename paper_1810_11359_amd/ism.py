@@ -33,6 +33,7 @@ EXPORTS = (
     "ism_status_string", "ism_abi_version", "ism_beta_from_t60", "ism_n_img_for_time",
     "ism_time_for_attenuation", "ism_n_samples", "ism_check_room", "ism_check_positions",
     "ism_count_taps", "ism_workspace_size", "ism_simulate", "ism_simulate_timed", "ism_simulate_polar",
+    "ism_simulate_diffuse_polar",
     "ism_batch_workspace_size", "ism_batch_prepare", "ism_batch_run", "ism_batch_run_timed",
     "ism_diffuse_workspace_size", "ism_simulate_diffuse", "ism_simulate_diffuse_timed",
     "ism_filter_trajectory",
@@ -110,6 +111,10 @@ def lib() -> ctypes.CDLL:
         L.ism_simulate_polar.restype = ctypes.c_int
         L.ism_simulate_polar.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, fp, ctypes.c_double, ctypes.c_int,
                                          fp, fp, ctypes.c_size_t, fp]
+        L.ism_simulate_diffuse_polar.restype = ctypes.c_int
+        L.ism_simulate_diffuse_polar.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp, ctypes.c_int,
+                                                 fp, ctypes.c_int, fp, ctypes.c_double, ctypes.c_int, fp, fp,
+                                                 ctypes.c_size_t, fp]
         L.ism_diffuse_workspace_size.restype = ctypes.c_int
         L.ism_diffuse_workspace_size.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
@@ -338,6 +343,32 @@ def simulate_diffuse(room: Room, src, rcv, t_diff: float, t60: float, seed: int 
                      device: str = "cuda"):
     """RIRs [n_src, n_rcv, nS] with the ISM up to t_diff and the diffuse tail after it."""
     return DiffuseSimulator(room, src, rcv, t_diff, t60, seed, precision, device).run()
+
+
+def simulate_diffuse_polar(room: Room, src, rcv, orient, t_diff: float, t60: float, seed: int = 0,
+                           pattern="cardioid", precision: str = "fp32", device: str = "cuda", check: bool = True):
+    """``simulate_diffuse`` with directional receivers (``orient`` and
+    ``pattern`` as for ``simulate_polar``): directional ISM part, tail at the
+    level of that part."""
+    import torch
+
+    a = PATTERNS[pattern] if isinstance(pattern, str) else float(pattern)
+    s, r, o = _host_pos(src), _host_pos(rcv), _host_pos(orient)
+    if o.shape != r.shape:
+        raise ValueError(f"orient must be [n_rcv, 3] = {r.shape}, got {o.shape}")
+    if check:
+        check_positions(room, s, r)
+    rc = room._c()
+    nbytes = diffuse_workspace_size(room, t_diff, t60, s.shape[0], r.shape[0], precision)
+    src_d, rcv_d, o_d = (torch.from_numpy(x).to(device) for x in (s, r, o))
+    out = torch.empty((s.shape[0], r.shape[0], room.n_samples), dtype=torch.float32, device=device)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+    st = torch.cuda.current_stream()
+    _check(lib().ism_simulate_diffuse_polar(ctypes.byref(rc), float(t_diff), float(t60), int(seed), src_d.data_ptr(),
+                                            s.shape[0], rcv_d.data_ptr(), r.shape[0], o_d.data_ptr(), a,
+                                            PRECISIONS[precision], out.data_ptr(), ws.data_ptr(), nbytes,
+                                            st.cuda_stream), "ism_simulate_diffuse_polar")
+    return out
 
 
 def filter_trajectory(x, rirs, stream=None):

@@ -158,6 +158,23 @@ def test_polar_checks_before_any_launch():
     assert set(ism.PATTERNS.values()) <= {0.0, 0.25, 0.5, 0.75, 1.0}
 
 
+def test_diffuse_polar_checks_before_any_launch():
+    r = _room()
+    rc = r._c()
+    L = ism.lib()
+    fake = ctypes.c_void_p(0x1000)
+    need = ism.diffuse_workspace_size(r, 0.02, 0.5, 1, 1)
+    f = L.ism_simulate_diffuse_polar
+    assert f(ctypes.byref(rc), 0.02, 0.5, 1, fake, 1, fake, 1, None, 0.5, 0, fake, fake, need, None) == \
+        ism.ISM_E_INVALID_ARG
+    assert f(ctypes.byref(rc), 0.02, 0.5, 1, fake, 1, fake, 1, fake, 2.0, 0, fake, fake, need, None) == \
+        ism.ISM_E_INVALID_ARG
+    assert f(ctypes.byref(rc), 0.02, 0.5, 1, fake, 1, fake, 1, fake, 0.5, 0, fake, fake, need - 1, None) == \
+        ism.ISM_E_WORKSPACE
+    assert f(ctypes.byref(rc), -1.0, 0.5, 1, fake, 1, fake, 1, fake, 0.5, 0, fake, fake, need, None) == \
+        ism.ISM_E_INVALID_ARG
+
+
 def test_batch_checks_before_any_launch():
     r = _room()
     fake = 0x1000

@@ -102,3 +102,33 @@ def test_diffuse_other_tap_modes(precision):
         c = np.median(ratio)
         assert 0.9 < c < 1.1  # the level moves with the tap mode's small error only
         assert np.max(np.abs(ratio - c)) <= 1e-5 * abs(c)
+
+
+def test_diffuse_directional_receivers():
+    """ism_simulate_diffuse_polar: the ISM part equals ism_simulate_polar's
+    RIR for T_max = t_diff bit for bit, and the tail draws the same words as
+    the omnidirectional call, so it is that tail times one constant per RIR
+    (the square root of the ratio of the two levels A)."""
+    import torch
+
+    name, L, t60, fs, t_w, t_diff, t_max, src, rcv, seed = CASES[0]
+    beta = ism.beta_from_t60(L, t60)
+    n = ism.n_img_for_time(L, 343.0, t_diff)
+    room = ism.Room(L, list(beta), n, 343.0, fs, t_max, t_w)
+    room_ism = ism.Room(L, list(beta), n, 343.0, fs, t_diff, t_w)
+    o = np.array([[1.0, 0.0, 0.0], [0.0, -1.0, 0.5], [0.3, 0.3, 1.0]], dtype=np.float32)
+    _say(f"diffuse cardioid {name}")
+    got = ism.simulate_diffuse_polar(room, src, rcv, o, t_diff, t60, seed, "cardioid").cpu().numpy()
+    ism_part = ism.simulate_polar(room_ism, src, rcv, o, "cardioid").cpu().numpy()
+    omni = ism.simulate_diffuse(room, src, rcv, t_diff, t60, seed).cpu().numpy()
+    torch.cuda.synchronize()
+    k_diff = ism.n_samples(t_diff, fs)
+    assert np.array_equal(got[..., :k_diff], ism_part)
+    assert not np.allclose(got[..., :k_diff], omni[..., :k_diff])
+    tail, tail_o = got[..., k_diff:].astype(np.float64), omni[..., k_diff:].astype(np.float64)
+    for i in np.ndindex(tail.shape[:-1]):
+        big = np.abs(tail_o[i]) > 1e-3 * np.max(np.abs(tail_o[i]))
+        ratio = tail[i][big] / tail_o[i][big]
+        c = np.median(ratio)
+        assert 0.0 < c < 1.5
+        assert np.max(np.abs(ratio - c)) <= 1e-5 * c
