@@ -246,6 +246,9 @@ typedef struct {
   const float *rcv; /* device float32 [n_rcv][3] */
   int n_rcv;
   float *out;       /* device float32 [n_src][n_rcv][nS(room)], caller-owned, overwritten */
+  const float *orient; /* NULL: omnidirectional receivers; else device float32 [n_rcv][3]
+                          receiver orientations, as for ism_simulate_polar      */
+  double pattern;   /* polar pattern a in [0, 1] when orient is set (ignored otherwise) */
 } ism_job;
 
 /* Host-side record of a prepared batch, filled by ism_batch_prepare and read by

@@ -315,7 +315,8 @@ __global__ __launch_bounds__(256) void tables_batch_kernel(const JobDev *__restr
   const float *s3 = jb.src + 3 * (br.rir / ra.n_rcv);
   const float *r3 = jb.rcv + 3 * (br.rir % ra.n_rcv);
   AxisEntry *t = tab + jb.tab_base + (size_t)br.rir * ra.n_tab;
-  for (int e = threadIdx.x; e < ra.n_tab; e += blockDim.x) t[e] = table_entry(ra, s3, r3, e);
+  const float *o3 = jb.orient ? jb.orient + 3 * (br.rir % ra.n_rcv) : nullptr;
+  for (int e = threadIdx.x; e < ra.n_tab; e += blockDim.x) t[e] = table_entry(ra, s3, r3, e, o3);
   if (threadIdx.x == 0) {
     AxisOrigin o;
     valid[blockIdx.x] = rir_header(ra, s3, r3, o);
@@ -972,7 +973,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
 }
 
 // Batch launch: every item names its job; the job table carries the room.
-template <int WT, bool HALF, int NQ, bool LUT>
+template <int WT, bool HALF, int NQ, bool LUT, bool POLAR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
@@ -986,7 +987,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
   float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
                                         : part + (size_t)it.slot * TILE;
   const AxisOrigin org = origin[grir];
-  accumulate_item<WT, HALF, NQ, LUT>(ra, it.tile, it.chunks, it.chunk,
+  accumulate_item<WT, HALF, NQ, LUT, POLAR>(ra, it.tile, it.chunks, it.chunk,
                                      tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org, valid[grir] != 0, dst,
                                      marg + (size_t)it.mslot * MARG_STRIDE);
 }
@@ -1129,18 +1130,18 @@ int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &r
 #undef ISM_ACC_M
 }
 
-template <int WT, bool HALF, bool LUT>
+template <int WT, bool HALF, bool LUT, bool POLAR>
 static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
                               const AxisOrigin *origin, const int *valid, float *part, float *marg, hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF), LUT>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
+  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
                      origin, valid, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 bool half, bool lut, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin,
-                 int *valid,
+                 bool half, bool lut, bool polar, const BatchReduce *red, uint32_t n_red, AxisEntry *tab,
+                 AxisOrigin *origin, int *valid,
                  float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
   if (hipGetLastError() != hipSuccess) return -1;
@@ -1149,11 +1150,12 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
     if (class_count[k] == 0) continue;
     const BatchItem *it = items + class_first[k];
     int rc = -2;
+#define ISM_BACC_M(W, H, L)                                                                                     \
+  (polar ? launch_acc_batch_w<W, H, L, true>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)          \
+         : launch_acc_batch_w<W, H, L, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st))
 #define ISM_BACC(W)                                                                                           \
   case W:                                                                                                     \
-    rc = half  ? launch_acc_batch_w<W, true, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)  \
-         : lut ? launch_acc_batch_w<W, false, true>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)  \
-               : launch_acc_batch_w<W, false, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st); \
+    rc = half ? ISM_BACC_M(W, true, false) : lut ? ISM_BACC_M(W, false, true) : ISM_BACC_M(W, false, false); \
     break;
     switch (class_wt[k]) {
       ISM_BACC(32)
@@ -1163,6 +1165,7 @@ int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const
       default: break;
     }
 #undef ISM_BACC
+#undef ISM_BACC_M
     if (rc != 0) return -1;
   }
   if (ev_stop && hipEventRecord(ev_stop, st) != hipSuccess) return -1;

@@ -26,8 +26,8 @@ int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float
 bool supported_window(int wt);
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 bool half, bool lut, const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin,
-                 int *valid,
+                 bool half, bool lut, bool polar, const BatchReduce *red, uint32_t n_red, AxisEntry *tab,
+                 AxisOrigin *origin, int *valid,
                  float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
                    double t60, uint64_t seed, hipStream_t st);
@@ -516,6 +516,7 @@ struct BatchState {  // stored in ism_batch::opaque
   uint64_t ws;
   uint64_t off_jobs, off_rirs, off_items, off_red, off_valid, off_origin, off_tab, off_part, off_marg;
   uint32_t n_rir, n_red, n_classes, mode;  // mode: 0 FP32, 1 FP16, 2 table taps
+  uint32_t polar, pad;                      // 1: directional kernels
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
   int32_t class_wt[kMaxClasses];
 };
@@ -550,8 +551,16 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
   // depend on the batch; tapering every job would only fragment small jobs,
   // and the batch's own tail is the largest-first order over all its items.
   std::vector<Plan> plans(n_jobs);
-  for (int j = 0; j < n_jobs; ++j)
+  bool polar = false;
+  for (int j = 0; j < n_jobs; ++j) {
     if (!jobs[j].src || !jobs[j].rcv || !jobs[j].out) return ISM_E_INVALID_ARG;
+    if (jobs[j].orient) {
+      if (!(jobs[j].pattern >= 0.0 && jobs[j].pattern <= 1.0)) return ISM_E_INVALID_ARG;
+      polar = true;
+    }
+  }
+  // with any directional job the batch runs the directional kernels; the
+  // others take the pattern a = 1, b = 0, whose factor is exactly 1
   // pass 1: plans, window classes and counts
   int n_classes = 0;
   int class_wt[kMaxClasses] = {0, 0, 0, 0};
@@ -597,6 +606,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
   }
   bp.st.n_classes = (uint32_t)n_classes;
   bp.st.mode = precision == ISM_FP16 ? 1u : precision == ISM_FP32_LUT ? 2u : 0u;
+  bp.st.polar = polar ? 1u : 0u;
   bp.st.n_rir = (uint32_t)n_rir;
   bp.st.n_red = (uint32_t)n_red;
   size_t o = 0;
@@ -635,9 +645,12 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
     JobDev &d = bp.jobs[j];
     std::memset(&d, 0, sizeof(d));
     d.ra = p.ra;
+    d.ra.dir_a = jb.orient ? (float)jb.pattern : 1.0f;
+    d.ra.dir_b = jb.orient ? (float)(1.0 - jb.pattern) : 0.0f;
     d.src = jb.src;
     d.rcv = jb.rcv;
     d.out = jb.out;
+    d.orient = jb.orient;
     d.tab_base = tab_base;
     d.rir_base = (uint32_t)rir_base;
     for (int r = 0; r < p.n_rir; ++r) bp.rirs[rir_base + r] = BatchRir{(uint32_t)j, (uint32_t)r};
@@ -726,7 +739,8 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
   char *w = (char *)(uintptr_t)b.ws;
   const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (const BatchRir *)(w + b.off_rirs), b.n_rir,
                               (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_wt,
-                              (int)b.n_classes, b.mode == 1, b.mode == 2, (const BatchReduce *)(w + b.off_red), b.n_red,
+                              (int)b.n_classes, b.mode == 1, b.mode == 2, b.polar != 0,
+                              (const BatchReduce *)(w + b.off_red), b.n_red,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
                               (int *)(w + b.off_valid), (float *)(w + b.off_part), (float *)(w + b.off_marg),
                               (hipStream_t)stream,

@@ -77,12 +77,13 @@ struct AxisOrigin {
 // Batch mode: one entry per job (room) of a batch, uploaded once per prepared
 // batch. Pointers are device pointers owned by the caller.
 struct JobDev {
-  RoomArgs ra;
+  RoomArgs ra;  // dir_a = 1, dir_b = 0 for omnidirectional jobs
   const float *src;
   const float *rcv;
   float *out;
-  uint64_t tab_base;  // first table entry of the job's first RIR
-  uint32_t rir_base;  // batch-wide index of the job's first RIR
+  const float *orient;  // receiver orientations, or null (omnidirectional)
+  uint64_t tab_base;    // first table entry of the job's first RIR
+  uint32_t rir_base;    // batch-wide index of the job's first RIR
   uint32_t pad;
 };
 

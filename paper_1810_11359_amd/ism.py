@@ -54,7 +54,8 @@ class _Room(ctypes.Structure):
 
 class _Job(ctypes.Structure):
     _fields_ = [("room", _Room), ("src", ctypes.c_void_p), ("n_src", ctypes.c_int), ("rcv", ctypes.c_void_p),
-                ("n_rcv", ctypes.c_int), ("out", ctypes.c_void_p)]
+                ("n_rcv", ctypes.c_int), ("out", ctypes.c_void_p), ("orient", ctypes.c_void_p),
+                ("pattern", ctypes.c_double)]
 
 
 class _Batch(ctypes.Structure):
@@ -404,8 +405,9 @@ def room_for(w) -> Room:
 class BatchSimulator:
     """Many rooms in one prepared batch (``ism_batch_prepare`` once, ``ism_batch_run`` per call).
 
-    ``jobs`` is a list of (Room, src, rcv); outputs are ``self.outs[i]`` with
-    shape [n_src, n_rcv, nS] on ``device``.
+    ``jobs`` is a list of (Room, src, rcv), or (Room, src, rcv, orient, pattern)
+    for directional receivers (as for ``simulate_polar``); outputs are
+    ``self.outs[i]`` with shape [n_src, n_rcv, nS] on ``device``.
     """
 
     def __init__(self, jobs, precision: str = "fp32", device: str = "cuda", check: bool = True, stream=None):
@@ -416,16 +418,25 @@ class BatchSimulator:
         self._keep = []
         self.outs = []
         arr = (_Job * len(jobs))()
-        host = [(_host_pos(src), _host_pos(rcv)) for _, src, rcv in jobs]
+        host = [(_host_pos(j[1]), _host_pos(j[2])) for j in jobs]
         if check:
-            for (room, _, _), (s, r) in zip(jobs, host):
-                check_positions(room, s, r)
+            for j, (s, r) in zip(jobs, host):
+                check_positions(j[0], s, r)
         # all positions of the batch in one device buffer (one host-to-device copy)
         pos = torch.from_numpy(np.concatenate([a for sr in host for a in sr], axis=0)).to(device)
         self._keep.append(pos)
         row = 0
-        for i, ((room, _, _), (s, r)) in enumerate(zip(jobs, host)):
+        for i, (job, (s, r)) in enumerate(zip(jobs, host)):
+            room = job[0]
             out = torch.empty((s.shape[0], r.shape[0], room.n_samples), dtype=torch.float32, device=device)
+            if len(job) == 5:
+                o = _host_pos(job[3])
+                if o.shape != r.shape:
+                    raise ValueError(f"orient must be [n_rcv, 3] = {r.shape}, got {o.shape}")
+                o_d = torch.from_numpy(o).to(device)
+                self._keep.append(o_d)
+                arr[i].orient = o_d.data_ptr()
+                arr[i].pattern = PATTERNS[job[4]] if isinstance(job[4], str) else float(job[4])
             self.outs.append(out)
             arr[i].room = room._c()
             arr[i].src, arr[i].n_src = pos[row:].data_ptr(), s.shape[0]

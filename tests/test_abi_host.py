@@ -192,6 +192,11 @@ def test_batch_checks_before_any_launch():
     jobs[1].out = None
     assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_E_INVALID_ARG
     jobs[1].out = fake
+    jobs[0].orient, jobs[0].pattern = fake, 1.5  # directional job with a pattern outside [0, 1]
+    assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_E_INVALID_ARG
+    jobs[0].pattern = 0.5
+    assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_OK
+    jobs[0].orient = None
     n_lut = ctypes.c_size_t()
     assert L.ism_batch_workspace_size(jobs, 2, ism.PRECISIONS["lut"], ctypes.byref(n_lut)) == ism.ISM_OK
     assert n_lut.value == n.value  # table taps plan like FP32

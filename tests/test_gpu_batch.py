@@ -88,6 +88,35 @@ def test_batch_table_taps_equal_single_calls(monkeypatch):
         assert torch.equal(o, single), f"batch differs from single-room call for {room.room}"
 
 
+def test_batch_directional_jobs_equal_single_calls(monkeypatch):
+    """A batch mixing directional and omnidirectional jobs: every job bitwise
+    equal to its own single call (ism_simulate_polar or ism_simulate), since
+    the omnidirectional jobs' pattern factor is exactly 1."""
+    import torch
+
+    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
+    jobs = _mixed_jobs()
+    rng = np.random.default_rng(11)
+    patterns = ["cardioid", None, "bidirectional", None, "hypercardioid"]
+    batch_jobs = []
+    for (room, src, rcv), pat in zip(jobs, patterns):
+        if pat is None:
+            batch_jobs.append((room, src, rcv))
+        else:
+            batch_jobs.append((room, src, rcv, rng.standard_normal((len(rcv), 3)).astype(np.float32), pat))
+    _say("mixed batch, directional jobs")
+    b = ism.BatchSimulator(batch_jobs)
+    outs = [o.clone() for o in b.run()]
+    torch.cuda.synchronize()
+    for job, o in zip(batch_jobs, outs):
+        if len(job) == 5:
+            single = ism.simulate_polar(job[0], job[1], job[2], job[3], job[4])
+        else:
+            single = ism.simulate(job[0], job[1], job[2])
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), f"batch differs from single-room call for {job[0].room}"
+
+
 def _feasible(oracle_mod):
     def ok(room, t60):
         try:
