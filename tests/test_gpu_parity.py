@@ -13,7 +13,7 @@ import pytest
 
 from paper_1810_11359_amd import ism, workloads
 
-from .helpers import oracle_room_args, rel_err
+from .helpers import assert_no_value_above_peak, oracle_peak, oracle_room_args, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -121,7 +121,9 @@ def test_large_room_uca_sampled_windows(oracle_mod):
     assert np.all(np.isfinite(got))
     pick = [0, 33]
     args = oracle_room_args(oracle_mod, w)
-    peak = np.max(np.abs(got[0, pick]), axis=-1)  # direct path lies in the first window
+    peak, _ = oracle_peak(oracle_mod, args, w.src, w.rcv[pick], room.n_samples)
+    peak = peak[0]
+    assert_no_value_above_peak(got[0, pick], peak, TOL_FP32)
     for k0, k1 in [(0, 1500), (47000, 48200), (94800, 96000)]:
         ref = oracle_mod.rir(*args, w.src, w.rcv[pick], k_begin=k0, k_end=k1)
         err = np.max(np.abs(got[0, pick, k0:k1] - ref[0]), axis=-1) / peak
@@ -190,7 +192,9 @@ def test_fp16_workloads_sampled(oracle_mod):
     _say("fp16 large_room_uca")
     got = _gpu_rir(room, w.src, w.rcv, "fp16")
     args = oracle_room_args(oracle_mod, w)
-    peak = np.max(np.abs(got[0, :1]), axis=-1)
+    peak, _ = oracle_peak(oracle_mod, args, w.src, w.rcv[:1], room.n_samples)
+    peak = peak[0]
+    assert_no_value_above_peak(got[0, :1], peak, TOL_FP16)
     for k0, k1 in [(0, 1500), (94800, 96000)]:
         ref = oracle_mod.rir(*args, w.src, w.rcv[:1], k_begin=k0, k_end=k1)
         err = np.max(np.abs(got[0, :1, k0:k1] - ref[0]), axis=-1) / peak

@@ -1,15 +1,15 @@
 """Pins of the diffuse-tail oracle (Sec. 2.2, Eq. (8); Sec. 3.3) on the CPU.
 
-The noise generator is pinned statistically (uniform, balanced, independent
-words; a single flipped counter bit changes about half of the output bits),
-the logistic transform by its moments and distribution function, the
-envelope by its closed form (-60 dB of power at t_diff + T60) and the level
-estimate by an input whose energy follows the envelope exactly. The exact
-bit stream of the generator is not pinned beyond these properties (no
-external known-answer values are used): parity unpinned for the stream
-itself, which the GPU test compares bit-exactly through the tail values.
+The noise generator is pinned bit for bit by the published Philox4x32-10
+known-answer vectors (tests/golden/philox4x32_10_kat.txt) and statistically
+(uniform, balanced, independent words; a single flipped counter bit changes
+about half of the output bits), the logistic transform by its moments and
+distribution function, the envelope by its closed form (-60 dB of power at
+t_diff + T60) and the level estimate by an input whose energy follows the
+envelope exactly.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -25,6 +25,54 @@ def orc(oracle_mod):
 
 def _words(orc, seed=11, rir=0, n=N_WORDS):
     return orc.noise_bits(seed, rir, np.arange(n)).astype(np.uint64)
+
+
+def _kat_vectors():
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].split()
+            if line:
+                rows.append([int(v, 16) for v in line])
+    assert len(rows) == 3 and all(len(r) == 10 for r in rows)
+    return rows
+
+
+def test_philox_known_answer_vectors(orc):
+    """The generator reproduces the published known-answer vectors of
+    Philox4x32-10 (Salmon et al., SC'11), word for word."""
+    for row in _kat_vectors():
+        ctr, key, expect = row[0:4], row[4:6], row[6:10]
+        got = orc.philox4x32_10([np.array([c], dtype=np.uint64) for c in ctr], key)
+        assert [int(g[0]) for g in got] == expect, (ctr, key, [hex(int(g[0])) for g in got])
+
+
+def test_philox_known_answer_vectors_catch_plausible_slips(orc):
+    """Plausible mistakes in a Philox implementation (high and low product
+    halves swapped, the key bumped before the first round, nine rounds) give
+    outputs that differ from the known answers."""
+    M, Wk, mask = (0xD2511F53, 0xCD9E8D57), (0x9E3779B9, 0xBB67AE85), 0xFFFFFFFF
+
+    def variant(ctr, key, swap=False, bump_first=False, rounds=10):
+        c = list(ctr)
+        k0, k1 = key
+        for r in range(rounds):
+            if r > 0 or bump_first:
+                k0, k1 = (k0 + Wk[0]) & mask, (k1 + Wk[1]) & mask
+            p0, p1 = M[0] * c[0], M[1] * c[2]
+            h0, l0, h1, l1 = p0 >> 32, p0 & mask, p1 >> 32, p1 & mask
+            if swap:
+                h0, l0, h1, l1 = l0, h0, l1, h1
+            c = [h1 ^ c[1] ^ k0, l1, h0 ^ c[3] ^ k1, l0]
+        return c
+
+    for row in _kat_vectors():
+        ctr, key, expect = row[0:4], row[4:6], row[6:10]
+        assert variant(ctr, key) == expect  # the plain definition, written out again
+        assert variant(ctr, key, swap=True) != expect
+        assert variant(ctr, key, bump_first=True) != expect
+        assert variant(ctr, key, rounds=9) != expect
 
 
 def test_philox_words_uniform_and_balanced(orc):
