@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the ISM hot path on one MI355X.
 
-One step = one ``ism_simulate`` call over the whole workload (host planning,
-axis tables, shell enumeration + windowed-sinc accumulation, ordered partial
-reduction), with positions, output and workspace already resident in HBM.
-Prints one JSON line: image-source sinc taps/s (G/s) with RIRs/s, the roofline
-of the tap-accumulation kernel (timed live with HIP events around each of its
-launches) and the FP64 CPU oracle's rate on a bounded sample of the same
-workload.
+Default run: the batch of 1024 independent rooms (sides U(3, 10) m, T60
+U(0.2, 1.0) s, per-wall jittered Sabine beta, 1-8 receivers, 16 kHz, T_w 4 ms),
+all RIRs in one prepared batch. One step = one ``ism_batch_run`` (axis tables,
+shell enumeration + windowed-sinc accumulation, ordered completion of the
+tiles) with positions, outputs and workspace already resident in HBM.
+
+The JSON line carries:
+  value / rirs_per_s   FP32 taps: image-source sinc taps/s (G/s) and RIRs/s;
+  roofline             the tap-accumulation kernel, timed live with HIP events
+                       around each of its launches, against the FP32 vector peak;
+  fp16                 the same batch with packed-FP16 taps: rate, speedup over
+                       FP32 on this GPU, max error against the FP64 oracle;
+  serving              a Poisson stream through the continuous-batching loop:
+                       RIRs/s with p50/p99 latency;
+  cpu_baseline         the FP64 oracle on a bounded sample of the same batch, on
+                       all usable host cores and on one core.
+Other workloads (``--workload``) print the single-leg line of that workload.
 """
 from __future__ import annotations
 
@@ -16,6 +26,7 @@ import ctypes
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,10 +39,13 @@ if ROOT not in sys.path:
 METRIC = "image-source sinc taps/s (G/s) + RIRs/s, FP32 vs FP16; p50/p99 serving latency"
 FLOP_PER_TAP = 18          # frozen accounting of one windowed-sinc tap
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 FLOP/clk)
+# Host threads the oracle may use: the machine's CPU share for one GPU.
+CPU_THREADS_MAX = 16
 # rocprofv3 summaries holding the calibrated HBM traffic of the timed kernel,
 # valid while the library bench.py loads hashes to the value recorded beside
 # it (the build is deterministic: edits that leave the code unchanged keep it)
-TRAFFIC_PROFILES = {"room_32_receivers": "profiles/accumulate_kernel_room_4x5x3_32rcv.md"}
+TRAFFIC_PROFILES = {"room_32_receivers": "profiles/accumulate_kernel_room_4x5x3_32rcv.md",
+                    "batch_rooms": "profiles/accumulate_batch_kernel_1024_rooms.md"}
 
 
 class _HipEvents:
@@ -94,6 +108,24 @@ def measured_traffic(workload: str, precision: str):
     return int(vals["traffic_bytes_per_launch"])
 
 
+def host_cpu():
+    """(usable threads for the oracle, nproc, CPU model name) of this host."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, min(usable, CPU_THREADS_MAX)), os.cpu_count() or 1, model
+
+
 def _oracle_args(orc, w):
     beta = orc.beta_from_t60(w.room, w.t60)
     if w.beta_jitter is not None:
@@ -102,50 +134,97 @@ def _oracle_args(orc, w):
     return (w.room, beta, n, w.c, w.fs, w.t_max, w.t_w)
 
 
-def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None, lut_q: int = 0):
-    """FP64 oracle on a bounded sample: the first ``n_rcv_sample`` receivers of a
-    single-room workload, or the first rooms of a batch up to that many RIRs.
-    With ``gpu_outs`` (host arrays [n_src, n_rcv, nS] per workload) it also
-    reports the largest max|h_gpu - h_oracle| / max|h_oracle| over the sample.
-    lut_q > 0: the oracle's table taps (Eq. (9)) at lut_q points per sample."""
-    from oracle import oracle as orc
-
-    orc.build()
-    jobs, left = [], n_rcv_sample
+def _sample_jobs(ws, n_rir: int):
+    """The first n_rir RIRs of the workloads: [(workload, receivers)] (one source each)."""
+    jobs, left = [], n_rir
     for w in ws:
         if left <= 0:
             break
         k = min(left, w.rcv.shape[0])
         jobs.append((w, w.rcv[:k]))
         left -= k
-    threads = max(1, min(os.cpu_count() or 1, 16, sum(r.shape[0] for _, r in jobs)))
-    taps = sum(orc.count_taps(*_oracle_args(orc, w), w.src, r) for w, r in jobs)
+    return jobs
+
+
+def _max_err(jobs, refs, outs):
+    """Largest per-RIR max|h_gpu - h_oracle| / max|h_oracle| over the sample."""
+    err = 0.0
+    for (w, r), ref, got in zip(jobs, refs, outs):
+        g = np.asarray(got, dtype=np.float64)[:, :r.shape[0], :]
+        peak = np.max(np.abs(ref), axis=-1)
+        err = max(err, float(np.max(np.max(np.abs(g - ref), axis=-1) / peak)))
+    return err
+
+
+def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None, lut_q: int = 0, one_core_taps: float = 1.5e8):
+    """FP64 oracle on a bounded sample: the first ``n_rcv_sample`` RIRs of the
+    workload(s), on all usable host threads (at most CPU_THREADS_MAX), then the
+    first RIRs of that sample holding at least ``one_core_taps`` taps on one
+    thread. ``gpu_outs``: {label: [host arrays [n_src, n_rcv, nS] per workload]};
+    for each label it reports the largest max|h_gpu - h_oracle| / max|h_oracle|
+    over the sample. lut_q > 0: the oracle's table taps (Eq. (9))."""
+    from oracle import oracle as orc
+
+    orc.build()
+    threads, nproc, model = host_cpu()
+    jobs = _sample_jobs(ws, n_rcv_sample)
+    n_rir = sum(r.shape[0] for _, r in jobs)
+    threads = min(threads, n_rir)
+    taps_per = [orc.count_taps(*_oracle_args(orc, w), w.src, r) for w, r in jobs]
+    taps = sum(taps_per)
     t0 = time.perf_counter()
     refs = [orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=min(threads, r.shape[0]), lut_q=lut_q)
             for w, r in jobs]
     dt = time.perf_counter() - t0
-    n = sum(r.shape[0] for _, r in jobs)
+    # one core: whole RIRs from the front of the sample
+    one_jobs, one_taps = [], 0
+    for (w, r) in jobs:
+        for i in range(r.shape[0]):
+            if one_taps >= one_core_taps:
+                break
+            t_i = orc.count_taps(*_oracle_args(orc, w), w.src, r[i:i + 1])
+            one_jobs.append((w, r[i:i + 1]))
+            one_taps += t_i
+    t1 = time.perf_counter()
+    for w, r in one_jobs:
+        orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=1, lut_q=lut_q)
+    dt1 = time.perf_counter() - t1
     out = {"value": taps / dt / 1e9, "unit": "G taps/s", "cores": threads, "kind": "oracle",
-           "sample": f"{n} full RIRs of the workload ({len(jobs)} room(s); {taps} taps, {dt:.2f} s wall, "
-                     f"up to {threads} threads)",
-           "rirs_per_s": n / dt}
-    if gpu_outs is not None:
-        err = 0.0
-        for (w, r), ref, got in zip(jobs, refs, gpu_outs):
-            g = np.asarray(got, dtype=np.float64)[:, :r.shape[0], :]
-            peak = np.max(np.abs(ref), axis=-1)
-            err = max(err, float(np.max(np.max(np.abs(g - ref), axis=-1) / peak)))
-        out["max_err_vs_oracle"] = err
-    return out
+           "sample": f"first {n_rir} full RIRs of the workload ({len(jobs)} room(s); {taps} taps, {dt:.2f} s wall "
+                     f"on {threads} threads); one core: first {len(one_jobs)} of them ({one_taps} taps, {dt1:.2f} s)",
+           "rirs_per_s": n_rir / dt, "value_1core": one_taps / dt1 / 1e9, "rirs_per_s_1core": len(one_jobs) / dt1,
+           "nproc": nproc, "cpu_model": model}
+    errs = {}
+    for label, outs in (gpu_outs or {}).items():
+        errs[label] = _max_err(jobs, refs, outs)
+    return out, errs
 
 
-def serve(args) -> int:
-    """Continuous-batching serving of a Poisson stream; prints RIRs/s with p50/p99 latency."""
+def _time_runs(sim, steps: int, warmup: int):
+    """Warm-up, then ``steps`` timed runs: (ms per whole step, per-run kernel ms list)."""
     import torch
 
-    from paper_1810_11359_amd import ism, workloads
-    from paper_1810_11359_amd.serving import GpuExecutor, Job, Scheduler, replay
+    hip = _HipEvents()
+    ev_a = [hip.create() for _ in range(steps)]
+    ev_b = [hip.create() for _ in range(steps)]
+    for _ in range(warmup):
+        sim.run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        sim.run(ev_start=ev_a[i], ev_stop=ev_b[i])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    kern_ms = [hip.elapsed_ms(a, b) for a, b in zip(ev_a, ev_b)]
+    for ev in ev_a + ev_b:
+        hip.destroy(ev)
+    return ms_total / steps, kern_ms
 
+
+def _feasible(ism):
     def feasible(room, t60):
         try:
             ism.beta_from_t60(room, t60)
@@ -153,25 +232,46 @@ def serve(args) -> int:
         except ism.IsmError:
             return False
 
-    reqs = workloads.serving_stream(rate=args.rate, n_jobs=args.jobs, seed=0, feasible=feasible)
+    return feasible
+
+
+def serving_leg(rate: float, n_jobs: int, count_taps: bool = False, n_slots: int = 4, budget: int = 64 << 30):
+    """Continuous-batching serving of a Poisson stream (mixed rooms, 16/48 kHz,
+    static arrays and moving-source trajectories): RIRs/s with p50/p99 latency."""
+    import torch
+
+    from paper_1810_11359_amd import ism, workloads
+    from paper_1810_11359_amd.serving import GpuExecutor, Job, Scheduler, replay
+
+    reqs = workloads.serving_stream(rate=rate, n_jobs=n_jobs, seed=0, feasible=_feasible(ism))
     jobs = [Job(i, ism.room_for(r.workload), r.workload.src, r.workload.rcv, r.arrival) for i, r in enumerate(reqs)]
     # exact tap counts cost host time proportional to the images of every job
-    taps = sum(ism.count_taps(j.room, j.src, j.rcv) for j in jobs) if args.count_taps else None
-    # warm-up: compile/load every kernel variant once
+    taps = sum(ism.count_taps(j.room, j.src, j.rcv) for j in jobs) if count_taps else None
+    # warm-up: load every kernel variant once
     warm = [Job(-1, j.room, j.src[:1], j.rcv[:1], 0.0) for j in jobs[:8]]
     replay(Scheduler(GpuExecutor(2), budget_bytes=8 << 30, n_slots=2), warm)
     torch.cuda.synchronize()
-    n_slots = 4
-    sch = Scheduler(GpuExecutor(n_slots), budget_bytes=64 << 30, n_slots=n_slots, max_batch_jobs=256)
+    sch = Scheduler(GpuExecutor(n_slots), budget_bytes=budget, n_slots=n_slots, max_batch_jobs=256)
     st = replay(sch, jobs)
     torch.cuda.synchronize()
-    out = {"metric": METRIC, "value": st.rirs_per_s, "unit": "RIRs/s", "n_gpus": 1, "steps": len(jobs),
-           "warmup": len(warm), "ms_per_step": st.makespan_s * 1e3 / len(jobs), "higher_is_better": True,
+    res = {"workload": f"serving_poisson_{rate:g}_jobs_per_s", "offered_jobs_per_s": rate, "n_jobs": len(jobs),
+           "slots": n_slots, "budget_bytes": budget, "warmup_jobs": len(warm)}
+    res.update(st.as_dict())
+    if taps is not None:
+        res["taps"] = int(taps)
+        res["taps_per_s"] = taps / st.makespan_s
+    return res
+
+
+def serve(args) -> int:
+    """Serving mode (--rate): one JSON line with the serving leg as the headline."""
+    s = serving_leg(args.rate, args.jobs, args.count_taps)
+    out = {"metric": METRIC, "value": s["rirs_per_s"], "unit": "RIRs/s", "n_gpus": 1, "steps": s["n_jobs"],
+           "warmup": s["warmup_jobs"], "ms_per_step": s["makespan_s"] * 1e3 / s["n_jobs"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-           "config": {"workload": f"serving_poisson_{args.rate:g}_jobs_per_s", "n_jobs": len(jobs),
-                      "n_rirs": st.n_rirs, "taps": None if taps is None else int(taps), "slots": n_slots,
-                      "budget_bytes": 64 << 30, "parallelism": "single GPU"},
-           "serving": st.as_dict(), "taps_per_s": None if taps is None else taps / st.makespan_s}
+           "config": {"workload": s["workload"], "n_jobs": s["n_jobs"], "n_rirs": s["n_rirs"], "slots": s["slots"],
+                      "budget_bytes": s["budget_bytes"], "parallelism": "single GPU"},
+           "serving": s}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -222,131 +322,167 @@ def bench_moving_source(args) -> int:
     return 0
 
 
+def calibrate_hbm(mib: int = 256) -> int:
+    """A plain device-to-device copy of known size (3 x ``mib`` MiB), run under
+    the rocprofv3 FETCH_SIZE / WRITE_SIZE passes to scale those counters."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_hbm": {"mib_per_copy": mib, "copies": 3}}), flush=True)
+    return 0
+
+
+def _roofline(taps: int, kern_ms, workload: str, precision: str, kernel: str):
+    kmean = float(np.mean(kern_ms))
+    achieved = FLOP_PER_TAP * taps / (kmean / 1e3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK, "traffic": measured_traffic(workload, precision),
+            "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": kernel, "kernel_ms_mean": kmean, "kernel_ms_p50": float(np.median(kern_ms)),
+            "flop_per_tap": FLOP_PER_TAP}
+
+
+def bench_batch(args) -> int:
+    """The default run: the 1024-room batch in FP32 (headline), the same batch in
+    packed FP16, a serving leg and the oracle baseline, in one JSON line."""
+    import torch
+
+    from paper_1810_11359_amd import ism, workloads
+
+    ws = workloads.batch_rooms(1024, seed=0, feasible=_feasible(ism))
+    rooms = [ism.room_for(w) for w in ws]
+    jobs = [(r, w.src, w.rcv) for r, w in zip(rooms, ws)]
+    taps = sum(ism.count_taps(r, w.src, w.rcv) for r, w in zip(rooms, ws))
+    sample = _sample_jobs(ws, args.cpu_sample)
+    n_rooms_sample = len(sample)
+
+    legs = {}
+    precisions = [args.precision] + (["fp16"] if args.precision == "fp32" and not args.no_fp16 else [])
+    for prec in precisions:
+        sim = ism.BatchSimulator(jobs, precision=prec)
+        ms_step, kern_ms = _time_runs(sim, args.steps, args.warmup)
+        legs[prec] = {"ms_per_step": ms_step, "kern_ms": kern_ms, "n_rir": sim.n_rirs,
+                      "outs": [o.cpu().numpy() for o in sim.outs[:n_rooms_sample]]}
+        del sim
+        torch.cuda.empty_cache()
+
+    head = legs[args.precision]
+    n_rir = head["n_rir"]
+    config = {"workload": f"batch_1024_rooms_{n_rir}_rirs", "n_rooms": len(ws), "n_rirs": n_rir, "fs": 16000.0,
+              "t_w_s": 0.004, "room_m": "U(3,10)^3", "t60_s": "U(0.2,1.0)", "taps_per_step": int(taps),
+              "parallelism": "single GPU"}
+    ms_step = head["ms_per_step"]
+    out = {"metric": METRIC, "value": taps / (ms_step / 1e3) / 1e9, "unit": "G taps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic", "config": config,
+           "rirs_per_s": n_rir / (ms_step / 1e3),
+           "roofline": _roofline(taps, head["kern_ms"], "batch_rooms", args.precision, "accumulate_batch_kernel")}
+    if "fp16" in legs and args.precision != "fp16":
+        h = legs["fp16"]
+        kmean = float(np.mean(h["kern_ms"]))
+        out["fp16"] = {"value": taps / (h["ms_per_step"] / 1e3) / 1e9, "unit": "G taps/s",
+                       "ms_per_step": h["ms_per_step"], "rirs_per_s": n_rir / (h["ms_per_step"] / 1e3),
+                       "speedup_vs_fp32": ms_step / h["ms_per_step"], "kernel_ms_mean": kmean,
+                       "kernel_speedup_vs_fp32": out["roofline"]["kernel_ms_mean"] / kmean,
+                       "taps_per_s_over_fp32_peak_at_18_flop": FLOP_PER_TAP * taps / (kmean / 1e3) / 1e12
+                       / FP32_VECTOR_PEAK}
+    if not args.no_serving:
+        out["serving"] = serving_leg(args.serving_rate, args.serving_jobs)
+    if not args.no_cpu_baseline:
+        base, errs = cpu_baseline(ws, args.cpu_sample, {k: v["outs"] for k, v in legs.items()},
+                                  lut_q=16 if args.precision == "lut" else 0)
+        out["cpu_baseline"] = base
+        out["max_err_vs_oracle"] = errs[args.precision]
+        if "fp16" in out:
+            out["fp16"]["max_err_vs_oracle"] = errs["fp16"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_single(args) -> int:
+    """A single-room workload: one ism_simulate (or ism_simulate_diffuse) per step."""
+    from paper_1810_11359_amd import ism, workloads
+
+    w = workloads.WORKLOADS[args.workload](0)
+    room = ism.room_for(w)
+    if w.t_diff > 0.0:
+        # ISM part up to t_diff, diffuse tail after it: taps are those of the ISM part
+        sim = ism.DiffuseSimulator(room, w.src, w.rcv, w.t_diff, w.t60, seed=0, precision=args.precision)
+        ism_room = ism.Room(room.room, room.beta, room.n_img, room.c, room.fs, w.t_diff, room.t_w)
+        taps = ism.count_taps(ism_room, w.src, w.rcv)
+    else:
+        sim = ism.Simulator(room, w.src, w.rcv, precision=args.precision)
+        taps = ism.count_taps(room, w.src, w.rcv)
+    n_rir = sim.n_src * sim.n_rcv
+    config = {"workload": w.name, "room_m": list(map(float, w.room)), "t60_s": w.t60, "fs": w.fs,
+              "t_w_s": w.t_w, "n_src": int(sim.n_src), "n_rcv": int(sim.n_rcv), "n_samples": room.n_samples,
+              "n_img": list(room.n_img), "taps_per_step": int(taps), "parallelism": "single GPU"}
+    if w.t_diff > 0.0:
+        config["t_diff_s"] = w.t_diff
+    ms_step, kern_ms = _time_runs(sim, args.steps, args.warmup)
+    out = {"metric": METRIC, "value": taps / (ms_step / 1e3) / 1e9, "unit": "G taps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic", "config": config,
+           "rirs_per_s": n_rir / (ms_step / 1e3),
+           "roofline": _roofline(taps, kern_ms, args.workload, args.precision, "accumulate_kernel")}
+    if not args.no_cpu_baseline and w.t_diff == 0.0:
+        base, errs = cpu_baseline([w], args.cpu_sample, {args.precision: [sim.out.cpu().numpy()]},
+                                  lut_q=16 if args.precision == "lut" else 0)
+        out["cpu_baseline"] = base
+        out["max_err_vs_oracle"] = errs[args.precision]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="room_32_receivers",
-                    choices=["room_32_receivers", "single_rir", "large_room_uca", "batch_rooms",
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch_rooms",
+                    choices=["batch_rooms", "room_32_receivers", "single_rir", "large_room_uca",
                              "paper_room_128rir", "paper_room_diffuse_1024rir", "moving_source_10s"])
-    ap.add_argument("--cpu-sample", type=int, default=16, help="receivers the CPU oracle baseline computes")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="RIRs the CPU oracle baseline computes (default 64 for the batch, 16 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "lut"],
                     help="tap arithmetic (accumulation is FP32 in all): FP32, packed FP16, or FP32 "
-                         "interpolation in a table of the windowed sinc (single-room workloads)")
+                         "interpolation in a table of the windowed sinc")
+    ap.add_argument("--no-fp16", action="store_true", help="batch: skip the packed-FP16 leg")
+    ap.add_argument("--no-serving", action="store_true", help="batch: skip the serving leg")
+    ap.add_argument("--serving-rate", type=float, default=1000.0, help="batch: serving leg offered jobs/s")
+    ap.add_argument("--serving-jobs", type=int, default=500, help="batch: serving leg jobs")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving mode: replay a Poisson stream of mixed RIR jobs at this many jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving mode: jobs in the stream")
     ap.add_argument("--count-taps", action="store_true", help="serving mode: also count the exact taps (slow)")
+    ap.add_argument("--calibrate-hbm", type=int, default=0, metavar="MIB",
+                    help="copy MIB MiB three times and exit (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the ISM path here does not "
               "shard across GPUs.", file=sys.stderr)
         return 2
-
     if args.precision == "lut" and args.rate > 0:
         print("the serving loop takes fp32 or fp16 taps, not table taps (--precision lut)", file=sys.stderr)
         return 2
-
-    import torch
-
-    from paper_1810_11359_amd import ism, workloads
-
+    if args.cpu_sample is None:
+        args.cpu_sample = 64 if args.workload == "batch_rooms" else 16
+    if args.calibrate_hbm > 0:
+        return calibrate_hbm(args.calibrate_hbm)
     if args.rate > 0:
         return serve(args)
     if args.workload == "moving_source_10s":
         return bench_moving_source(args)
     if args.workload == "batch_rooms":
-        def feasible(room, t60):
-            try:
-                ism.beta_from_t60(room, t60)
-                return True
-            except ism.IsmError:
-                return False
-
-        ws = workloads.batch_rooms(1024, seed=0, feasible=feasible)
-        rooms = [ism.room_for(w) for w in ws]
-        sim = ism.BatchSimulator([(r, w.src, w.rcv) for r, w in zip(rooms, ws)], precision=args.precision)
-        n_rir = sim.n_rirs
-        taps = sum(ism.count_taps(r, w.src, w.rcv) for r, w in zip(rooms, ws))
-        config = {"workload": f"batch_1024_rooms_{n_rir}_rirs", "n_rooms": len(ws), "n_rirs": n_rir, "fs": 16000.0,
-                  "t_w_s": 0.004, "room_m": "U(3,10)^3", "t60_s": "U(0.2,1.0)", "taps_per_step": int(taps),
-                  "parallelism": "single GPU"}
-    else:
-        w = workloads.WORKLOADS[args.workload](0)
-        ws = [w]
-        room = ism.room_for(w)
-        if w.t_diff > 0.0:
-            # ISM part up to t_diff, diffuse tail after it: taps are those of the ISM part
-            sim = ism.DiffuseSimulator(room, w.src, w.rcv, w.t_diff, w.t60, seed=0, precision=args.precision)
-            ism_room = ism.Room(room.room, room.beta, room.n_img, room.c, room.fs, w.t_diff, room.t_w)
-            taps = ism.count_taps(ism_room, w.src, w.rcv)
-        else:
-            sim = ism.Simulator(room, w.src, w.rcv, precision=args.precision)
-            taps = ism.count_taps(room, w.src, w.rcv)
-        n_rir = sim.n_src * sim.n_rcv
-        config = {"workload": w.name, "room_m": list(map(float, w.room)), "t60_s": w.t60, "fs": w.fs,
-                  "t_w_s": w.t_w, "n_src": int(sim.n_src), "n_rcv": int(sim.n_rcv), "n_samples": room.n_samples,
-                  "n_img": list(room.n_img), "taps_per_step": int(taps), "parallelism": "single GPU"}
-        if w.t_diff > 0.0:
-            config["t_diff_s"] = w.t_diff
-    hip = _HipEvents()
-    ev_a = [hip.create() for _ in range(args.steps)]
-    ev_b = [hip.create() for _ in range(args.steps)]
-
-    for _ in range(args.warmup):
-        sim.run()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    e0.record()
-    for i in range(args.steps):
-        sim.run(ev_start=ev_a[i], ev_stop=ev_b[i])
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = e0.elapsed_time(e1)
-    kern_ms = [hip.elapsed_ms(a, b) for a, b in zip(ev_a, ev_b)]
-    for ev in ev_a + ev_b:
-        hip.destroy(ev)
-
-    ms_step = ms_total / args.steps
-    value = taps / (ms_step / 1e3) / 1e9
-    kmean = float(np.mean(kern_ms))
-    achieved = FLOP_PER_TAP * taps / (kmean / 1e3) / 1e12
-    traffic = measured_traffic(args.workload, args.precision)
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "G taps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.precision,
-        "data": "synthetic",
-        "config": config,
-        "rirs_per_s": n_rir / (ms_step / 1e3),
-        "wall_s_timed": wall,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK, "traffic": traffic,
-                     "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "accumulate_kernel" if args.workload != "batch_rooms" else "accumulate_batch_kernel",
-                     "kernel_ms_mean": kmean,
-                     "kernel_ms_p50": float(np.median(kern_ms)), "flop_per_tap": FLOP_PER_TAP},
-    }
-    if not args.no_cpu_baseline and all(getattr(x, "t_diff", 0.0) == 0.0 for x in ws):
-        res = sim.outs if args.workload == "batch_rooms" else [sim.out]
-        gpu_outs = [o.cpu().numpy() for o in res[:args.cpu_sample]]
-        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_sample, gpu_outs, lut_q=16 if args.precision == "lut" else 0)
-        out["max_err_vs_oracle"] = out["cpu_baseline"].pop("max_err_vs_oracle")
-    print(json.dumps(out), flush=True)
-    return 0
+        return bench_batch(args)
+    return bench_single(args)
 
 
 if __name__ == "__main__":

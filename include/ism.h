@@ -113,23 +113,62 @@ int ism_check_positions(const ism_room *room, const float *src, int n_src, const
 int ism_count_taps(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
                    int64_t *taps_out);
 
+/* ---- Work schedule ------------------------------------------------------------------ */
+
+/* How a call splits its work into work items (units of the accumulation
+ * kernel: one RIR, one 256-sample output tile, one slab of the image shell
+ * that tile owns). The split changes the summation order, so results agree
+ * across schedules within rounding (<= 1e-6 of the RIR peak), not bitwise; a
+ * given schedule always gives the same bits. NULL means the tuned default. A
+ * field left at 0 (tail_rounds: < 0) keeps its default. Used by tuning and
+ * tests; the library reads no environment variables. */
+typedef struct {
+  double item_taps;     /* > 0: every work item holds about this many estimated taps,
+                           with no tail taper                                         */
+  double min_item_taps; /* > 0: smallest work item (replaces the tuned value)         */
+  double balance_items; /* > 0: items a large call is split into (replaces the tuned
+                           value; sets the item size of large calls)                  */
+  double tail_rounds;   /* single calls: the items dispatched once less than this many
+                           rounds of resident waves of work remain are cut smaller so
+                           the launch ends evenly; 0 = no taper, < 0 = default (1)    */
+} ism_schedule;
+
 /* ---- GPU simulation -------------------------------------------------------------- */
 
 /* Device workspace (bytes) that ism_simulate needs for this room, pair count
  * and precision. The size depends only on these arguments. */
 int ism_workspace_size(const ism_room *room, int n_src, int n_rcv, int precision, size_t *bytes);
 
-/* RIRs of every (source, receiver) pair of one room.
+/* RIRs of every (source, receiver) pair of one room: the problem statement of
+ * Sec. 4 (room, reflection coefficients, positions, fs, RIR length, window)
+ * with positions given in host memory.
+ *   src   host float32 [n_src][3], rcv host float32 [n_rcv][3] (positions [m]),
+ *         checked as by ism_check_positions before any launch (a position not
+ *         strictly inside the room -> ISM_E_OUT_OF_ROOM, a source equal to a
+ *         receiver -> ISM_E_INVALID_ARG) and copied into the workspace, so the
+ *         host arrays may be reused as soon as the call returns;
+ *   out   device float32 [n_src][n_rcv][nS], row-major, fully overwritten;
+ *   ws    device workspace of at least ism_workspace_size() bytes;
+ *   stream  hipStream_t or NULL.
+ * A call that fails any check returns its status and leaves out untouched.
+ * Kernels run asynchronously on stream; results are those of ism_simulate. */
+int ism_simulate_host(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                      int precision, float *out, void *ws, size_t ws_bytes, void *stream);
+
+/* RIRs of every (source, receiver) pair of one room, positions in device memory
+ * (an extension of ism_simulate_host for callers whose positions are already
+ * on the GPU).
  *   src   device float32 [n_src][3], rcv device float32 [n_rcv][3] (positions [m]);
  *   out   device float32 [n_src][n_rcv][nS], row-major, fully overwritten;
  *   ws    device workspace of at least ism_workspace_size() bytes (contents
  *         need not be initialised; overwritten);
  *   stream  hipStream_t or NULL.
- * Positions live on the device, so they are checked on the device: a pair whose
+ * Room, counts, precision and workspace are checked before any launch.
+ * Positions live on the device, so they are checked there: a pair whose
  * source or receiver is not strictly inside the room, or whose source equals
- * its receiver, gets an RIR filled with NaN (call ism_check_positions on a host
- * copy to get a status instead). The summation order is fixed, so repeated
- * calls with the same arguments give bitwise identical results.
+ * its receiver, gets an RIR filled with NaN (ism_simulate_host returns a
+ * status instead). The summation order is fixed, so repeated calls with the
+ * same arguments give bitwise identical results.
  * Asynchronous; out and ws must stay valid until the stream reaches it. */
 int ism_simulate(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
                  int precision, float *out, void *ws, size_t ws_bytes, void *stream);
@@ -142,6 +181,15 @@ int ism_simulate(const ism_room *room, const float *src, int n_src, const float 
 int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
                        int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
                        void *ev_stop);
+
+/* ism_simulate_timed with an explicit work schedule (see ism_schedule; NULL =
+ * default, the same as ism_simulate_timed). The workspace must hold
+ * ism_workspace_size_ex() bytes for the same schedule. */
+int ism_workspace_size_ex(const ism_room *room, int n_src, int n_rcv, int precision, const ism_schedule *sched,
+                          size_t *bytes);
+int ism_simulate_ex(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv, int precision,
+                    const ism_schedule *sched, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
+                    void *ev_stop);
 
 /* ism_simulate with directional receivers (the paper's library takes each
  * receiver's polar pattern and orientation, Sec. 4; it gives no formula).
@@ -257,7 +305,8 @@ typedef struct {
   uint64_t opaque[40];
 } ism_batch;
 
-/* Device workspace (bytes) for a batch of n_jobs jobs (host array). */
+/* Device workspace (bytes) for a batch of n_jobs jobs (host array), for
+ * ism_batch_prepare and for ism_simulate_batch. */
 int ism_batch_workspace_size(const ism_job *jobs, int n_jobs, int precision, size_t *bytes);
 
 /* Plans a batch on the host (every job checked as in ism_simulate; the first
@@ -273,12 +322,35 @@ int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, 
 
 /* Simulates every job of a prepared batch on stream: kernel launches only (no
  * host-device copies, no allocation), so it can be captured in a HIP graph and
- * replayed. Results are bitwise identical to ism_simulate of each job. */
+ * replayed. Each job is planned as a single call with tail_rounds = 0 (see
+ * ism_schedule): its result is bitwise identical to ism_simulate_ex of that
+ * job with that schedule, whatever the other jobs of the batch, and within
+ * rounding (<= 1e-6 of the RIR peak) of ism_simulate, whose default schedule
+ * tapers the tail of a single call. */
 int ism_batch_run(const ism_batch *batch, void *stream);
 
 /* ism_batch_run that also records the caller's HIP events ev_start before the
  * first and ev_stop after the last tap-accumulation launch (either may be NULL). */
 int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, void *ev_stop);
+
+/* ism_batch_workspace_size and ism_batch_prepare with an explicit work
+ * schedule for every job (tail_rounds is ignored: batches do not taper). */
+int ism_batch_workspace_size_ex(const ism_job *jobs, int n_jobs, int precision, const ism_schedule *sched,
+                                size_t *bytes);
+int ism_batch_prepare_ex(const ism_job *jobs, int n_jobs, int precision, const ism_schedule *sched, void *ws,
+                         size_t ws_bytes, void *stream, ism_batch *batch);
+
+/* Many rooms in one call, positions in host memory (the batched form of
+ * ism_simulate_host; Sec. 3 on rooms of uneven image counts). Here src, rcv
+ * and orient of each job are HOST float32 arrays ([n_src][3], [n_rcv][3],
+ * [n_rcv][3] or NULL); out stays a device array. Every job is checked as by
+ * ism_check_room / ism_check_positions (and its pattern) before any launch:
+ * the first failing job's status is returned and no output is touched. The
+ * positions are copied into ws with the batch tables (one host-to-device copy
+ * on stream, complete when the call returns), then the kernels of
+ * ism_batch_run are launched asynchronously. ws: ism_batch_workspace_size()
+ * bytes of the same jobs. Results are those of ism_batch_run. */
+int ism_simulate_batch(const ism_job *jobs, int n_jobs, int precision, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -7,9 +7,9 @@ the tap-accumulation kernel (HIP events the library records around it) on
 representative workloads over a grid of (min_item_taps, balance_items) pairs,
 keeps the pair with the best geometric-mean time relative to each workload's
 fastest pair, and writes the table header the host planner compiles in.
-Rebuild the library afterwards. The candidate values reach the planner
-through the ISM_ITEM_MIN_TAPS / ISM_ITEM_BALANCE environment variables,
-which it reads on every call.
+Rebuild the library afterwards. The candidate values reach the planner as
+the call's explicit schedule (``ism_schedule``: min_item_taps,
+balance_items).
 """
 from __future__ import annotations
 
@@ -76,15 +76,16 @@ def class_workloads(wt: int):
     raise ValueError(wt)
 
 
-def time_kernel(ws, precision: str, ev: _Events, reps: int) -> float:
+def time_kernel(ws, precision: str, ev: _Events, reps: int, schedule=None) -> float:
     """Mean accumulate-kernel time (ms) of one call over the workload(s)."""
     import torch
 
     if len(ws) == 1:
         w = ws[0]
-        sim = ism.Simulator(ism.room_for(w), w.src, w.rcv, precision=precision)
+        sim = ism.Simulator(ism.room_for(w), w.src, w.rcv, precision=precision, schedule=schedule)
     else:
-        sim = ism.BatchSimulator([(ism.room_for(w), w.src, w.rcv) for w in ws], precision=precision)
+        sim = ism.BatchSimulator([(ism.room_for(w), w.src, w.rcv) for w in ws], precision=precision,
+                                 schedule=schedule)
     sim.run()
     torch.cuda.synchronize()
     pairs = [ev.pair() for _ in range(reps)]
@@ -106,9 +107,8 @@ def tune(reps: int = 3, classes=(32, 64, 96, 128), precisions=("fp32", "fp16"), 
             times = {}
             for mt in MIN_TAPS:
                 for bal in BALANCE:
-                    os.environ["ISM_ITEM_MIN_TAPS"] = repr(mt)
-                    os.environ["ISM_ITEM_BALANCE"] = repr(bal)
-                    times[(mt, bal)] = [time_kernel(ws, prec, ev, reps) for _, ws in loads]
+                    sc = ism.Schedule(min_item_taps=mt, balance_items=bal)
+                    times[(mt, bal)] = [time_kernel(ws, prec, ev, reps, sc) for _, ws in loads]
                     log(f"W={wt} {prec} min_item_taps={mt:g} balance_items={bal:g}: "
                         + ", ".join(f"{name} {t:.3f} ms" for (name, _), t in zip(loads, times[(mt, bal)])))
             best_each = [min(t[i] for t in times.values()) for i in range(len(loads))]
@@ -117,8 +117,6 @@ def tune(reps: int = 3, classes=(32, 64, 96, 128), precisions=("fp32", "fp16"), 
             results[(wt, prec)] = (best, score, times, [n for n, _ in loads])
             log(f"W={wt} {prec}: best min_item_taps={best[0]:g} balance_items={best[1]:g} "
                 f"(score {score[best]:.4f}; default pair {score[(1.2e5, 49152.0)]:.4f})")
-    os.environ.pop("ISM_ITEM_MIN_TAPS", None)
-    os.environ.pop("ISM_ITEM_BALANCE", None)
     return results
 
 

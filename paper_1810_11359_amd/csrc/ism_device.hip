@@ -463,11 +463,14 @@ __device__ __forceinline__ ItemGeom item_geom(const RoomArgs &ra, const AxisRang
 // candidates in the batch, and on column lane c its first position excl and
 // its count cnt. The column gain in col_run is the product of the x and y
 // gain factors times gscale.
-template <bool POLAR, class Consume>
+// DUMP (enumeration check): col_xy receives each column's x and y table
+// indices, (x << 16) | y.
+template <bool POLAR, bool DUMP, class Consume>
 __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEntry *__restrict__ tx,
                                                 const AxisEntry *__restrict__ ty, const AxisRange &ay,
                                                 const AxisRange &az, const float gscale, EnumLds &es,
-                                                float *__restrict__ col_p, Consume &&consume) {
+                                                float *__restrict__ col_p, uint32_t *__restrict__ col_xy,
+                                                Consume &&consume) {
   const int lane = threadIdx.x & 63;
   for (int nx0 = g.nx_a; nx0 < g.nx_b; nx0 += 64) {
     // lanes = x indices: y range of the columns that reach the outer sphere
@@ -507,7 +510,9 @@ __device__ __forceinline__ void enumerate_shell(const ItemGeom &g, const AxisEnt
         const int i = max(xm - 1, 0);
         const uint32_t xc = es.nx_col[i];
         const AxisEntry ex = tx[nx0 + i];
-        const AxisEntry ey = ty[(int)(xc & 0x7ffu) + (gcol - (int)(xc >> 11))];
+        const int iy = (int)(xc & 0x7ffu) + (gcol - (int)(xc >> 11));
+        const AxisEntry ey = ty[iy];
+        if constexpr (DUMP) col_xy[lane] = ((uint32_t)(nx0 + i) << 16) | (uint32_t)iy;
         float sh, sl;
         two_sum(ex.sq_hi, ey.sq_hi, sh, sl);
         sl += ex.sq_lo + ey.sq_lo;
@@ -711,10 +716,14 @@ __device__ __forceinline__ void write_invalid(int n_own, float *__restrict__ dst
 // own LDS tile. dst receives the own samples of the tile (or a partial tile
 // when C > 1), marg the margins. HALF selects the FP16 tap arithmetic, LUT
 // the table taps; accumulation is FP32 in all modes.
-template <int WT, bool HALF, int NQ, bool LUT = false, bool POLAR = false>
+// DUMP: the enumeration check. No taps; every owned image is written to
+// dump->rec as a DumpRec of RIR rir (amplitude and fraction as the table
+// taps compute them).
+template <int WT, bool HALF, int NQ, bool LUT = false, bool POLAR = false, bool DUMP = false>
 __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                 const AxisEntry *__restrict__ tab, const AxisOrigin &org,
-                                                const bool valid, float *__restrict__ dst, float *__restrict__ marg) {
+                                                const bool valid, float *__restrict__ dst, float *__restrict__ marg,
+                                                const DumpArgs *dump = nullptr, const int rir = 0) {
   constexpr int LSPAN = TILE + WT - 1;
   constexpr int LPG = 64 / NQ;          // lanes per image
   constexpr int TPL = WT / LPG;         // taps per lane per step
@@ -730,12 +739,13 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   __shared__ Rec stp[SCAP];  // staged records (ImageParams::rec)
   __shared__ EnumLds es;
   __shared__ float col_p[POLAR ? 64 : 1];  // polar calls: column part of |d| cos(theta)
+  __shared__ uint32_t col_xy[DUMP ? 64 : 1];  // enumeration check: column table indices
 
   const int lane = threadIdx.x & 63;
   const int h = lane / LPG, l = lane % LPG;  // image group, lane within it
   const int n_own = min(TILE, ra.n_samples - tile_id * TILE);  // may be <= 0 past nS
   if (!valid) {
-    write_invalid<WT>(n_own, dst, marg, lane, 64);
+    if constexpr (!DUMP) write_invalid<WT>(n_own, dst, marg, lane, 64);
     return;
   }
   const AxisEntry *__restrict__ tx = tab + ra.off[0];
@@ -847,8 +857,8 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   auto rec = [&](int k) { return stp[k]; };
 
   int ns = 0;  // staged images (wave-uniform)
-  enumerate_shell<POLAR>(g, tx, ty, ay, az, column_gain_scale<NARROW>(ra), es, col_p, [&](int total, int excl,
-                                                                                        int cnt) {
+  enumerate_shell<POLAR, DUMP>(g, tx, ty, ay, az, column_gain_scale<NARROW || DUMP>(ra), es, col_p, col_xy,
+                               [&](int total, int excl, int cnt) {
     // Chunks of 64 candidate positions; lane i takes position q0 + i. Its
     // column is the last one starting at or before it: each column marks its
     // first position in the chunk, a running maximum over the lanes carries
@@ -879,9 +889,35 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       const int cl_c = cl;
       const float cg_c = cg;
       const AxisEntry ez_c = ez;
+      const int nz_c = nz;
       if (q + 64 < total) {
         locate(q + 64, cl, nz, cg);
         if (q + 64 + lane < total) ez = tz[nz];
+      }
+      if constexpr (DUMP) {
+        // delay and amplitude exactly as the table taps compute them
+        ImageParams<true> p;
+        p.ok = false;
+        if (q + lane < total) p = image_params<WT, false, true, POLAR>(ra, g, es.col_s[cl_c], cg_c, ez_c, 0.0f);
+        const uint64_t okm = __ballot(p.ok);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
+        uint32_t first = 0;
+        if (lane == 0 && okm != 0) first = atomicAdd(dump->count, (uint32_t)__builtin_popcountll(okm));
+        first = (uint32_t)__builtin_amdgcn_readlane((int)first, 0);
+        if (p.ok && first + (uint32_t)rank < dump->cap) {
+          const uint32_t xy = col_xy[cl_c];
+          const int idx[3] = {(int)(xy >> 16), (int)(xy & 0xffffu), nz_c};
+          DumpRec d;
+          d.rir = rir;
+          for (int k = 0; k < 3; ++k) d.n[ra.perm[k]] = ra.lo[k] + idx[k];
+          d.k0 = g.T0 + p.base;
+          d.fq = __float_as_uint(p.rec.x) >> 8;
+          d.A = p.rec.y;
+          d.pad = 0;
+          dump->rec[first + (uint32_t)rank] = d;
+        }
+        wave_sync();
+        continue;
       }
       // lanes = candidates: parameters, then compaction into the stage
       ImageParams<NARROW> p;
@@ -921,6 +957,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       wave_sync();
     }
   });
+  if constexpr (DUMP) return;
   if (h < ns) step(stp[h]);  // last images, fewer than NQ
 
   wave_sync();
@@ -934,14 +971,13 @@ __device__ __forceinline__ uint32_t plan_first_item(const PlanArgs &pa, int pos)
   return f;
 }
 
-// Single-room launch: the item index decodes through the per-tile chunk counts.
-template <int WT, bool HALF, int NQ, bool LUT, bool POLAR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
-                                                             const AxisEntry *__restrict__ tab_all,
-                                                             const AxisOrigin *__restrict__ origin,
-                                                             const int *__restrict__ valid, float *__restrict__ out,
-                                                             float *__restrict__ part, float *__restrict__ marg) {
-  const uint32_t item = blockIdx.x;
+// Work item of a single-room launch: the item index decodes through the
+// per-tile chunk counts.
+struct SingleItem {
+  int pos, tile_id, C, rir, c;
+  uint32_t first;  // first item of the dispatch position
+};
+__device__ __forceinline__ SingleItem decode_item(const PlanArgs &pa, uint32_t item) {
   // largest dispatch position pos whose first item is <= item: the block by
   // binary search over first_blk, then the position within the block
   const int nblk = (pa.n_tiles + PLAN_BLK - 1) / PLAN_BLK;
@@ -960,21 +996,53 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void ac
     first = next;
     ++pos;
   }
-  const int tile_id = pa.n_tiles - 1 - pos;
-  const int C = pa.chunks[tile_id];
+  SingleItem si;
+  si.pos = pos;
+  si.first = first;
+  si.tile_id = pa.n_tiles - 1 - pos;
+  si.C = pa.chunks[si.tile_id];
   const uint32_t rel = item - first;
-  const int rir = (int)(rel / (uint32_t)C);
-  const int c = (int)(rel % (uint32_t)C);
+  si.rir = (int)(rel / (uint32_t)si.C);
+  si.c = (int)(rel % (uint32_t)si.C);
+  return si;
+}
+
+template <int WT, bool HALF, int NQ, bool LUT, bool POLAR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAccWavesPerSimd))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
+                                                             const AxisEntry *__restrict__ tab_all,
+                                                             const AxisOrigin *__restrict__ origin,
+                                                             const int *__restrict__ valid, float *__restrict__ out,
+                                                             float *__restrict__ part, float *__restrict__ marg) {
+  const uint32_t item = blockIdx.x;
+  const SingleItem si = decode_item(pa, item);
   // (for a tile past nS, dst is never written: the tile has no own samples)
-  float *dst = (C == 1) ? out + (size_t)rir * ra.n_samples + (size_t)tile_id * TILE : part + (size_t)item * TILE;
-  const AxisOrigin org = origin[rir];
-  accumulate_item<WT, HALF, NQ, LUT, POLAR>(ra, tile_id, C, c, tab_all + (size_t)rir * ra.n_tab, org,
-                                            valid[rir] != 0, dst, marg + (size_t)item * WT);
+  float *dst = (si.C == 1) ? out + (size_t)si.rir * ra.n_samples + (size_t)si.tile_id * TILE
+                           : part + (size_t)item * TILE;
+  const AxisOrigin org = origin[si.rir];
+  accumulate_item<WT, HALF, NQ, LUT, POLAR>(ra, si.tile_id, si.C, si.c, tab_all + (size_t)si.rir * ra.n_tab, org,
+                                            valid[si.rir] != 0, dst, marg + (size_t)item * WT);
+}
+
+// Enumeration check: the items of a single-room launch, images only.
+template <int WT>
+__global__ __launch_bounds__(64) void enumerate_dump_kernel(RoomArgs ra, PlanArgs pa,
+                                                            const AxisEntry *__restrict__ tab_all,
+                                                            const AxisOrigin *__restrict__ origin,
+                                                            const int *__restrict__ valid, DumpArgs dump) {
+  const SingleItem si = decode_item(pa, blockIdx.x);
+  const AxisOrigin org = origin[si.rir];
+  accumulate_item<WT, false, 2, false, false, true>(ra, si.tile_id, si.C, si.c, tab_all + (size_t)si.rir * ra.n_tab,
+                                                    org, valid[si.rir] != 0, nullptr, nullptr, &dump, si.rir);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // Batch launch: every item names its job; the job table carries the room.
 template <int WT, bool HALF, int NQ, bool LUT, bool POLAR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAccWavesPerSimd))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
                                                                    const BatchItem *__restrict__ items,
                                                                    const AxisEntry *__restrict__ tab_all,
                                                                    const AxisOrigin *__restrict__ origin,
@@ -1103,6 +1171,20 @@ static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items
                         hipStream_t st) {
   hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR>), dim3(n_items), dim3(64),
                      0, st, ra, pa, tab, origin, valid, out, part, marg);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_dump(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
+                const AxisOrigin *origin, const int *valid, DumpArgs dump, hipStream_t st) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, dump.count, 0u, 1);
+  if (hipGetLastError() != hipSuccess) return -1;
+  switch (wt) {
+    case 32: hipLaunchKernelGGL(enumerate_dump_kernel<32>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    case 64: hipLaunchKernelGGL(enumerate_dump_kernel<64>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    case 96: hipLaunchKernelGGL(enumerate_dump_kernel<96>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    case 128: hipLaunchKernelGGL(enumerate_dump_kernel<128>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    default: return -2;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "ism.h"
+#include "ism_debug.h"
 #include "ism_internal.h"
 #include "ism_tuning.h"
 
@@ -24,6 +25,8 @@ int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &r
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, const float *marg,
                   float *out, hipStream_t st);
 bool supported_window(int wt);
+int launch_dump(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
+                const AxisOrigin *origin, const int *valid, DumpArgs dump, hipStream_t st);
 int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
                  const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
                  bool half, bool lut, bool polar, const BatchReduce *red, uint32_t n_red, AxisEntry *tab,
@@ -75,48 +78,50 @@ struct Plan {
   int n_rir;
   uint32_t n_items;
   bool any_split;
-  size_t off_valid, off_origin, off_tab, off_part, off_marg, ws_bytes;
+  size_t off_valid, off_origin, off_tab, off_part, off_marg, off_pos, ws_bytes;
 };
 
 // Work-item size in estimated taps. A launch should hold about balance_items
 // items (some eight per resident wave) so that the largest-first order keeps
 // every CU busy to the end; small calls keep items of min_item_taps. Both come
-// from the tuning table (ism_tuning.h) for the window and precision. The
-// environment variables ISM_TARGET_TAPS (a fixed size; tests use it to change
-// the split), ISM_ITEM_MIN_TAPS and ISM_ITEM_BALANCE (used by the tuner)
-// override them.
+// from the tuning table (ism_tuning.h) for the window and precision unless the
+// call's schedule (ism_schedule) replaces them.
 constexpr double kMinItemTaps = 1.2e5;
 constexpr double kBalanceItems = 49152.0;
-double item_target(double total_taps, int wt, bool half) {
-  if (const char *e = std::getenv("ISM_TARGET_TAPS")) return std::max(1e3, std::atof(e));
+double item_target(double total_taps, int wt, bool half, const ism_schedule *sc) {
   double min_taps = kMinItemTaps, balance = kBalanceItems;
   for (const ItemTuning &t : kItemTuning)
     if (t.wt == wt && t.half == (half ? 1 : 0)) {
       min_taps = t.min_item_taps;
       balance = t.balance_items;
     }
-  if (const char *e = std::getenv("ISM_ITEM_MIN_TAPS")) min_taps = std::max(1e3, std::atof(e));
-  if (const char *e = std::getenv("ISM_ITEM_BALANCE")) balance = std::max(1.0, std::atof(e));
+  if (sc && sc->min_item_taps > 0.0) min_taps = std::max(1e3, sc->min_item_taps);
+  if (sc && sc->balance_items > 0.0) balance = std::max(1.0, sc->balance_items);
   return std::max(min_taps, total_taps / balance);
 }
 
 // Waves of the accumulate kernel resident on the device at once (256 CUs x
-// 4 SIMDs x 6), and the rounds of them over which the tail is tapered
-// (ISM_TAIL_ROUNDS overrides; 0 disables the taper).
-constexpr double kResidentWaves = 256.0 * 4.0 * 6.0;
+// 4 SIMDs x the waves per SIMD the kernel is built for), and the default
+// rounds of them over which a single call tapers its tail.
+constexpr double kResidentWaves = 256.0 * 4.0 * kAccWavesPerSimd;
 constexpr double kTailRounds = 1.0;
-double tail_taper_rounds() {
-  if (const char *e = std::getenv("ISM_TAIL_ROUNDS")) return std::max(0.0, std::atof(e));
-  return kTailRounds;
+
+bool valid_schedule(const ism_schedule *sc) {
+  if (!sc) return true;
+  const double v[4] = {sc->item_taps, sc->min_item_taps, sc->balance_items, sc->tail_rounds};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return sc->item_taps >= 0.0 && sc->min_item_taps >= 0.0 && sc->balance_items >= 0.0;
 }
 
-// target <= 0: item size chosen from this call's own estimated work.
+// sched: the call's schedule (null = the tuned default).
 // taper: cut the items dispatched last (single calls; a batch's tail is the
 // largest-first order over all its jobs' items instead).
-int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, double target = 0.0,
+int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, const ism_schedule *sched = nullptr,
               bool taper = true) {
   int st = ism_check_room(r);
   if (st != ISM_OK) return st;
+  if (!valid_schedule(sched)) return ISM_E_INVALID_ARG;
   if (n_src < 1 || n_rcv < 1) return ISM_E_INVALID_ARG;
   if ((int64_t)n_src * n_rcv > ISM_MAX_PAIRS) return ISM_E_TOO_LARGE;
   if (precision != ISM_FP32 && precision != ISM_FP16 && precision != ISM_FP32_LUT)
@@ -175,15 +180,16 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, d
     p.tile_taps[t] = imgs * W;
     p.total_taps += p.tile_taps[t] * p.n_rir;
   }
-  // an explicit item size (argument or ISM_TARGET_TAPS) is used as given
-  const bool fixed = target > 0.0 || std::getenv("ISM_TARGET_TAPS") != nullptr;
-  if (!fixed) target = item_target(p.total_taps, p.wt, p.half);
+  // an explicit item size is used as given
+  const bool fixed = sched && sched->item_taps > 0.0;
+  const double target = fixed ? std::max(1e3, sched->item_taps) : item_target(p.total_taps, p.wt, p.half, sched);
   // Tail taper: tiles are dispatched last first, and the items of a tile
   // dispatched when the work left (this tile included) is below tail_rounds
   // rounds of the resident waves are cut to that work over tail_rounds x the
   // resident waves, down to target / 8, so the last waves of a launch finish
   // close together instead of one full-size item after another.
-  const double tail_rounds = (fixed || !taper) ? 0.0 : tail_taper_rounds();
+  const double tail_rounds =
+      (fixed || !taper) ? 0.0 : (sched && sched->tail_rounds >= 0.0 ? sched->tail_rounds : kTailRounds);
   p.any_split = false;
   double rem = p.total_taps;
   for (int pos = 0; pos < pa.n_tiles; ++pos) {
@@ -211,7 +217,9 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, d
   p.off_tab = align_up(p.off_origin + sizeof(AxisOrigin) * (size_t)p.n_rir);
   p.off_part = align_up(p.off_tab + sizeof(AxisEntry) * (size_t)p.n_rir * ra.n_tab);
   p.off_marg = align_up(p.off_part + (p.any_split ? sizeof(float) * (size_t)p.n_items * TILE : 0));
-  p.ws_bytes = p.off_marg + sizeof(float) * (size_t)p.n_items * p.wt;
+  // host-position calls copy src then rcv here
+  p.off_pos = align_up(p.off_marg + sizeof(float) * (size_t)p.n_items * p.wt);
+  p.ws_bytes = align_up(p.off_pos + sizeof(float) * 3 * ((size_t)n_src + (size_t)n_rcv));
   return ISM_OK;
 }
 
@@ -360,18 +368,24 @@ int ism_count_taps(const ism_room *room, const float *src, int n_src, const floa
   return ISM_OK;
 }
 
-int ism_workspace_size(const ism_room *room, int n_src, int n_rcv, int precision, size_t *bytes) {
+int ism_workspace_size_ex(const ism_room *room, int n_src, int n_rcv, int precision, const ism_schedule *sched,
+                          size_t *bytes) {
   if (!bytes) return ISM_E_INVALID_ARG;
   Plan p;
-  const int st = make_plan(room, n_src, n_rcv, precision, p);
+  const int st = make_plan(room, n_src, n_rcv, precision, p, sched);
   if (st != ISM_OK) return st;
   *bytes = p.ws_bytes;
   return ISM_OK;
 }
 
+int ism_workspace_size(const ism_room *room, int n_src, int n_rcv, int precision, size_t *bytes) {
+  return ism_workspace_size_ex(room, n_src, n_rcv, precision, nullptr, bytes);
+}
+
 int ism_simulate(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv, int precision,
                  float *out, void *ws, size_t ws_bytes, void *stream) {
-  return ism_simulate_timed(room, src, n_src, rcv, n_rcv, precision, out, ws, ws_bytes, stream, nullptr, nullptr);
+  return ism_simulate_ex(room, src, n_src, rcv, n_rcv, precision, nullptr, out, ws, ws_bytes, stream, nullptr,
+                         nullptr);
 }
 
 // Launches the ISM kernels of a plan: tables, taps, completion of the tiles.
@@ -399,15 +413,61 @@ static int run_plan(const Plan &p, const float *src, const float *rcv, float *ou
   return ISM_OK;
 }
 
-int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
-                       int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
-                       void *ev_stop) {
+int ism_simulate_ex(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv, int precision,
+                    const ism_schedule *sched, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
+                    void *ev_stop) {
   Plan p;
-  const int st = make_plan(room, n_src, n_rcv, precision, p);
+  const int st = make_plan(room, n_src, n_rcv, precision, p, sched);
   if (st != ISM_OK) return st;
   if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
   if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
   return run_plan(p, src, rcv, out, ws, stream, ev_start, ev_stop);
+}
+
+int ism_simulate_timed(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                       int precision, float *out, void *ws, size_t ws_bytes, void *stream, void *ev_start,
+                       void *ev_stop) {
+  return ism_simulate_ex(room, src, n_src, rcv, n_rcv, precision, nullptr, out, ws, ws_bytes, stream, ev_start,
+                         ev_stop);
+}
+
+int ism_simulate_host(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                      int precision, float *out, void *ws, size_t ws_bytes, void *stream) {
+  Plan p;
+  int st = make_plan(room, n_src, n_rcv, precision, p);
+  if (st != ISM_OK) return st;
+  if (!src || !rcv || !out) return ISM_E_INVALID_ARG;
+  st = ism_check_positions(room, src, n_src, rcv, n_rcv);
+  if (st != ISM_OK) return st;
+  if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
+  // positions into the workspace: pageable host memory, so the call returns
+  // once the host arrays have been read
+  hipStream_t s = (hipStream_t)stream;
+  float *pos = (float *)((char *)ws + p.off_pos);
+  if (hipMemcpyAsync(pos, src, sizeof(float) * 3 * (size_t)n_src, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(pos + 3 * (size_t)n_src, rcv, sizeof(float) * 3 * (size_t)n_rcv, hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return ISM_E_DEVICE;
+  return run_plan(p, pos, pos + 3 * (size_t)n_src, out, ws, stream, nullptr, nullptr);
+}
+
+int ism_debug_enumerate(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                        const ism_schedule *sched, void *records, uint32_t cap, uint32_t *count, void *ws,
+                        size_t ws_bytes, void *stream) {
+  Plan p;
+  const int st = make_plan(room, n_src, n_rcv, ISM_FP32, p, sched);
+  if (st != ISM_OK) return st;
+  if (!src || !rcv || !count || (cap > 0 && !records)) return ISM_E_INVALID_ARG;
+  if (!ws || ws_bytes < p.ws_bytes) return ISM_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  int *valid = (int *)(w + p.off_valid);
+  AxisOrigin *origin = (AxisOrigin *)(w + p.off_origin);
+  AxisEntry *tab = (AxisEntry *)(w + p.off_tab);
+  if (launch_tables(p.ra, src, rcv, nullptr, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
+  DumpArgs d{(DumpRec *)records, count, cap};
+  if (launch_dump(p.wt, p.ra, p.pa, p.n_items, tab, origin, valid, d, s) != 0) return ISM_E_DEVICE;
+  return ISM_OK;
 }
 
 int ism_simulate_polar(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
@@ -514,7 +574,7 @@ constexpr int kMaxClasses = 4;
 
 struct BatchState {  // stored in ism_batch::opaque
   uint64_t ws;
-  uint64_t off_jobs, off_rirs, off_items, off_red, off_valid, off_origin, off_tab, off_part, off_marg;
+  uint64_t off_jobs, off_rirs, off_items, off_red, off_pos, off_valid, off_origin, off_tab, off_part, off_marg;
   uint32_t n_rir, n_red, n_classes, mode;  // mode: 0 FP32, 1 FP16, 2 table taps
   uint32_t polar, pad;                      // 1: directional kernels
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
@@ -527,6 +587,7 @@ struct BatchPlan {
   std::vector<BatchRir> rirs;
   std::vector<BatchItem> items;
   std::vector<BatchReduce> red;
+  std::vector<size_t> pos_off;  // per job: offset (floats) of its src, rcv, orient in the position area
   BatchState st;
   size_t ws_bytes;
 };
@@ -543,7 +604,8 @@ int cost_bucket(double cost) {
 // Plans a batch. With fill == false only the counts and the workspace layout
 // are computed (ism_batch_workspace_size); with fill == true the job, RIR,
 // item and reduce tables are built as well (ism_batch_prepare).
-int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bool fill) {
+int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedule *sched, BatchPlan &bp,
+               bool fill) {
   if (!jobs || n_jobs < 1) return ISM_E_INVALID_ARG;
   std::memset(&bp.st, 0, sizeof(bp.st));
   // Each job is planned as a single call would plan it without the tail
@@ -569,7 +631,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
   std::vector<uint64_t> bucket_count((size_t)kMaxClasses * kCostBuckets, 0);
   for (int j = 0; j < n_jobs; ++j) {
     Plan &p = plans[j];
-    const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, 0.0, false);
+    const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, sched, false);
     if (stt != ISM_OK) return stt;
     int cls = -1;
     for (int k = 0; k < n_classes; ++k)
@@ -618,6 +680,15 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
   o = align_up(o + sizeof(BatchItem) * (size_t)n_items);
   bp.st.off_red = o;
   o = align_up(o + sizeof(BatchReduce) * (size_t)n_red);
+  // positions of every job (ism_simulate_batch copies host positions here)
+  bp.st.off_pos = o;
+  bp.pos_off.resize(n_jobs);
+  size_t pos_floats = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    bp.pos_off[j] = pos_floats;
+    pos_floats += 3 * ((size_t)jobs[j].n_src + (size_t)jobs[j].n_rcv * (jobs[j].orient ? 2 : 1));
+  }
+  o = align_up(o + sizeof(float) * pos_floats);
   bp.st.off_valid = o;
   o = align_up(o + sizeof(int) * n_rir);
   bp.st.off_origin = o;
@@ -696,26 +767,67 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, BatchPlan &bp, bo
 
 }  // namespace
 
-int ism_batch_workspace_size(const ism_job *jobs, int n_jobs, int precision, size_t *bytes) {
+int ism_batch_workspace_size_ex(const ism_job *jobs, int n_jobs, int precision, const ism_schedule *sched,
+                                size_t *bytes) {
   if (!bytes) return ISM_E_INVALID_ARG;
   BatchPlan bp;
-  const int st = plan_batch(jobs, n_jobs, precision, bp, false);
+  const int st = plan_batch(jobs, n_jobs, precision, sched, bp, false);
   if (st != ISM_OK) return st;
   *bytes = bp.ws_bytes;
   return ISM_OK;
 }
 
-int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, size_t ws_bytes, void *stream,
-                      ism_batch *batch) {
+int ism_batch_workspace_size(const ism_job *jobs, int n_jobs, int precision, size_t *bytes) {
+  return ism_batch_workspace_size_ex(jobs, n_jobs, precision, nullptr, bytes);
+}
+
+namespace {
+// Plans a batch and uploads its tables (and, with host_pos, the jobs' host
+// positions) into ws with one host-to-device copy on stream.
+int prepare_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedule *sched, void *ws,
+                  size_t ws_bytes, void *stream, bool host_pos, ism_batch *batch) {
   if (!batch) return ISM_E_INVALID_ARG;
   BatchPlan bp;
-  const int st = plan_batch(jobs, n_jobs, precision, bp, true);
+  int st = plan_batch(jobs, n_jobs, precision, sched, bp, true);
   if (st != ISM_OK) return st;
+  if (host_pos) {
+    for (int j = 0; j < n_jobs; ++j) {
+      st = ism_check_positions(&jobs[j].room, jobs[j].src, jobs[j].n_src, jobs[j].rcv, jobs[j].n_rcv);
+      if (st != ISM_OK) return st;
+      if (jobs[j].orient)
+        for (int i = 0; i < jobs[j].n_rcv; ++i) {
+          const float *o = jobs[j].orient + 3 * i;
+          if (!(std::isfinite(o[0]) && std::isfinite(o[1]) && std::isfinite(o[2])) ||
+              (o[0] == 0.0f && o[1] == 0.0f && o[2] == 0.0f))
+            return ISM_E_INVALID_ARG;
+        }
+    }
+  }
   if (!ws || ws_bytes < bp.ws_bytes) return ISM_E_WORKSPACE;
   // one contiguous host image of the metadata, copied with a single transfer
   // (alignment gaps between the tables are left uninitialised)
   std::unique_ptr<char[]> host_buf(new char[bp.st.off_valid]);
   char *const host = host_buf.get();
+  if (host_pos) {
+    // the jobs' device view points into the position area of ws
+    float *dpos = (float *)((char *)ws + bp.st.off_pos);
+    float *hpos = (float *)(host + bp.st.off_pos);
+    for (int j = 0; j < n_jobs; ++j) {
+      const ism_job &jb = jobs[j];
+      JobDev &d = bp.jobs[j];
+      size_t o = bp.pos_off[j];
+      std::memcpy(hpos + o, jb.src, sizeof(float) * 3 * (size_t)jb.n_src);
+      d.src = dpos + o;
+      o += 3 * (size_t)jb.n_src;
+      std::memcpy(hpos + o, jb.rcv, sizeof(float) * 3 * (size_t)jb.n_rcv);
+      d.rcv = dpos + o;
+      o += 3 * (size_t)jb.n_rcv;
+      if (jb.orient) {
+        std::memcpy(hpos + o, jb.orient, sizeof(float) * 3 * (size_t)jb.n_rcv);
+        d.orient = dpos + o;
+      }
+    }
+  }
   std::memcpy(host + bp.st.off_jobs, bp.jobs.data(), sizeof(JobDev) * bp.jobs.size());
   std::memcpy(host + bp.st.off_rirs, bp.rirs.data(), sizeof(BatchRir) * bp.rirs.size());
   std::memcpy(host + bp.st.off_items, bp.items.data(), sizeof(BatchItem) * bp.items.size());
@@ -727,6 +839,24 @@ int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, 
   std::memset(batch, 0, sizeof(*batch));
   std::memcpy(batch, &bp.st, sizeof(bp.st));
   return ISM_OK;
+}
+}  // namespace
+
+int ism_batch_prepare_ex(const ism_job *jobs, int n_jobs, int precision, const ism_schedule *sched, void *ws,
+                         size_t ws_bytes, void *stream, ism_batch *batch) {
+  return prepare_batch(jobs, n_jobs, precision, sched, ws, ws_bytes, stream, false, batch);
+}
+
+int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, size_t ws_bytes, void *stream,
+                      ism_batch *batch) {
+  return prepare_batch(jobs, n_jobs, precision, nullptr, ws, ws_bytes, stream, false, batch);
+}
+
+int ism_simulate_batch(const ism_job *jobs, int n_jobs, int precision, void *ws, size_t ws_bytes, void *stream) {
+  ism_batch b;
+  const int st = prepare_batch(jobs, n_jobs, precision, nullptr, ws, ws_bytes, stream, true, &b);
+  if (st != ISM_OK) return st;
+  return ism_batch_run(&b, stream);
 }
 
 int ism_batch_run(const ism_batch *batch, void *stream) { return ism_batch_run_timed(batch, stream, nullptr, nullptr); }

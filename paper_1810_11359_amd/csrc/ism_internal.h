@@ -19,6 +19,9 @@ constexpr int PLAN_BLK = 16;
 constexpr int MARG_STRIDE = 128;
 // Work items per tile are capped so the per-tile chunk count fits a byte.
 constexpr int MAX_CHUNKS = 255;
+// Waves per SIMD the accumulate kernels are built for (their LDS and VGPR
+// budget); the planner sizes the tail taper of a launch with it.
+constexpr int kAccWavesPerSimd = 7;
 
 // Per-call room constants, passed by value as a kernel argument. Lengths are in
 // metres, delays in samples. Float-float pairs (hi, lo) carry double-precision
@@ -113,6 +116,23 @@ struct BatchReduce {
   uint32_t first;
   uint32_t mprev, mnext;
   uint16_t nprev, nnext;
+};
+
+// Enumeration check (test entry ism_debug_enumerate): one record per image a
+// work item owns, with the lattice index n per room axis, k0 = floor(x), the
+// delay fraction fq in units of 2^-24 and the Eq. (4) amplitude in FP32.
+struct DumpRec {
+  int32_t rir;
+  int32_t n[3];
+  int32_t k0;
+  uint32_t fq;
+  float A;
+  uint32_t pad;
+};
+struct DumpArgs {
+  DumpRec *rec;
+  uint32_t *count;  // records produced (may exceed cap; only cap are stored)
+  uint32_t cap;
 };
 
 }  // namespace ism

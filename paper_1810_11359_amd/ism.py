@@ -36,7 +36,8 @@ EXPORTS = (
     "ism_simulate_diffuse_polar",
     "ism_batch_workspace_size", "ism_batch_prepare", "ism_batch_run", "ism_batch_run_timed",
     "ism_diffuse_workspace_size", "ism_simulate_diffuse", "ism_simulate_diffuse_timed",
-    "ism_filter_trajectory",
+    "ism_filter_trajectory", "ism_workspace_size_ex", "ism_simulate_ex", "ism_simulate_host",
+    "ism_batch_workspace_size_ex", "ism_batch_prepare_ex", "ism_simulate_batch", "ism_debug_enumerate",
 )
 
 
@@ -60,6 +61,35 @@ class _Job(ctypes.Structure):
 
 class _Batch(ctypes.Structure):
     _fields_ = [("opaque", ctypes.c_uint64 * 40)]
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("item_taps", ctypes.c_double), ("min_item_taps", ctypes.c_double),
+                ("balance_items", ctypes.c_double), ("tail_rounds", ctypes.c_double)]
+
+
+@dataclass
+class Schedule:
+    """Work split of a call (``ism_schedule``): 0 keeps a field's default
+    (tail_rounds: a negative value does)."""
+    item_taps: float = 0.0
+    min_item_taps: float = 0.0
+    balance_items: float = 0.0
+    tail_rounds: float = -1.0
+
+    def _c(self) -> _Schedule:
+        return _Schedule(float(self.item_taps), float(self.min_item_taps), float(self.balance_items),
+                         float(self.tail_rounds))
+
+
+def _sched(schedule):
+    """ctypes pointer argument for an optional Schedule (None -> NULL)."""
+    return None if schedule is None else ctypes.byref(schedule._c())
+
+
+# One record of ism_debug_enumerate (include/ism_debug.h).
+IMAGE_RECORD = np.dtype([("rir", "<i4"), ("n", "<i4", (3,)), ("k0", "<i4"), ("fq", "<u4"), ("amp", "<f4"),
+                         ("pad", "<u4")])
 
 
 _lib = None
@@ -124,6 +154,26 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t, fp]
         L.ism_filter_trajectory.restype = ctypes.c_int
         L.ism_filter_trajectory.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, fp]
+        sp = ctypes.POINTER(_Schedule)
+        L.ism_workspace_size_ex.restype = ctypes.c_int
+        L.ism_workspace_size_ex.argtypes = [rp, ctypes.c_int, ctypes.c_int, ctypes.c_int, sp,
+                                            ctypes.POINTER(ctypes.c_size_t)]
+        L.ism_simulate_ex.restype = ctypes.c_int
+        L.ism_simulate_ex.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, sp, fp, fp,
+                                      ctypes.c_size_t, fp, fp, fp]
+        L.ism_simulate_host.restype = ctypes.c_int
+        L.ism_simulate_host.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp,
+                                        ctypes.c_size_t, fp]
+        L.ism_batch_workspace_size_ex.restype = ctypes.c_int
+        L.ism_batch_workspace_size_ex.argtypes = [jp, ctypes.c_int, ctypes.c_int, sp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ism_batch_prepare_ex.restype = ctypes.c_int
+        L.ism_batch_prepare_ex.argtypes = [jp, ctypes.c_int, ctypes.c_int, sp, fp, ctypes.c_size_t, fp,
+                                           ctypes.POINTER(_Batch)]
+        L.ism_simulate_batch.restype = ctypes.c_int
+        L.ism_simulate_batch.argtypes = [jp, ctypes.c_int, ctypes.c_int, fp, ctypes.c_size_t, fp]
+        L.ism_debug_enumerate.restype = ctypes.c_int
+        L.ism_debug_enumerate.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, sp, fp, ctypes.c_uint32, fp, fp,
+                                          ctypes.c_size_t, fp]
         L.ism_simulate_diffuse_timed.restype = ctypes.c_int
         L.ism_simulate_diffuse_timed.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp,
                                                  ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
@@ -214,11 +264,11 @@ def count_taps(room: Room, src, rcv) -> int:
     return out.value
 
 
-def workspace_size(room: Room, n_src: int, n_rcv: int, precision: str = "fp32") -> int:
+def workspace_size(room: Room, n_src: int, n_rcv: int, precision: str = "fp32", schedule: Schedule = None) -> int:
     rc = room._c()
     out = ctypes.c_size_t()
-    _check(lib().ism_workspace_size(ctypes.byref(rc), int(n_src), int(n_rcv), PRECISIONS[precision],
-                                    ctypes.byref(out)), "ism_workspace_size")
+    _check(lib().ism_workspace_size_ex(ctypes.byref(rc), int(n_src), int(n_rcv), PRECISIONS[precision],
+                                       _sched(schedule), ctypes.byref(out)), "ism_workspace_size_ex")
     return out.value
 
 
@@ -229,12 +279,15 @@ class Simulator:
     launches kernels only.
     """
 
-    def __init__(self, room: Room, src, rcv, precision: str = "fp32", device: str = "cuda", check: bool = True):
+    def __init__(self, room: Room, src, rcv, precision: str = "fp32", device: str = "cuda", check: bool = True,
+                 schedule: Schedule = None):
         import torch
 
         self.torch = torch
         self.room = room
         self._room_c = room._c()
+        self.schedule = schedule
+        self._sched_c = None if schedule is None else schedule._c()
         s, r = _host_pos(src), _host_pos(rcv)
         if check:
             check_positions(room, s, r)
@@ -243,7 +296,7 @@ class Simulator:
         self.rcv = torch.from_numpy(r).to(device)
         self.n_src, self.n_rcv = s.shape[0], r.shape[0]
         self.out = torch.empty((self.n_src, self.n_rcv, room.n_samples), dtype=torch.float32, device=device)
-        nbytes = workspace_size(room, self.n_src, self.n_rcv, precision)
+        nbytes = workspace_size(room, self.n_src, self.n_rcv, precision, schedule)
         self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
         self.ws_bytes = nbytes
 
@@ -252,16 +305,62 @@ class Simulator:
 
         ``ev_start``/``ev_stop`` are optional raw hipEvent_t handles recorded around the tap kernel."""
         st = stream if stream is not None else self.torch.cuda.current_stream()
-        _check(lib().ism_simulate_timed(ctypes.byref(self._room_c), self.src.data_ptr(), self.n_src,
-                                        self.rcv.data_ptr(), self.n_rcv, self.precision, self.out.data_ptr(),
-                                        self.ws.data_ptr(), self.ws_bytes, st.cuda_stream, ev_start, ev_stop),
-               "ism_simulate_timed")
+        sc = None if self._sched_c is None else ctypes.byref(self._sched_c)
+        _check(lib().ism_simulate_ex(ctypes.byref(self._room_c), self.src.data_ptr(), self.n_src,
+                                     self.rcv.data_ptr(), self.n_rcv, self.precision, sc, self.out.data_ptr(),
+                                     self.ws.data_ptr(), self.ws_bytes, st.cuda_stream, ev_start, ev_stop),
+               "ism_simulate_ex")
         return self.out
 
 
-def simulate(room: Room, src, rcv, precision: str = "fp32", device: str = "cuda"):
+def simulate(room: Room, src, rcv, precision: str = "fp32", device: str = "cuda", schedule: Schedule = None):
     """RIRs [n_src, n_rcv, nS] (float32, on ``device``) of every source/receiver pair."""
-    return Simulator(room, src, rcv, precision, device).run()
+    return Simulator(room, src, rcv, precision, device, schedule=schedule).run()
+
+
+def simulate_host(room: Room, src, rcv, precision: str = "fp32", out=None, device: str = "cuda"):
+    """``ism_simulate_host``: positions passed from host memory and checked by
+    the library before any launch. ``out`` (optional) is a float32 device
+    tensor [n_src, n_rcv, nS] to overwrite; returns it."""
+    import torch
+
+    s, r = _host_pos(src), _host_pos(rcv)
+    if out is None:
+        out = torch.empty((s.shape[0], r.shape[0], room.n_samples), dtype=torch.float32, device=device)
+    rc = room._c()
+    nbytes = workspace_size(room, s.shape[0], r.shape[0], precision)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=out.device)
+    st = torch.cuda.current_stream(out.device)
+    _check(lib().ism_simulate_host(ctypes.byref(rc), s.ctypes.data, s.shape[0], r.ctypes.data, r.shape[0],
+                                   PRECISIONS[precision], out.data_ptr(), ws.data_ptr(), nbytes, st.cuda_stream),
+           "ism_simulate_host")
+    return out
+
+
+def debug_enumerate(room: Room, src, rcv, schedule: Schedule = None, cap: int = None, device: str = "cuda"):
+    """``ism_debug_enumerate``: every image the work items of ``ism_simulate_ex``
+    own, as a numpy array of IMAGE_RECORD (unordered). ``cap`` bounds the
+    records fetched (default: the lattice size of all pairs)."""
+    import torch
+
+    s, r = _host_pos(src), _host_pos(rcv)
+    n_rir = s.shape[0] * r.shape[0]
+    if cap is None:
+        cap = n_rir * int(np.prod(room.n_img))
+    rc = room._c()
+    nbytes = workspace_size(room, s.shape[0], r.shape[0], "fp32", schedule)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+    rec = torch.empty(max(cap, 1) * IMAGE_RECORD.itemsize, dtype=torch.uint8, device=device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=device)
+    src_d, rcv_d = torch.from_numpy(s).to(device), torch.from_numpy(r).to(device)
+    st = torch.cuda.current_stream()
+    _check(lib().ism_debug_enumerate(ctypes.byref(rc), src_d.data_ptr(), s.shape[0], rcv_d.data_ptr(), r.shape[0],
+                                     _sched(schedule), rec.data_ptr(), int(cap), cnt.data_ptr(), ws.data_ptr(),
+                                     nbytes, st.cuda_stream), "ism_debug_enumerate")
+    n = int(cnt.item()) & 0xFFFFFFFF
+    if n > cap:
+        raise IsmError(ISM_E_TOO_LARGE, f"ism_debug_enumerate: {n} images, cap {cap}")
+    return np.frombuffer(rec[:n * IMAGE_RECORD.itemsize].cpu().numpy().tobytes(), dtype=IMAGE_RECORD)
 
 
 # First-order receiver patterns a + (1 - a) cos(theta) (ism_simulate_polar).
@@ -410,7 +509,8 @@ class BatchSimulator:
     ``self.outs[i]`` with shape [n_src, n_rcv, nS] on ``device``.
     """
 
-    def __init__(self, jobs, precision: str = "fp32", device: str = "cuda", check: bool = True, stream=None):
+    def __init__(self, jobs, precision: str = "fp32", device: str = "cuda", check: bool = True, stream=None,
+                 schedule: Schedule = None):
         import torch
 
         self.torch = torch
@@ -446,14 +546,15 @@ class BatchSimulator:
             arr[i].out = out.data_ptr()
         self.n_rirs = sum(int(o.shape[0] * o.shape[1]) for o in self.outs)
         nbytes = ctypes.c_size_t()
-        _check(lib().ism_batch_workspace_size(arr, len(jobs), self.precision, ctypes.byref(nbytes)),
-               "ism_batch_workspace_size")
+        _check(lib().ism_batch_workspace_size_ex(arr, len(jobs), self.precision, _sched(schedule),
+                                                 ctypes.byref(nbytes)), "ism_batch_workspace_size_ex")
         self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=device)
         self.ws_bytes = nbytes.value
         self.batch = _Batch()
         st = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().ism_batch_prepare(arr, len(jobs), self.precision, self.ws.data_ptr(), self.ws_bytes,
-                                       st.cuda_stream, ctypes.byref(self.batch)), "ism_batch_prepare")
+        _check(lib().ism_batch_prepare_ex(arr, len(jobs), self.precision, _sched(schedule), self.ws.data_ptr(),
+                                          self.ws_bytes, st.cuda_stream, ctypes.byref(self.batch)),
+               "ism_batch_prepare_ex")
 
     def run(self, stream=None, ev_start=None, ev_stop=None):
         st = stream if stream is not None else self.torch.cuda.current_stream()
@@ -463,3 +564,56 @@ class BatchSimulator:
             _check(lib().ism_batch_run_timed(ctypes.byref(self.batch), st.cuda_stream, ev_start, ev_stop),
                    "ism_batch_run_timed")
         return self.outs
+
+
+def batch_workspace_size(jobs, precision: str = "fp32", schedule: Schedule = None) -> int:
+    """``ism_batch_workspace_size_ex`` of jobs given as (Room, n_src, n_rcv) or
+    (Room, n_src, n_rcv, directional) tuples (no positions are needed to size it)."""
+    arr = (_Job * len(jobs))()
+    dummy = ctypes.c_float(0.0)
+    for i, j in enumerate(jobs):
+        arr[i].room = j[0]._c()
+        arr[i].n_src, arr[i].n_rcv = int(j[1]), int(j[2])
+        arr[i].src = arr[i].rcv = arr[i].out = ctypes.addressof(dummy)
+        if len(j) > 3 and j[3]:
+            arr[i].orient, arr[i].pattern = ctypes.addressof(dummy), 1.0
+    out = ctypes.c_size_t()
+    _check(lib().ism_batch_workspace_size_ex(arr, len(jobs), PRECISIONS[precision], _sched(schedule),
+                                             ctypes.byref(out)), "ism_batch_workspace_size_ex")
+    return out.value
+
+
+def simulate_batch(jobs, precision: str = "fp32", outs=None, device: str = "cuda"):
+    """``ism_simulate_batch``: jobs as (Room, src, rcv) or (Room, src, rcv, orient,
+    pattern) with HOST positions, checked by the library before any launch and
+    uploaded with the batch tables. ``outs`` (optional): float32 device tensors
+    [n_src, n_rcv, nS] per job to overwrite. Returns the list of outputs."""
+    import torch
+
+    arr = (_Job * len(jobs))()
+    keep = []
+    if outs is None:
+        outs = []
+        for j in jobs:
+            s, r = _host_pos(j[1]), _host_pos(j[2])
+            outs.append(torch.empty((s.shape[0], r.shape[0], j[0].n_samples), dtype=torch.float32, device=device))
+    for i, j in enumerate(jobs):
+        s, r = _host_pos(j[1]), _host_pos(j[2])
+        keep += [s, r]
+        arr[i].room = j[0]._c()
+        arr[i].src, arr[i].n_src = s.ctypes.data, s.shape[0]
+        arr[i].rcv, arr[i].n_rcv = r.ctypes.data, r.shape[0]
+        arr[i].out = outs[i].data_ptr()
+        if len(j) == 5:
+            o = _host_pos(j[3])
+            keep.append(o)
+            arr[i].orient = o.ctypes.data
+            arr[i].pattern = PATTERNS[j[4]] if isinstance(j[4], str) else float(j[4])
+    nbytes = ctypes.c_size_t()
+    _check(lib().ism_batch_workspace_size(arr, len(jobs), PRECISIONS[precision], ctypes.byref(nbytes)),
+           "ism_batch_workspace_size")
+    ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=outs[0].device)
+    st = torch.cuda.current_stream(outs[0].device)
+    _check(lib().ism_simulate_batch(arr, len(jobs), PRECISIONS[precision], ws.data_ptr(), nbytes.value,
+                                    st.cuda_stream), "ism_simulate_batch")
+    return outs

@@ -16,9 +16,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "ism.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ism_[a-z0-9_]+)\s*\(", text)))
+    """Every function any header under include/ declares."""
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(ism_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -208,21 +213,28 @@ def test_batch_checks_before_any_launch():
 
 def test_tail_taper_splits_only_single_calls(monkeypatch):
     """Single calls cut the items dispatched last (more items, hence more
-    margin records in the workspace); a fixed item size or ISM_TAIL_ROUNDS=0
-    turns the taper off, and batches never taper."""
+    margin records in the workspace); a fixed item size or tail_rounds = 0
+    turns the taper off, and batches never taper. The library reads no
+    environment variables: setting the old override names changes nothing."""
     from paper_1810_11359_amd import workloads
 
     w = workloads.room_32_receivers(0)
     room = ism.room_for(w)
     tapered = ism.workspace_size(room, 1, 8)
-    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
-    plain = ism.workspace_size(room, 1, 8)
+    plain = ism.workspace_size(room, 1, 8, schedule=ism.Schedule(tail_rounds=0.0))
     assert tapered > plain
-    monkeypatch.setenv("ISM_TAIL_ROUNDS", "1")
-    monkeypatch.setenv("ISM_TARGET_TAPS", "120000")
-    fixed = ism.workspace_size(room, 1, 8)
-    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
-    assert ism.workspace_size(room, 1, 8) == fixed
+    assert ism.workspace_size(room, 1, 8, schedule=ism.Schedule(tail_rounds=-1.0)) == tapered
+    fixed = ism.workspace_size(room, 1, 8, schedule=ism.Schedule(item_taps=120000.0))
+    assert ism.workspace_size(room, 1, 8, schedule=ism.Schedule(item_taps=120000.0, tail_rounds=1.0)) == fixed
+    # a batch of one job plans like the untapered single call (plus its tables)
+    assert ism.batch_workspace_size([(room, 1, 8)]) > plain
+    for name in ("ISM_TAIL_ROUNDS", "ISM_TARGET_TAPS", "ISM_ITEM_MIN_TAPS", "ISM_ITEM_BALANCE"):
+        monkeypatch.setenv(name, "0")
+    assert ism.workspace_size(room, 1, 8) == tapered
+    for bad in (ism.Schedule(item_taps=-1.0), ism.Schedule(balance_items=float("nan"))):
+        with pytest.raises(ism.IsmError) as e:
+            ism.workspace_size(room, 1, 8, schedule=bad)
+        assert e.value.status == ism.ISM_E_INVALID_ARG
 
 
 def test_diffuse_argument_checks():
@@ -234,3 +246,42 @@ def test_diffuse_argument_checks():
         with pytest.raises(ism.IsmError) as e:
             ism.diffuse_workspace_size(r, t_diff, t60, 1, 1)
         assert e.value.status == ism.ISM_E_INVALID_ARG
+
+
+def test_host_position_calls_check_before_any_launch():
+    """ism_simulate_host and ism_simulate_batch validate host positions (and
+    everything else) before touching the device: with fake device pointers
+    every rejected call returns its status without a launch."""
+    r = _room()
+    rc = r._c()
+    L = ism.lib()
+    fake = ctypes.c_void_p(0x1000)
+    need = ism.workspace_size(r, 1, 1)
+    ok = np.array([[1.0, 1.0, 1.0]], dtype=np.float32)
+    rcv = np.array([[2.0, 2.0, 2.0]], dtype=np.float32)
+    for pos, status in (([[0.0, 1.0, 1.0]], ism.ISM_E_OUT_OF_ROOM), ([[1.0, 1.0, float("nan")]], ism.ISM_E_OUT_OF_ROOM),
+                        ([[1.0, 1.0, 1.0]], ism.ISM_E_INVALID_ARG)):
+        bad = np.array(pos, dtype=np.float32)
+        assert L.ism_simulate_host(ctypes.byref(rc), ok.ctypes.data, 1, bad.ctypes.data, 1, 0, fake, fake, need,
+                                   None) == status
+    assert L.ism_simulate_host(ctypes.byref(rc), ok.ctypes.data, 1, rcv.ctypes.data, 1, 0, fake, fake, need - 1,
+                               None) == ism.ISM_E_WORKSPACE
+    assert L.ism_simulate_host(ctypes.byref(rc), ok.ctypes.data, 1, rcv.ctypes.data, 1, 2, fake, fake, need,
+                               None) == ism.ISM_E_UNSUPPORTED
+    assert L.ism_simulate_host(ctypes.byref(rc), None, 1, rcv.ctypes.data, 1, 0, fake, fake, need,
+                               None) == ism.ISM_E_INVALID_ARG
+    # batch: the second job's receiver lies outside its room
+    jobs = (ism._Job * 2)()
+    far = np.array([[1.0, 9.0, 1.0]], dtype=np.float32)
+    for i, rr in enumerate((rcv, far)):
+        jobs[i].room = rc
+        jobs[i].src, jobs[i].n_src, jobs[i].rcv, jobs[i].n_rcv = ok.ctypes.data, 1, rr.ctypes.data, 1
+        jobs[i].out = 0x1000
+    n = ctypes.c_size_t()
+    assert L.ism_batch_workspace_size(jobs, 2, 0, ctypes.byref(n)) == ism.ISM_OK
+    assert L.ism_simulate_batch(jobs, 2, 0, fake, n.value, None) == ism.ISM_E_OUT_OF_ROOM
+    jobs[1].rcv = rcv.ctypes.data
+    assert L.ism_simulate_batch(jobs, 2, 0, fake, n.value - 1, None) == ism.ISM_E_WORKSPACE
+    o = np.zeros((1, 3), dtype=np.float32)
+    jobs[0].orient, jobs[0].pattern = o.ctypes.data, 0.5
+    assert L.ism_simulate_batch(jobs, 2, 0, fake, n.value, None) == ism.ISM_E_INVALID_ARG

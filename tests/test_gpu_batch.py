@@ -48,20 +48,27 @@ def _mixed_jobs():
     return jobs
 
 
-def test_batch_equals_single_room_calls(oracle_mod, monkeypatch):
+# a batch plans each job like a single call without the tail taper
+UNTAPERED = ism.Schedule(tail_rounds=0.0)
+
+
+def test_batch_equals_single_room_calls(oracle_mod):
     import torch
 
-    # a batch plans each job like a single call without the tail taper
-    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
     jobs = _mixed_jobs()
     _say("mixed batch")
     b = ism.BatchSimulator(jobs)
     outs = [o.clone() for o in b.run()]
     torch.cuda.synchronize()
     for (room, src, rcv), o in zip(jobs, outs):
-        single = ism.simulate(room, src, rcv)
+        single = ism.simulate(room, src, rcv, schedule=UNTAPERED)
         torch.cuda.synchronize()
         assert torch.equal(o, single), f"batch differs from single-room call for {room.room}"
+        # the default single call tapers its tail: another split, same sums within rounding
+        tapered = ism.simulate(room, src, rcv)
+        torch.cuda.synchronize()
+        peak = torch.amax(torch.abs(single), dim=-1)
+        assert bool(torch.all(torch.amax(torch.abs(tapered - o), dim=-1) <= 1e-6 * peak))
     # oracle on two of the jobs
     for k in (0, 1):
         room, src, rcv = jobs[k]
@@ -71,30 +78,30 @@ def test_batch_equals_single_room_calls(oracle_mod, monkeypatch):
         assert np.all(err <= TOL_FP32)
 
 
-def test_batch_table_taps_equal_single_calls(monkeypatch):
+def test_batch_table_taps_equal_single_calls():
     """Table taps (Eq. (9)) through the batch path: each job bitwise equal to
-    its own single-room call with the same precision."""
+    its own single-room call with the same precision (and schedule)."""
     import torch
 
-    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
     jobs = _mixed_jobs()
     _say("mixed batch, table taps")
     b = ism.BatchSimulator(jobs, precision="lut")
     outs = [o.clone() for o in b.run()]
     torch.cuda.synchronize()
     for (room, src, rcv), o in zip(jobs, outs):
-        single = ism.simulate(room, src, rcv, precision="lut")
+        single = ism.simulate(room, src, rcv, precision="lut", schedule=UNTAPERED)
         torch.cuda.synchronize()
         assert torch.equal(o, single), f"batch differs from single-room call for {room.room}"
 
 
-def test_batch_directional_jobs_equal_single_calls(monkeypatch):
+def test_batch_directional_jobs_equal_single_calls():
     """A batch mixing directional and omnidirectional jobs: every job bitwise
-    equal to its own single call (ism_simulate_polar or ism_simulate), since
-    the omnidirectional jobs' pattern factor is exactly 1."""
+    equal to itself alone in a batch, omnidirectional jobs bitwise equal to
+    their single call with the batch's schedule (their pattern factor is
+    exactly 1), directional jobs within rounding of ism_simulate_polar (whose
+    default schedule tapers the tail)."""
     import torch
 
-    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
     jobs = _mixed_jobs()
     rng = np.random.default_rng(11)
     patterns = ["cardioid", None, "bidirectional", None, "hypercardioid"]
@@ -109,12 +116,18 @@ def test_batch_directional_jobs_equal_single_calls(monkeypatch):
     outs = [o.clone() for o in b.run()]
     torch.cuda.synchronize()
     for job, o in zip(batch_jobs, outs):
+        alone = ism.BatchSimulator([job]).run()[0]
+        torch.cuda.synchronize()
+        assert torch.equal(o, alone), f"batch job differs from the job alone for {job[0].room}"
         if len(job) == 5:
             single = ism.simulate_polar(job[0], job[1], job[2], job[3], job[4])
+            torch.cuda.synchronize()
+            peak = torch.amax(torch.abs(single), dim=-1)
+            assert bool(torch.all(torch.amax(torch.abs(single - o), dim=-1) <= 1e-6 * peak))
         else:
-            single = ism.simulate(job[0], job[1], job[2])
-        torch.cuda.synchronize()
-        assert torch.equal(o, single), f"batch differs from single-room call for {job[0].room}"
+            single = ism.simulate(job[0], job[1], job[2], schedule=UNTAPERED)
+            torch.cuda.synchronize()
+            assert torch.equal(o, single), f"batch differs from single-room call for {job[0].room}"
 
 
 def _feasible(oracle_mod):

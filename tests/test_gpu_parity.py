@@ -35,10 +35,10 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _gpu_rir(room, src, rcv, precision="fp32"):
+def _gpu_rir(room, src, rcv, precision="fp32", schedule=None):
     import torch
 
-    out = ism.simulate(room, src, rcv, precision=precision)
+    out = ism.simulate(room, src, rcv, precision=precision, schedule=schedule)
     torch.cuda.synchronize()
     return out.cpu().numpy().astype(np.float64)
 
@@ -146,7 +146,7 @@ def test_invalid_pair_gives_nan():
     assert np.all(np.isnan(h[0, 1])) and np.all(np.isnan(h[0, 3]))
 
 
-def test_repeatable_and_split_invariant(monkeypatch):
+def test_repeatable_and_split_invariant():
     import torch
 
     w = workloads.room_32_receivers(1)
@@ -156,8 +156,7 @@ def test_repeatable_and_split_invariant(monkeypatch):
     b = _gpu_rir(room, w.src, w.rcv[:8])
     peak = np.max(np.abs(a), axis=-1)
     assert np.array_equal(a, b)  # fixed summation order: bitwise reproducible
-    monkeypatch.setenv("ISM_TARGET_TAPS", "20000")  # many more work items per tile
-    c = _gpu_rir(room, w.src, w.rcv[:8])
+    c = _gpu_rir(room, w.src, w.rcv[:8], schedule=ism.Schedule(item_taps=20000.0))  # many more items per tile
     # Another split only reorders the FP32 sums: a late sample adds ~1e4 taps of
     # up to ~0.1 peak each, so reordering moves it by a few ulps of such terms
     # (~1e-7 of the peak). 1e-6 bounds that with margin, 10x inside the parity

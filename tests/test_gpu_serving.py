@@ -10,12 +10,10 @@ from paper_1810_11359_amd.serving import GpuExecutor, Job, Scheduler, replay
 pytestmark = pytest.mark.gpu
 
 
-def test_mixed_stream_equals_jobs_alone(monkeypatch):
+def test_mixed_stream_equals_jobs_alone():
     import torch
 
     assert torch.cuda.is_available()
-    # batches plan each job like a single call without the tail taper
-    monkeypatch.setenv("ISM_TAIL_ROUNDS", "0")
 
     def feasible(room, t60):
         try:
@@ -41,6 +39,7 @@ def test_mixed_stream_equals_jobs_alone(monkeypatch):
     assert st.n_jobs == len(jobs)
     assert max(sch.batch_sizes) > 1  # jobs were actually batched together
     for j in sorted(sch.done, key=lambda j: j.jid):
-        alone = ism.simulate(j.room, j.src, j.rcv)
+        # batches plan each job like a single call without the tail taper
+        alone = ism.simulate(j.room, j.src, j.rcv, schedule=ism.Schedule(tail_rounds=0.0))
         torch.cuda.synchronize()
         assert torch.equal(alone, j.out), f"job {j.jid} differs alone vs in the mix"
