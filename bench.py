@@ -172,10 +172,21 @@ def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None, lut_q: int = 0, one_core_
     threads = min(threads, n_rir)
     taps_per = [orc.count_taps(*_oracle_args(orc, w), w.src, r) for w, r in jobs]
     taps = sum(taps_per)
+    # every RIR of the sample on its own oracle thread, `threads` at a time
+    # (the oracle's C code runs outside the interpreter lock)
+    from concurrent.futures import ThreadPoolExecutor
+
+    tasks = [(j, i) for j, (w, r) in enumerate(jobs) for i in range(r.shape[0])]
+
+    def one(t):
+        w, r = jobs[t[0]]
+        return orc.rir(*_oracle_args(orc, w), w.src, r[t[1]:t[1] + 1], n_threads=1, lut_q=lut_q)
+
     t0 = time.perf_counter()
-    refs = [orc.rir(*_oracle_args(orc, w), w.src, r, n_threads=min(threads, r.shape[0]), lut_q=lut_q)
-            for w, r in jobs]
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        parts = list(pool.map(one, tasks))
     dt = time.perf_counter() - t0
+    refs = [np.concatenate([parts[k] for k, t in enumerate(tasks) if t[0] == j], axis=1) for j in range(len(jobs))]
     # one core: whole RIRs from the front of the sample
     one_jobs, one_taps = [], 0
     for (w, r) in jobs:
@@ -276,24 +287,40 @@ def serve(args) -> int:
     return 0
 
 
+# Moving-source workloads: (room [m], T60 = T_max [s], fs [Hz], T_w [s], trajectory end points)
+MOVING_SOURCE = {
+    "moving_source_10s": ([4.0, 5.0, 3.0], 0.5, 16000.0, 0.004, ([0.8, 0.8, 1.6], [3.2, 4.2, 1.6])),
+    "moving_source_48k_96000": ([6.0, 9.0, 3.5], 2.0, 48000.0, 0.002, ([1.0, 1.0, 1.6], [5.0, 8.0, 1.6])),
+}
+
+
 def bench_moving_source(args) -> int:
-    """Moving-source filtering (ism_filter_trajectory): a 10 s signal at 16 kHz
-    through the RIRs of 100 trajectory points to an 8-mic array in a 4 x 5 x 3 m
-    room at T60 0.5 s (RIRs of 8000 samples, computed once by ism_simulate,
-    outside the timed region). One step = one filter call; value in G MAC/s
+    """Moving-source filtering (ism_filter_trajectory): a 10 s signal through
+    the RIRs of 100 trajectory points to an 8-mic array (5 cm radius): a
+    4 x 5 x 3 m room at T60 0.5 s and 16 kHz (RIRs of 8000 samples), or a
+    6 x 9 x 3.5 m room at T60 2 s and 48 kHz (RIRs of 96 000 samples). The
+    RIRs are computed once by ism_simulate outside the timed region (their
+    time is reported beside). One step = one filter call; value in G MAC/s
     (n_x x n_rir x n_mic multiply-adds), roofline against the FP32 vector peak
     at 2 FLOP per multiply-add."""
     import torch
 
     from paper_1810_11359_amd import ism
 
-    L, t60, fs = [4.0, 5.0, 3.0], 0.5, 16000.0
-    room = ism.Room(L, list(ism.beta_from_t60(L, t60)), ism.n_img_for_time(L, 343.0, t60), 343.0, fs, t60, 0.004)
+    L, t60, fs, t_w, (p0, p1) = MOVING_SOURCE[args.workload]
+    room = ism.Room(L, list(ism.beta_from_t60(L, t60)), ism.n_img_for_time(L, 343.0, t60), 343.0, fs, t60, t_w)
     rng = np.random.default_rng(0)
-    pts = np.linspace([0.8, 0.8, 1.6], [3.2, 4.2, 1.6], 100).astype(np.float32)
-    mics = (np.array([2.0, 2.5, 1.2]) + 0.05 * np.stack([np.cos(np.arange(8) * np.pi / 4),
-                                                          np.sin(np.arange(8) * np.pi / 4), np.zeros(8)], 1))
-    rirs = ism.simulate(room, pts, mics.astype(np.float32))
+    pts = np.linspace(p0, p1, 100).astype(np.float32)
+    ctr = np.array([L[0] / 2, L[1] / 2, 1.2])
+    mics = (ctr + 0.05 * np.stack([np.cos(np.arange(8) * np.pi / 4), np.sin(np.arange(8) * np.pi / 4),
+                                   np.zeros(8)], 1))
+    sim = ism.Simulator(room, pts, mics.astype(np.float32))
+    sim.run()
+    torch.cuda.synchronize()
+    t_sim0 = time.perf_counter()
+    rirs = sim.run()
+    torch.cuda.synchronize()
+    sim_ms = (time.perf_counter() - t_sim0) * 1e3
     x = torch.from_numpy(rng.standard_normal(int(10 * fs)).astype(np.float32)).cuda()
     n_pos, n_mic, n_rir = rirs.shape
     macs = x.shape[0] * n_rir * n_mic
@@ -312,8 +339,10 @@ def bench_moving_source(args) -> int:
     out = {"metric": "moving-source filter multiply-adds/s (G/s)", "value": macs / (ms_step / 1e3) / 1e9,
            "unit": "G MAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-           "config": {"workload": "moving_source_10s_16k_100pts_8mics", "n_x": int(x.shape[0]), "n_pos": n_pos,
-                      "n_mic": n_mic, "n_rir": n_rir, "macs_per_step": macs, "parallelism": "single GPU"},
+           "config": {"workload": f"{args.workload}_{fs / 1000:g}k_100pts_8mics_{n_rir}_taps",
+                      "n_x": int(x.shape[0]), "n_pos": n_pos, "n_mic": n_mic, "n_rir": n_rir, "macs_per_step": macs,
+                      "parallelism": "single GPU"},
+           "simulate_rirs_ms": sim_ms,
            "wall_s_timed": time.perf_counter() - wall0,
            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
                         "frac": achieved / FP32_VECTOR_PEAK, "traffic": None, "kernel": "filter_kernel (whole call)",
@@ -447,7 +476,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch_rooms",
                     choices=["batch_rooms", "room_32_receivers", "single_rir", "large_room_uca",
-                             "paper_room_128rir", "paper_room_diffuse_1024rir", "moving_source_10s"])
+                             "paper_room_128rir", "paper_room_diffuse_1024rir", "moving_source_10s",
+                             "moving_source_48k_96000"])
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="RIRs the CPU oracle baseline computes (default 64 for the batch, 16 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -478,7 +508,7 @@ def main() -> int:
         return calibrate_hbm(args.calibrate_hbm)
     if args.rate > 0:
         return serve(args)
-    if args.workload == "moving_source_10s":
+    if args.workload in MOVING_SOURCE:
         return bench_moving_source(args)
     if args.workload == "batch_rooms":
         return bench_batch(args)

@@ -319,3 +319,21 @@ def filter_trajectory(x, rirs) -> np.ndarray:
         for m in range(n_mic):
             y[m, p * seg:p * seg + xs.size + n_rir - 1] += np.convolve(xs, rirs[p, m])
     return y
+
+
+def filter_samples(x, rirs, m: int, n_idx) -> np.ndarray:
+    """Selected outputs of the moving-source filter, one by one from the
+    definition: y_m[n] = sum_k x[n - k] rirs[p(n - k), m, k] over the k with
+    0 <= n - k < n_x, p(i) = floor(i / L), L = ceil(n_x / n_pos) (float64).
+    Equal to filter_trajectory(x, rirs)[m, n_idx]."""
+    x = np.asarray(x, dtype=np.float64)
+    n_pos, n_mic, n_rir = np.asarray(rirs).shape
+    n_x = x.shape[0]
+    seg = -(-n_x // n_pos)
+    out = np.zeros(len(n_idx))
+    for t, n in enumerate(n_idx):
+        k = np.arange(max(0, n - n_x + 1), min(n_rir, n + 1))
+        i = n - k
+        h = np.asarray(rirs[i // seg, m, k], dtype=np.float64)
+        out[t] = float(np.sum(x[i] * h))
+    return out

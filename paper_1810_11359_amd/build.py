@@ -44,6 +44,7 @@ def asm(out_path: str) -> str:
 
 
 if __name__ == "__main__":
+    # python -m paper_1810_11359_amd.build [--asm OUT.s]
     build(verbose=True)
-    if len(sys.argv) > 1 and sys.argv[1] == "--asm":
-        asm(os.path.join(ROOT, "_work", "ism_device.s"))
+    if len(sys.argv) > 2 and sys.argv[1] == "--asm":
+        print(asm(sys.argv[2]))

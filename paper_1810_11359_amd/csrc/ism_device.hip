@@ -24,11 +24,22 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
+
+#include <type_traits>
 
 #include "ism.h"
 #include "ism_internal.h"
 
 namespace ism {
+
+// Bits of a staged record that carry the tile-local base of an image (its
+// integer delay minus the tile start), and the mask that extracts them.
+constexpr int kBaseBits = (TILE <= 256) ? 8 : 9;
+constexpr uint32_t kBaseMask = (1u << kBaseBits) - 1u;
+static_assert(TILE <= (1 << kBaseBits), "tile-local bases must fit the record");
+// The delay fraction of the FP32 and table-tap records, in units of 2^-kFracBits.
+constexpr int kFracBits = 32 - kBaseBits;
 
 // ---------------------------------------------------------------------------
 // Float-float building blocks (Dekker / Knuth error-free transformations).
@@ -53,9 +64,11 @@ __device__ __forceinline__ void ff_mul(float ah, float al, float bh, float bl, f
   e = __builtin_fmaf(al, bh, e);
   fast_two_sum(p, e, ch, cl);
 }
-// b^e for e >= 0 by binary powering in float-float (0^0 = 1).
-__device__ float ff_pow(float b, int e) {
-  float rh = 1.0f, rl = 0.0f, bh = b, bl = 0.0f;
+// (b + bl)^e for e >= 0 by binary powering in float-float (0^0 = 1): the
+// reflection coefficient keeps its double-precision value, so the gain of an
+// image many reflections deep is accurate to a few FP32 ulp.
+__device__ float ff_pow(float b, float b_lo, int e) {
+  float rh = 1.0f, rl = 0.0f, bh = b, bl = b_lo;
   while (e > 0) {
     if (e & 1) ff_mul(rh, rl, bh, bl, rh, rl);
     e >>= 1;
@@ -179,6 +192,121 @@ constexpr SincPoly<WT> make_sinc_poly() {
   return P;
 }
 
+// Monomial coefficients of the degree-SPD interpolant at the Chebyshev nodes
+// of [-1/2, 1/2]: c = V^-1 y for the node values y, V the Vandermonde matrix
+// of the nodes (inverted in double by the compiler, Gauss-Jordan with partial
+// pivoting). Used for general-mode FP16 windows, whose interpolants are
+// computed per call.
+struct ChebFit {
+  float node[SPD + 1];
+  float vinv[SPD + 1][SPD + 1];  // vinv[k][i]: coefficient of t^k per unit value at node i
+  float sin_pi_f[SPD + 1];       // sin(pi f_i) / pi at f_i = node_i + 1/2
+};
+constexpr ChebFit make_cheb_fit() {
+  constexpr int NP = SPD + 1;
+  ChebFit F{};
+  double x[NP] = {}, a[NP][2 * NP] = {};
+  for (int i = 0; i < NP; ++i) x[i] = 0.5 * cx_cos((2.0 * i + 1.0) * kPi / (2.0 * NP));
+  for (int i = 0; i < NP; ++i) {  // [V | I], V[i][k] = x_i^k
+    double pw = 1.0;
+    for (int k = 0; k < NP; ++k) {
+      a[i][k] = pw;
+      pw *= x[i];
+    }
+    a[i][NP + i] = 1.0;
+  }
+  for (int c = 0; c < NP; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < NP; ++r)
+      if ((a[r][c] < 0 ? -a[r][c] : a[r][c]) > (a[piv][c] < 0 ? -a[piv][c] : a[piv][c])) piv = r;
+    for (int k = 0; k < 2 * NP; ++k) {
+      const double t = a[c][k];
+      a[c][k] = a[piv][k];
+      a[piv][k] = t;
+    }
+    const double d = a[c][c];
+    for (int k = 0; k < 2 * NP; ++k) a[c][k] /= d;
+    for (int r = 0; r < NP; ++r)
+      if (r != c) {
+        const double m = a[r][c];
+        for (int k = 0; k < 2 * NP; ++k) a[r][k] -= m * a[c][k];
+      }
+  }
+  // V^-1 maps node values to coefficients: c_k = sum_i (V^-1)[k][i] y_i
+  for (int k = 0; k < NP; ++k)
+    for (int i = 0; i < NP; ++i) F.vinv[k][i] = (float)a[k][NP + i];
+  for (int i = 0; i < NP; ++i) {
+    F.node[i] = (float)x[i];
+    F.sin_pi_f[i] = (float)(cx_sin(kPi * (x[i] + 0.5)) / kPi);  // pi (x + 1/2) in (0, pi)
+  }
+  return F;
+}
+__constant__ ChebFit kChebFit = make_cheb_fit();
+
+// sin(pi x) and cos(pi x) in FP32 for |x| < 2^22, to a few ulp. x is reduced
+// exactly to r = x - n/2 with n = rint(2x) (|r| <= 1/4); sin(pi r) and
+// cos(pi r) are summed from their Taylor series to degree 9 and 10 (the first
+// omitted terms are below 2e-10 at |pi r| <= pi/4), with coefficients
+// pi^k / k! rounded to FP32, and rotated by the quadrant n mod 4.
+__device__ __forceinline__ void sincospi_acc(float x, float &s, float &c) {
+  const float n = __builtin_rintf(2.0f * x);
+  const float r = __builtin_fmaf(n, -0.5f, x);  // exact
+  const float r2 = r * r;
+  constexpr float S1 = (float)kPi, S3 = (float)(-kPi * kPi * kPi / 6.0),
+                  S5 = (float)(kPi * kPi * kPi * kPi * kPi / 120.0),
+                  S7 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi / 5040.0),
+                  S9 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 362880.0);
+  constexpr float C2 = (float)(-kPi * kPi / 2.0), C4 = (float)(kPi * kPi * kPi * kPi / 24.0),
+                  C6 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi / 720.0),
+                  C8 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 40320.0),
+                  C10 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 3628800.0);
+  float ps = __builtin_fmaf(r2, S9, S7);
+  ps = __builtin_fmaf(r2, ps, S5);
+  ps = __builtin_fmaf(r2, ps, S3);
+  ps = __builtin_fmaf(r2, ps, S1);
+  const float sr = r * ps;
+  float pc = __builtin_fmaf(r2, C10, C8);
+  pc = __builtin_fmaf(r2, pc, C6);
+  pc = __builtin_fmaf(r2, pc, C4);
+  pc = __builtin_fmaf(r2, pc, C2);
+  const float cr = __builtin_fmaf(r2, pc, 1.0f);
+  const int q = ((int)n) & 3;
+  s = q == 0 ? sr : q == 1 ? cr : q == 2 ? -sr : -cr;
+  c = q == 0 ? cr : q == 1 ? -sr : q == 2 ? -cr : sr;
+}
+
+// Constants of tap jj (j = jj + 1 - WT/2) of a general-mode window of W
+// samples under cap WT, for FP32 (half == 0) or FP16 (half == 1) taps, into
+// e[0 .. WC_STRIDE). FP16: the interpolant of s_j(t) = tap value at
+// f = t + 1/2 (Eq. (6), 0 where |j - f| >= W/2) at the Chebyshev nodes.
+__device__ void window_const_entry(float W, int WT, int half, int jj, float *e) {
+  const int j = jj + 1 - WT / 2;
+  const float sg = (j & 1) ? 1.0f : -1.0f;  // sin(pi (j - f)) = sg sin(pi f)
+  for (int k = 0; k < WC_STRIDE; ++k) e[k] = 0.0f;
+  if (!half) {
+    float sn, cs;
+    sincospi_acc(2.0f * (float)j / W, sn, cs);
+    e[0] = -sg * 0x1p-32f;
+    e[1] = sg * (float)j;
+    e[2] = cs;
+    e[3] = sn;
+    return;
+  }
+  float y[SPD + 1];
+  for (int i = 0; i <= SPD; ++i) {
+    const float f = kChebFit.node[i] + 0.5f;
+    const float v = (float)j - f;
+    float sn, cs;
+    sincospi_acc(2.0f * v / W, sn, cs);
+    y[i] = (__builtin_fabsf(v) < 0.5f * W) ? sg * kChebFit.sin_pi_f[i] / v * 0.5f * (1.0f + cs) : 0.0f;
+  }
+  for (int k = 0; k <= SPD; ++k) {
+    float ck = 0.0f;
+    for (int i = 0; i <= SPD; ++i) ck = __builtin_fmaf(kChebFit.vinv[k][i], y[i], ck);
+    e[k] = ck;
+  }
+}
+
 // Lookup-table taps (Eq. (9)): the windowed sinc of Eq. (6) tabulated at Q
 // points per sample, L[n] = (1 + cos(2 pi n / (Q W))) / 2 sinc(n / Q) for
 // n = -QW/2 .. QW/2, and each tap interpolated linearly between the two
@@ -252,7 +380,7 @@ __device__ __forceinline__ AxisEntry table_entry(const RoomArgs &ra, const float
   // Gain factor: the path from image n crosses |floor(n/2)| copies of the wall
   // at 0 and |ceil(n/2)| copies of the wall at L along this axis.
   const int e0 = abs(n >> 1), e1 = abs((n + 1) >> 1);
-  const float g = ff_pow(ra.beta[2 * a], e0) * ff_pow(ra.beta[2 * a + 1], e1);
+  const float g = ff_pow(ra.beta[2 * a], ra.beta_lo[2 * a], e0) * ff_pow(ra.beta[2 * a + 1], ra.beta_lo[2 * a + 1], e1);
   // the enumeration only needs the square of the displacement
   float sq, sqe;
   ff_sq(v, ve, sq, sqe);
@@ -582,7 +710,7 @@ template <bool HALF>
 __device__ __forceinline__ float column_gain_scale(const RoomArgs &ra) {
   return HALF ? ra.kappa : ra.kappa * (float)(0.5 / kPi);
 }
-template <int WT, bool HALF, bool LUT, bool POLAR>
+template <int WT, bool HALF, bool LUT, bool POLAR, bool GEN = false>
 __device__ __forceinline__ ImageParams<HALF || LUT> image_params(const RoomArgs &ra, const ItemGeom &g,
                                                                  const float2v cs, const float cgain,
                                                                  const AxisEntry ez, const float cp) {
@@ -612,25 +740,25 @@ __device__ __forceinline__ ImageParams<HALF || LUT> image_params(const RoomArgs 
   if constexpr (POLAR) A *= __builtin_fmaf(ra.dir_b, (cp + ez.proj) * rx, ra.dir_a);
   if constexpr (HALF) {
     const float t = fr - 0.5f;
-    const uint32_t Ab = (__float_as_uint(A) & ~0xffu) | ((uint32_t)p.base & 0xffu);
+    const uint32_t Ab = (__float_as_uint(A) & ~kBaseMask) | ((uint32_t)p.base & kBaseMask);
     p.rec = float2v{t, __uint_as_float(Ab)};
   } else if constexpr (LUT) {
     // 24-bit fraction (as in the FP32 record) with the base in the low byte;
     // its top 4 bits are the table phase, the next 20 the interpolation weight
-    const uint32_t fq = min((uint32_t)__builtin_rintf(fr * 0x1p24f), (1u << 24) - 1u);
-    p.rec = float2v{__uint_as_float((fq << 8) | ((uint32_t)p.base & 0xffu)), A};
+    const uint32_t fq = min((uint32_t)__builtin_rintf(fr * (float)(1u << kFracBits)), (1u << kFracBits) - 1u);
+    p.rec = float2v{__uint_as_float((fq << kBaseBits) | ((uint32_t)p.base & kBaseMask)), A};
   } else {
     // 24-bit fraction fq in [1, 2^24 - 2] (rounding moves the delay by at
     // most 3e-8 samples) and the base in the low byte; float(F) rounds F to
     // 24 bits, so f = float(F) 2^-32 lies in [2^-24, 1 - 2^-24].
-    const uint32_t fq = min(max((uint32_t)__builtin_rintf(fr * 0x1p24f), 1u), (1u << 24) - 2u);
-    const uint32_t F = (fq << 8) | ((uint32_t)p.base & 0xffu);
+    const uint32_t fq = min(max((uint32_t)__builtin_rintf(fr * (float)(1u << kFracBits)), 1u), (1u << kFracBits) - 2u);
+    const uint32_t F = (fq << kBaseBits) | ((uint32_t)p.base & kBaseMask);
     const float f = (float)F * 0x1p-32f;
     // The hardware sine and cosine take the angle in turns; their relative
     // error (< 1e-6, also for the tiny angles of f near 0 or 1) enters each
     // tap of the image once. sin(pi f) is taken as sin(pi min(f, 1 - f)).
     const float C2 = A * __builtin_amdgcn_sinf(0.5f * fminf(f, 1.0f - f));
-    const float turn = f * (1.0f / (float)WT);
+    const float turn = f * (GEN ? ra.inv_win : 1.0f / (float)WT);  // phi = 2 pi f / W in turns
     p.rec = f4v{__uint_as_float(F), C2 * __builtin_amdgcn_cosf(turn), C2 * __builtin_amdgcn_sinf(turn), C2};
   }
   return p;
@@ -719,11 +847,16 @@ __device__ __forceinline__ void write_invalid(int n_own, float *__restrict__ dst
 // DUMP: the enumeration check. No taps; every owned image is written to
 // dump->rec as a DumpRec of RIR rir (amplitude and fraction as the table
 // taps compute them).
-template <int WT, bool HALF, int NQ, bool LUT = false, bool POLAR = false, bool DUMP = false>
+// GEN: general-mode window (WT is the cap, W = 2 ra.win_hw): the per-lane tap
+// constants come from wc ([WT][WC_STRIDE], written for this window by
+// window_consts_kernel) and FP32 taps with |j - f| >= W/2 are masked.
+template <int WT, bool HALF, int NQ, bool LUT = false, bool POLAR = false, bool DUMP = false, bool GEN = false>
 __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int tile_id, const int C, const int c,
                                                 const AxisEntry *__restrict__ tab, const AxisOrigin &org,
                                                 const bool valid, float *__restrict__ dst, float *__restrict__ marg,
-                                                const DumpArgs *dump = nullptr, const int rir = 0) {
+                                                const DumpArgs *dump = nullptr, const int rir = 0,
+                                                const float *__restrict__ wc = nullptr) {
+  static_assert(!(GEN && (LUT || DUMP)), "general-mode windows take FP32 or FP16 taps");
   constexpr int LSPAN = TILE + WT - 1;
   constexpr int LPG = 64 / NQ;          // lanes per image
   constexpr int TPL = WT / LPG;         // taps per lane per step
@@ -760,7 +893,28 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   float nsg[TPL], sgj[TPL], cth[TPL], sth[TPL];  // FP32 taps
   float pc0[TPL];                                // FP16 taps: c0 of each tap
   half2_t pq[NPAIR][SPD];                        // and c1..c5 of tap pairs (2p, 2p + 1)
-  if constexpr (HALF) {
+  if constexpr (GEN && HALF) {
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) pc0[m] = wc[WC_STRIDE * (l + LPG * m)];
+#pragma unroll
+    for (int pr = 0; pr < NPAIR; ++pr)
+#pragma unroll
+      for (int k = 0; k < SPD; ++k) {
+        const int m0 = 2 * pr, m1 = 2 * pr + 1;
+        const float a = wc[WC_STRIDE * (l + LPG * m0) + k + 1];
+        const float b = m1 < TPL ? wc[WC_STRIDE * (l + LPG * m1) + k + 1] : 0.0f;
+        pq[pr][k] = half2_t{(_Float16)a, (_Float16)b};
+      }
+  } else if constexpr (GEN) {
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+      const float4 e = *reinterpret_cast<const float4 *>(wc + WC_STRIDE * (l + LPG * m));
+      nsg[m] = e.x;
+      sgj[m] = e.y;
+      cth[m] = e.z;
+      sth[m] = e.w;
+    }
+  } else if constexpr (HALF && !DUMP) {
     const SincPoly<WT> &P = poly_table<WT>();
 #pragma unroll
     for (int m = 0; m < TPL; ++m) pc0[m] = P.c[0][l + LPG * m];
@@ -773,7 +927,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         const float b = m1 < TPL ? P.c[k + 1][l + LPG * m1] : 0.0f;
         pq[pr][k] = half2_t{(_Float16)a, (_Float16)b};
       }
-  } else if constexpr (!LUT) {
+  } else if constexpr (!LUT && !DUMP) {
     const TapConsts<WT> &K = tap_table<WT>();
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
@@ -790,6 +944,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   // beat the vector-memory path, 0.68 against 0.89 ms on the 32-receiver
   // call); lrow is this lane's first entry of row 0 (rows are WT pairs apart)
   __shared__ __attribute__((aligned(16))) float lds_lut[LUT ? kLutQ * WT * 2 : 4];
+  const float hw = ra.win_hw;  // general mode: taps with |j - f| >= W/2 are masked
   if constexpr (LUT) {
     const float *gl = &lut_table<WT>().p[0][0][0];
     for (int i = lane; i < kLutQ * WT * 2; i += 64) lds_lut[i] = gl[i];
@@ -803,7 +958,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   // FP16) issued ahead.
   auto step = [&](const Rec P) {
     __asm__ volatile("" ::"v"(P));
-    const int b = (int)(__float_as_uint(HALF ? P.y : P.x) & 0xffu);
+    const int b = (int)(__float_as_uint(HALF ? P.y : P.x) & kBaseMask);
     float *t = th + b;
     if constexpr (HALF) {
       // tap = A (c0 + t q(t)), q in packed FP16 two taps at a time, the
@@ -824,12 +979,25 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       const uint32_t F = __float_as_uint(P.x);
       const float A = P.y;
       const int ph = (kLutQ - 1) - (int)(F >> 28);
-      const float al = 1.0f - (float)((F >> 8) & 0xfffffu) * 0x1p-20f;
+      const float al = 1.0f - (float)((F >> kBaseBits) & ((1u << (28 - kBaseBits)) - 1u)) *
+                                  (1.0f / (float)(1u << (28 - kBaseBits)));
       const float *const row = lrow + 2 * WT * ph;
 #pragma unroll
       for (int m = 0; m < TPL; ++m) {
         const float2v e = *reinterpret_cast<const float2v *>(row + 2 * LPG * m);
         t[LPG * m] = __builtin_fmaf(A, __builtin_fmaf(al, e.y, e.x), t[LPG * m]);
+      }
+    } else if constexpr (GEN) {
+      // general window: no half-period symmetry between the lane's taps; a
+      // tap outside |j - f| < W/2 gets a zero reciprocal
+      const float fs = (float)__float_as_uint(P.x);  // f 2^32
+#pragma unroll
+      for (int m = 0; m < TPL; ++m) {
+        float w = __builtin_fmaf(cth[m], P.y, P.w);
+        w = __builtin_fmaf(sth[m], P.z, w);
+        const float u = __builtin_fmaf(nsg[m], fs, sgj[m]);  // sigma (j - f)
+        const float r = __builtin_fabsf(u) < hw ? __builtin_amdgcn_rcpf(u) : 0.0f;
+        t[LPG * m] = __builtin_fmaf(w, r, t[LPG * m]);
       }
     } else {
       // When TPL is even, tap m + TPL/2 sits half a window period after tap
@@ -906,12 +1074,15 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
         first = (uint32_t)__builtin_amdgcn_readlane((int)first, 0);
         if (p.ok && first + (uint32_t)rank < dump->cap) {
           const uint32_t xy = col_xy[cl_c];
-          const int idx[3] = {(int)(xy >> 16), (int)(xy & 0xffffu), nz_c};
+          // lattice index per table axis, then per room axis (table axis k is room axis perm[k])
+          const int t0 = ra.lo[0] + (int)(xy >> 16), t1 = ra.lo[1] + (int)(xy & 0xffffu), t2 = ra.lo[2] + nz_c;
           DumpRec d;
           d.rir = rir;
-          for (int k = 0; k < 3; ++k) d.n[ra.perm[k]] = ra.lo[k] + idx[k];
+          d.n[0] = ra.perm[0] == 0 ? t0 : (ra.perm[1] == 0 ? t1 : t2);
+          d.n[1] = ra.perm[0] == 1 ? t0 : (ra.perm[1] == 1 ? t1 : t2);
+          d.n[2] = ra.perm[0] == 2 ? t0 : (ra.perm[1] == 2 ? t1 : t2);
           d.k0 = g.T0 + p.base;
-          d.fq = __float_as_uint(p.rec.x) >> 8;
+          d.fq = (__float_as_uint(p.rec.x) >> kBaseBits) << (kBaseBits - 8);  // units of 2^-24
           d.A = p.rec.y;
           d.pad = 0;
           dump->rec[first + (uint32_t)rank] = d;
@@ -923,7 +1094,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
       ImageParams<NARROW> p;
       p.ok = false;
       if (q + lane < total)
-        p = image_params<WT, HALF, LUT, POLAR>(ra, g, es.col_s[cl_c], cg_c, ez_c, POLAR ? col_p[cl_c] : 0.0f);
+        p = image_params<WT, HALF, LUT, POLAR, GEN>(ra, g, es.col_s[cl_c], cg_c, ez_c, POLAR ? col_p[cl_c] : 0.0f);
       const uint64_t okm = __ballot(p.ok);
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(okm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)okm, 0u));
       if (p.ok) stp[ns + rank] = p.rec;
@@ -1007,20 +1178,36 @@ __device__ __forceinline__ SingleItem decode_item(const PlanArgs &pa, uint32_t i
   return si;
 }
 
-template <int WT, bool HALF, int NQ, bool LUT, bool POLAR>
+template <int WT, bool HALF, int NQ, bool LUT, bool POLAR, bool GEN>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAccWavesPerSimd))) void accumulate_kernel(RoomArgs ra, PlanArgs pa,
                                                              const AxisEntry *__restrict__ tab_all,
                                                              const AxisOrigin *__restrict__ origin,
                                                              const int *__restrict__ valid, float *__restrict__ out,
-                                                             float *__restrict__ part, float *__restrict__ marg) {
+                                                             float *__restrict__ part, float *__restrict__ marg,
+                                                             const float *__restrict__ wc) {
   const uint32_t item = blockIdx.x;
   const SingleItem si = decode_item(pa, item);
   // (for a tile past nS, dst is never written: the tile has no own samples)
   float *dst = (si.C == 1) ? out + (size_t)si.rir * ra.n_samples + (size_t)si.tile_id * TILE
                            : part + (size_t)item * TILE;
   const AxisOrigin org = origin[si.rir];
-  accumulate_item<WT, HALF, NQ, LUT, POLAR>(ra, si.tile_id, si.C, si.c, tab_all + (size_t)si.rir * ra.n_tab, org,
-                                            valid[si.rir] != 0, dst, marg + (size_t)item * WT);
+  accumulate_item<WT, HALF, NQ, LUT, POLAR, false, GEN>(ra, si.tile_id, si.C, si.c,
+                                                        tab_all + (size_t)si.rir * ra.n_tab, org, valid[si.rir] != 0,
+                                                        dst, marg + (size_t)item * WT, nullptr, 0, wc);
+}
+
+// Per-tap constants of a general-mode window (one thread per tap of the cap).
+__global__ __launch_bounds__(256) void window_consts_kernel(float W, int WT, int half, float *__restrict__ wc) {
+  const int jj = threadIdx.x;
+  if (jj < WT) window_const_entry(W, WT, half, jj, wc + WC_STRIDE * jj);
+}
+// Batch mode: one block per job; jobs without general-mode constants exit.
+__global__ __launch_bounds__(256) void window_consts_batch_kernel(const JobDev *__restrict__ jobs, int half) {
+  const JobDev &jb = jobs[blockIdx.x];
+  if (!jb.wc) return;
+  const int WT = (int)(2.0f * jb.ra.half_w);
+  const int jj = threadIdx.x;
+  if (jj < WT) window_const_entry(2.0f * jb.ra.win_hw, WT, half, jj, jb.wc + WC_STRIDE * jj);
 }
 
 // Enumeration check: the items of a single-room launch, images only.
@@ -1040,24 +1227,39 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int n) {
   if (i < n) p[i] = v;
 }
 
-// Batch launch: every item names its job; the job table carries the room.
-template <int WT, bool HALF, int NQ, bool LUT, bool POLAR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAccWavesPerSimd))) void accumulate_batch_kernel(const JobDev *__restrict__ jobs,
-                                                                   const BatchItem *__restrict__ items,
-                                                                   const AxisEntry *__restrict__ tab_all,
-                                                                   const AxisOrigin *__restrict__ origin,
-                                                                   const int *__restrict__ valid,
-                                                                   float *__restrict__ part, float *__restrict__ marg) {
-  const BatchItem it = items[blockIdx.x];
-  const JobDev &jb = jobs[it.job];
-  const RoomArgs ra = jb.ra;
-  const uint32_t grir = jb.rir_base + it.rir;
-  float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
-                                        : part + (size_t)it.slot * TILE;
-  const AxisOrigin org = origin[grir];
-  accumulate_item<WT, HALF, NQ, LUT, POLAR>(ra, it.tile, it.chunks, it.chunk,
-                                     tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org, valid[grir] != 0, dst,
-                                     marg + (size_t)it.mslot * MARG_STRIDE);
+// Batch launch: persistent. The grid holds at most the resident waves; each
+// workgroup (one wave) takes item blockIdx.x first, then the next unclaimed
+// item of the largest-first list from the class's queue counter (which the
+// run sets to the grid size before the launch), until the list is exhausted.
+// Without a queue (queue == null) a workgroup takes every gridDim.x-th item.
+// Every item names its job; the job table carries the room.
+template <int WT, bool HALF, int NQ, bool LUT, bool POLAR, bool GEN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAccWavesPerSimd))) void accumulate_batch_kernel(
+    const JobDev *__restrict__ jobs, const BatchItem *__restrict__ items, uint32_t n_items, uint32_t *queue,
+    const AxisEntry *__restrict__ tab_all, const AxisOrigin *__restrict__ origin, const int *__restrict__ valid,
+    float *__restrict__ part, float *__restrict__ marg) {
+  const int lane = threadIdx.x & 63;
+  uint32_t item = blockIdx.x;
+  while (item < n_items) {
+    const BatchItem it = items[item];
+    const JobDev &jb = jobs[it.job];
+    const RoomArgs ra = jb.ra;
+    const uint32_t grir = jb.rir_base + it.rir;
+    float *dst = (it.slot == 0xffffffffu) ? jb.out + (size_t)it.rir * ra.n_samples + (size_t)it.tile * TILE
+                                          : part + (size_t)it.slot * TILE;
+    const AxisOrigin org = origin[grir];
+    accumulate_item<WT, HALF, NQ, LUT, POLAR, false, GEN>(ra, it.tile, it.chunks, it.chunk,
+                                                         tab_all + jb.tab_base + (size_t)it.rir * ra.n_tab, org,
+                                                         valid[grir] != 0, dst,
+                                                         marg + (size_t)it.mslot * MARG_UNIT, nullptr, 0, jb.wc);
+    if (queue) {
+      uint32_t next = 0;
+      if (lane == 0) next = atomicAdd(queue, 1u);
+      item = (uint32_t)__builtin_amdgcn_readlane((int)next, 0);
+    } else {
+      item += gridDim.x;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1143,8 +1345,8 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restr
   } else {
     v = *o;
   }
-  if (zl) v = ordered_sum(v, marg + (size_t)br.mprev * MARG_STRIDE + LM + k, MARG_STRIDE, br.nprev);
-  if (zr) v = ordered_sum(v, marg + (size_t)br.mnext * MARG_STRIDE + (k - (TILE - LM)), MARG_STRIDE, br.nnext);
+  if (zl) v = ordered_sum(v, marg + (size_t)br.mprev * MARG_UNIT + LM + k, W, br.nprev);
+  if (zr) v = ordered_sum(v, marg + (size_t)br.mnext * MARG_UNIT + (k - (TILE - LM)), W, br.nnext);
   *o = v;
 }
 
@@ -1165,89 +1367,156 @@ int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, const 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int WT, bool HALF, bool LUT, bool POLAR = false>
+template <int WT, bool HALF, bool LUT, bool POLAR, bool GEN>
 static int launch_acc_w(const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                         const AxisOrigin *origin, const int *valid, float *out, float *part, float *marg,
-                        hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR>), dim3(n_items), dim3(64),
-                     0, st, ra, pa, tab, origin, valid, out, part, marg);
+                        const float *wc, hipStream_t st) {
+  hipLaunchKernelGGL((accumulate_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR, GEN>), dim3(n_items),
+                     dim3(64), 0, st, ra, pa, tab, origin, valid, out, part, marg, wc);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_dump(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                 const AxisOrigin *origin, const int *valid, DumpArgs dump, hipStream_t st) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, dump.count, 0u, 1);
-  if (hipGetLastError() != hipSuccess) return -1;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    fprintf(stderr, "ism_debug_enumerate: fill launch: %s\n", hipGetErrorString(e));
+    return -1;
+  }
   switch (wt) {
     case 32: hipLaunchKernelGGL(enumerate_dump_kernel<32>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
     case 64: hipLaunchKernelGGL(enumerate_dump_kernel<64>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
     case 96: hipLaunchKernelGGL(enumerate_dump_kernel<96>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
     case 128: hipLaunchKernelGGL(enumerate_dump_kernel<128>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    case 160: hipLaunchKernelGGL(enumerate_dump_kernel<160>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    case 192: hipLaunchKernelGGL(enumerate_dump_kernel<192>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    case 224: hipLaunchKernelGGL(enumerate_dump_kernel<224>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
+    case 256: hipLaunchKernelGGL(enumerate_dump_kernel<256>, dim3(n_items), dim3(64), 0, st, ra, pa, tab, origin, valid, dump); break;
     default: return -2;
   }
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    fprintf(stderr, "ism_debug_enumerate: enumeration launch: %s\n", hipGetErrorString(e));
+    return -1;
+  }
+  return 0;
+}
+
+bool supported_window(int wt, bool gen) {
+  if (gen) return wt >= 32 && wt <= MAX_WINDOW && wt % 32 == 0;
+  return wt == 32 || wt == 64 || wt == 96 || wt == 128;
+}
+
+int launch_window_consts(float W, int wt, bool half, float *wc, hipStream_t st) {
+  hipLaunchKernelGGL(window_consts_kernel, dim3(1), dim3(MAX_WINDOW), 0, st, W, wt, half ? 1 : 0, wc);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-bool supported_window(int wt) { return wt == 32 || wt == 64 || wt == 96 || wt == 128; }
+// Calls the kernel instance of a window class: exact windows W in {32, 64,
+// 96, 128} with every tap mode, general-mode caps 32 .. 256 with FP32 or FP16
+// taps. fn is a generic lambda taking the template arguments as values.
+template <class Fn>
+static int dispatch_window(int wt, bool gen, bool half, bool lut, bool polar, Fn &&fn) {
+  if (half && lut) return -2;
+  auto by_mode = [&](auto W, auto G) -> int {
+    constexpr bool kG = decltype(G)::value;
+    if (half) return polar ? fn(W, std::true_type{}, std::false_type{}, std::true_type{}, G)
+                           : fn(W, std::true_type{}, std::false_type{}, std::false_type{}, G);
+    if constexpr (!kG) {
+      if (lut) return polar ? fn(W, std::false_type{}, std::true_type{}, std::true_type{}, G)
+                            : fn(W, std::false_type{}, std::true_type{}, std::false_type{}, G);
+    } else {
+      if (lut) return -2;
+    }
+    return polar ? fn(W, std::false_type{}, std::false_type{}, std::true_type{}, G)
+                 : fn(W, std::false_type{}, std::false_type{}, std::false_type{}, G);
+  };
+  using F = std::false_type;
+  using T = std::true_type;
+  if (!gen) {
+    switch (wt) {
+      case 32: return by_mode(std::integral_constant<int, 32>{}, F{});
+      case 64: return by_mode(std::integral_constant<int, 64>{}, F{});
+      case 96: return by_mode(std::integral_constant<int, 96>{}, F{});
+      case 128: return by_mode(std::integral_constant<int, 128>{}, F{});
+      default: return -2;
+    }
+  }
+  switch (wt) {
+    case 32: return by_mode(std::integral_constant<int, 32>{}, T{});
+    case 64: return by_mode(std::integral_constant<int, 64>{}, T{});
+    case 96: return by_mode(std::integral_constant<int, 96>{}, T{});
+    case 128: return by_mode(std::integral_constant<int, 128>{}, T{});
+    case 160: return by_mode(std::integral_constant<int, 160>{}, T{});
+    case 192: return by_mode(std::integral_constant<int, 192>{}, T{});
+    case 224: return by_mode(std::integral_constant<int, 224>{}, T{});
+    case 256: return by_mode(std::integral_constant<int, 256>{}, T{});
+    default: return -2;
+  }
+}
 
 // polar: directional receivers (any tap mode; half and lut exclusive).
-int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &ra, const PlanArgs &pa,
+int launch_accumulate(int wt, bool gen, bool half, bool lut, bool polar, const RoomArgs &ra, const PlanArgs &pa,
                       uint32_t n_items, const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out,
-                      float *part, float *marg, hipStream_t st) {
-  if (half && lut) return -2;
-#define ISM_ACC_M(W, H, L)                                                                                   \
-  (polar ? launch_acc_w<W, H, L, true>(ra, pa, n_items, tab, origin, valid, out, part, marg, st)             \
-         : launch_acc_w<W, H, L, false>(ra, pa, n_items, tab, origin, valid, out, part, marg, st))
-#define ISM_ACC(W) \
-  case W:          \
-    return half ? ISM_ACC_M(W, true, false) : lut ? ISM_ACC_M(W, false, true) : ISM_ACC_M(W, false, false);
-  switch (wt) {
-    ISM_ACC(32)
-    ISM_ACC(64)
-    ISM_ACC(96)
-    ISM_ACC(128)
-    default: return -2;
-  }
-#undef ISM_ACC
-#undef ISM_ACC_M
+                      float *part, float *marg, const float *wc, hipStream_t st) {
+  return dispatch_window(wt, gen, half, lut, polar, [&](auto W, auto H, auto L, auto P, auto G) -> int {
+    return launch_acc_w<decltype(W)::value, decltype(H)::value, decltype(L)::value, decltype(P)::value,
+                        decltype(G)::value>(ra, pa, n_items, tab, origin, valid, out, part, marg, wc, st);
+  });
 }
 
-template <int WT, bool HALF, bool LUT, bool POLAR>
-static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, const AxisEntry *tab,
-                              const AxisOrigin *origin, const int *valid, float *part, float *marg, hipStream_t st) {
-  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR>), dim3(n_items), dim3(64), 0, st, jobs, items, tab,
-                     origin, valid, part, marg);
+// Workgroups of a persistent batch launch: the waves resident at once
+// (256 CUs x 4 SIMDs x the waves per SIMD the kernel is built for).
+constexpr uint32_t kBatchGrid = 256u * 4u * (uint32_t)kAccWavesPerSimd;
+uint32_t batch_grid(uint32_t n_items) { return n_items < kBatchGrid ? n_items : kBatchGrid; }
+
+template <int WT, bool HALF, bool LUT, bool POLAR, bool GEN>
+static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, uint32_t *queue,
+                              const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *part,
+                              float *marg, hipStream_t st) {
+  hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR, GEN>),
+                     dim3(batch_grid(n_items)), dim3(64), 0, st, jobs, items, n_items, queue, tab, origin, valid,
+                     part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
-                 const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 bool half, bool lut, bool polar, const BatchReduce *red, uint32_t n_red, AxisEntry *tab,
-                 AxisOrigin *origin, int *valid,
-                 float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+// queue[k] = the first item of class k not taken by a workgroup's first pick.
+__global__ void queue_init_kernel(uint32_t *queue, uint4 a, uint4 b) {
+  const uint32_t v[kMaxBatchClasses] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  if (threadIdx.x < kMaxBatchClasses) queue[threadIdx.x] = v[threadIdx.x];
+}
+
+int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
+                 const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
+                 const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
+                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
+                 float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
   if (hipGetLastError() != hipSuccess) return -1;
+  if (any_gen) {
+    hipLaunchKernelGGL(window_consts_batch_kernel, dim3(n_jobs), dim3(MAX_WINDOW), 0, st, jobs, half ? 1 : 0);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  if (queue) {
+    uint32_t fp[kMaxBatchClasses] = {};
+    for (int k = 0; k < n_classes && k < kMaxBatchClasses; ++k) fp[k] = batch_grid(class_count[k]);
+    hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(64), 0, st, queue, make_uint4(fp[0], fp[1], fp[2], fp[3]),
+                       make_uint4(fp[4], fp[5], fp[6], fp[7]));
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
   if (ev_start && hipEventRecord(ev_start, st) != hipSuccess) return -1;
   for (int k = 0; k < n_classes; ++k) {
     if (class_count[k] == 0) continue;
     const BatchItem *it = items + class_first[k];
-    int rc = -2;
-#define ISM_BACC_M(W, H, L)                                                                                     \
-  (polar ? launch_acc_batch_w<W, H, L, true>(jobs, it, class_count[k], tab, origin, valid, part, marg, st)          \
-         : launch_acc_batch_w<W, H, L, false>(jobs, it, class_count[k], tab, origin, valid, part, marg, st))
-#define ISM_BACC(W)                                                                                           \
-  case W:                                                                                                     \
-    rc = half ? ISM_BACC_M(W, true, false) : lut ? ISM_BACC_M(W, false, true) : ISM_BACC_M(W, false, false); \
-    break;
-    switch (class_wt[k]) {
-      ISM_BACC(32)
-      ISM_BACC(64)
-      ISM_BACC(96)
-      ISM_BACC(128)
-      default: break;
-    }
-#undef ISM_BACC
-#undef ISM_BACC_M
+    uint32_t *qk = queue ? queue + k : nullptr;
+    const int rc = dispatch_window(class_wt[k], class_gen[k] != 0, half, lut, polar,
+                                   [&](auto W, auto H, auto L, auto P, auto G) -> int {
+                                     return launch_acc_batch_w<decltype(W)::value, decltype(H)::value,
+                                                               decltype(L)::value, decltype(P)::value,
+                                                               decltype(G)::value>(jobs, it, class_count[k], qk, tab,
+                                                                                   origin, valid, part, marg, st);
+                                   });
     if (rc != 0) return -1;
   }
   if (ev_stop && hipEventRecord(ev_stop, st) != hipSuccess) return -1;

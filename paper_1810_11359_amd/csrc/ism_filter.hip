@@ -14,7 +14,7 @@
 
 namespace ism {
 
-constexpr int FT = 128;       // threads per block
+constexpr int FT = 256;       // threads per block
 constexpr int FR = 4;         // consecutive outputs per thread
 constexpr int FN = FT * FR;   // outputs per block
 constexpr int FK = 256;       // filter taps per chunk
@@ -22,7 +22,15 @@ constexpr int FJ = 64;        // taps per sub-chunk (the unit a wave skips)
 constexpr int FW = 64 * FR;   // outputs per wave
 constexpr int XPAD = 1;       // zero slot in front of the staged input window (aligns the 16-byte reads)
 
-// grid = (ceil(n_y / FN), n_mic). For each chunk of FK taps and each segment
+// XCDs of the device: consecutive workgroups are dispatched to them in turn.
+constexpr int kXcds = 8;
+
+// grid = ceil(n_y / FN) x n_mic blocks, one dimension. Block b runs on XCD
+// b % 8; it takes logical block (b % 8) * ceil(G / 8) + b / 8 (G blocks in
+// all), so each XCD works through a contiguous run of output blocks of one
+// microphone, which read the same RIR chunks: that reuse stays in the XCD's
+// L2 instead of being fetched once per XCD. Logical block L covers outputs
+// [(L % gx) FN, +FN) of microphone L / gx. For each chunk of FK taps and each segment
 // the chunk's input window touches, the block stages the window (input
 // samples of other segments zeroed) and the segment's FK taps in LDS; a
 // thread keeps its 4 outputs in registers and slides a 4-sample input window
@@ -34,9 +42,13 @@ constexpr int XPAD = 1;       // zero slot in front of the staged input window (
 // input range is short next to a segment.
 __global__ __launch_bounds__(FT) void filter_kernel(const float *__restrict__ x, int n_x,
                                                     const float *__restrict__ rir, int n_mic, int n_rir,
-                                                    int seg_len, float *__restrict__ y, int n_y) {
-  const int m = blockIdx.y;
-  const int n0 = blockIdx.x * FN;
+                                                    int seg_len, float *__restrict__ y, int n_y, int gx) {
+  const int G = gx * n_mic;
+  const int per_xcd = (G + kXcds - 1) / kXcds;
+  const int L = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (L >= G) return;  // uniform over the block
+  const int m = L / gx;
+  const int n0 = (L % gx) * FN;
   const int tid = threadIdx.x;
   __shared__ __attribute__((aligned(16))) float xs[XPAD + FN + FK];
   __shared__ __attribute__((aligned(16))) float hs[FK];
@@ -68,21 +80,29 @@ __global__ __launch_bounds__(FT) void filter_kernel(const float *__restrict__ x,
         if (ihi < s0 || ilo >= s1 || kc + jb >= n_rir) continue;  // uniform over the wave
         const f4 v = *reinterpret_cast<const f4 *>(&xs[base - jb]);
         float v0 = v.x, v1 = v.y, v2 = v.z, v3 = v.w;
+        // two-level sums: the FJ products of a sub-chunk, then the sub-chunk
+        // sums, so rounding grows as sqrt(FJ) + sqrt(n_rir / FJ) instead of
+        // sqrt(n_rir) over an output's n_rir products
+        float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, b3 = 0.0f;
 #pragma unroll 4
         for (int j = jb; j < jb + FJ; j += 4) {
           const f4 t = *reinterpret_cast<const f4 *>(&hs[j]);
           // u.w, u.z, u.y, u.x = inputs one, two, three, four slots before v0
           const f4 u = *reinterpret_cast<const f4 *>(&xs[base - j - 4]);
-          a0 = __builtin_fmaf(v0, t.x, a0); a0 = __builtin_fmaf(u.w, t.y, a0);
-          a0 = __builtin_fmaf(u.z, t.z, a0); a0 = __builtin_fmaf(u.y, t.w, a0);
-          a1 = __builtin_fmaf(v1, t.x, a1); a1 = __builtin_fmaf(v0, t.y, a1);
-          a1 = __builtin_fmaf(u.w, t.z, a1); a1 = __builtin_fmaf(u.z, t.w, a1);
-          a2 = __builtin_fmaf(v2, t.x, a2); a2 = __builtin_fmaf(v1, t.y, a2);
-          a2 = __builtin_fmaf(v0, t.z, a2); a2 = __builtin_fmaf(u.w, t.w, a2);
-          a3 = __builtin_fmaf(v3, t.x, a3); a3 = __builtin_fmaf(v2, t.y, a3);
-          a3 = __builtin_fmaf(v1, t.z, a3); a3 = __builtin_fmaf(v0, t.w, a3);
+          b0 = __builtin_fmaf(v0, t.x, b0); b0 = __builtin_fmaf(u.w, t.y, b0);
+          b0 = __builtin_fmaf(u.z, t.z, b0); b0 = __builtin_fmaf(u.y, t.w, b0);
+          b1 = __builtin_fmaf(v1, t.x, b1); b1 = __builtin_fmaf(v0, t.y, b1);
+          b1 = __builtin_fmaf(u.w, t.z, b1); b1 = __builtin_fmaf(u.z, t.w, b1);
+          b2 = __builtin_fmaf(v2, t.x, b2); b2 = __builtin_fmaf(v1, t.y, b2);
+          b2 = __builtin_fmaf(v0, t.z, b2); b2 = __builtin_fmaf(u.w, t.w, b2);
+          b3 = __builtin_fmaf(v3, t.x, b3); b3 = __builtin_fmaf(v2, t.y, b3);
+          b3 = __builtin_fmaf(v1, t.z, b3); b3 = __builtin_fmaf(v0, t.w, b3);
           v3 = u.w; v2 = u.z; v1 = u.y; v0 = u.x;
         }
+        a0 += b0;
+        a1 += b1;
+        a2 += b2;
+        a3 += b3;
       }
     }
   }
@@ -98,9 +118,12 @@ int launch_filter(const float *x, int n_x, const float *rir, int n_pos, int n_mi
                   hipStream_t st) {
   const int seg_len = (n_x + n_pos - 1) / n_pos;
   const int n_y = n_x + n_rir - 1;
-  const unsigned gx = (unsigned)((n_y + FN - 1) / FN);
-  hipLaunchKernelGGL(filter_kernel, dim3(gx, (unsigned)n_mic), dim3(FT), 0, st, x, n_x, rir, n_mic, n_rir, seg_len,
-                     y, n_y);
+  const int gx = (n_y + FN - 1) / FN;
+  if ((int64_t)gx * n_mic > (int64_t)0x7fffff00) return -2;  // block count beyond a grid dimension
+  const int G = gx * n_mic;
+  const int per_xcd = (G + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(filter_kernel, dim3((unsigned)(per_xcd * kXcds)), dim3(FT), 0, st, x, n_x, rir, n_mic, n_rir,
+                     seg_len, y, n_y, gx);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

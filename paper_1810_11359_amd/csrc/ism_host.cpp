@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <thread>
@@ -19,19 +20,20 @@
 namespace ism {
 int launch_tables(const RoomArgs &ra, const float *src, const float *rcv, const float *orient, AxisEntry *tab,
                   AxisOrigin *origin, int *valid, int n_rir, hipStream_t st);
-int launch_accumulate(int wt, bool half, bool lut, bool polar, const RoomArgs &ra, const PlanArgs &pa,
+int launch_accumulate(int wt, bool gen, bool half, bool lut, bool polar, const RoomArgs &ra, const PlanArgs &pa,
                       uint32_t n_items, const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *out,
-                      float *part, float *marg, hipStream_t st);
+                      float *part, float *marg, const float *wc, hipStream_t st);
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, const float *marg,
                   float *out, hipStream_t st);
-bool supported_window(int wt);
+bool supported_window(int wt, bool gen);
+int launch_window_consts(float W, int wt, bool half, float *wc, hipStream_t st);
 int launch_dump(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items, const AxisEntry *tab,
                 const AxisOrigin *origin, const int *valid, DumpArgs dump, hipStream_t st);
-int launch_batch(const JobDev *jobs, const BatchRir *rirs, uint32_t n_rir, const BatchItem *items,
-                 const uint32_t *class_first, const uint32_t *class_count, const int *class_wt, int n_classes,
-                 bool half, bool lut, bool polar, const BatchReduce *red, uint32_t n_red, AxisEntry *tab,
-                 AxisOrigin *origin, int *valid,
-                 float *part, float *marg, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
+int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
+                 const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
+                 const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
+                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
+                 float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
                    double t60, uint64_t seed, hipStream_t st);
 int launch_filter(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
@@ -43,6 +45,12 @@ using namespace ism;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+
+// A failed HIP runtime call: names it on stderr and maps it to ISM_E_DEVICE.
+int device_error(const char *where, hipError_t e) {
+  fprintf(stderr, "libism: %s: %s\n", where, hipGetErrorString(e));
+  return ISM_E_DEVICE;
+}
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -67,18 +75,39 @@ int even_window(const ism_room &r) {
   return (int)iw;
 }
 
+// Kernel class of a window of W = t_w fs samples (Eq. (6)): exact mode for an
+// even integer W in {32, 64, 96, 128} (cap WT = W), else general mode with
+// the cap WT = the next multiple of 32 (at least 32, at most MAX_WINDOW).
+int window_class(const ism_room &r, int &wt, bool &gen, double &W) {
+  W = r.t_w * r.fs;
+  const int ev = even_window(r);
+  if (ev == 32 || ev == 64 || ev == 96 || ev == 128) {
+    wt = ev;
+    gen = false;
+    W = ev;
+    return ISM_OK;
+  }
+  if (W > MAX_WINDOW * (1.0 + 1e-9)) return ISM_E_TOO_LARGE;
+  W = std::min(W, (double)MAX_WINDOW);
+  wt = std::max(32, 32 * (int)std::ceil(W / 32.0 - 1e-9));
+  gen = true;
+  return ISM_OK;
+}
+
 struct Plan {
   RoomArgs ra;
   PlanArgs pa;
   double tile_taps[MAX_TILES];  // estimated taps of each tile's image shell
   double total_taps;            // over all RIRs
-  int wt;
+  int wt;     // window cap WT (kernel layout)
+  bool gen;   // general-mode window (per-call tap constants)
+  double win; // W = t_w fs
   bool half;
   bool lut;  // table taps (Eq. (9)); FP32 arithmetic otherwise
   int n_rir;
   uint32_t n_items;
   bool any_split;
-  size_t off_valid, off_origin, off_tab, off_part, off_marg, off_pos, ws_bytes;
+  size_t off_valid, off_origin, off_tab, off_part, off_marg, off_wc, off_pos, ws_bytes;
 };
 
 // Work-item size in estimated taps. A launch should hold about balance_items
@@ -128,8 +157,10 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, c
     return precision == ISM_BF16 ? ISM_E_UNSUPPORTED : ISM_E_INVALID_ARG;
   p.half = precision == ISM_FP16;
   p.lut = precision == ISM_FP32_LUT;
-  p.wt = even_window(*r);
-  if (p.wt == 0 || !supported_window(p.wt)) return ISM_E_UNSUPPORTED;
+  st = window_class(*r, p.wt, p.gen, p.win);
+  if (st != ISM_OK) return st;
+  // table taps are built for the exact windows only
+  if (!supported_window(p.wt, p.gen) || (p.gen && p.lut)) return ISM_E_UNSUPPORTED;
   const int64_t nS = ism_n_samples(r->t_max, r->fs);
   const double W = (double)p.wt;
   const double q = r->fs / r->c;
@@ -150,13 +181,16 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, c
     off += r->n_img[a];
     ra.period[k] = (float)(2.0 * r->room[a] * q);
     ra.inv_period[k] = (float)(1.0 / (2.0 * r->room[a] * q));
-    ra.beta[2 * k] = (float)r->beta[2 * a];
-    ra.beta[2 * k + 1] = (float)r->beta[2 * a + 1];
+    split(r->beta[2 * a], ra.beta[2 * k], ra.beta_lo[2 * k]);
+    split(r->beta[2 * a + 1], ra.beta[2 * k + 1], ra.beta_lo[2 * k + 1]);
   }
   ra.n_tab = off;
   split(q, ra.q_hi, ra.q_lo);
   ra.kappa = (float)(r->fs / (4.0 * kPi * r->c));
   ra.half_w = (float)(W / 2.0);
+  ra.win_hw = (float)(p.win / 2.0);
+  ra.inv_win = (float)(1.0 / p.win);
+  ra.gen = p.gen ? 1 : 0;
   ra.n_samples = (int)nS;
   ra.k_end = (int)nS + p.wt / 2 - 1;
   ra.n_src = n_src;
@@ -217,8 +251,10 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, c
   p.off_tab = align_up(p.off_origin + sizeof(AxisOrigin) * (size_t)p.n_rir);
   p.off_part = align_up(p.off_tab + sizeof(AxisEntry) * (size_t)p.n_rir * ra.n_tab);
   p.off_marg = align_up(p.off_part + (p.any_split ? sizeof(float) * (size_t)p.n_items * TILE : 0));
+  // general-mode window constants
+  p.off_wc = align_up(p.off_marg + sizeof(float) * (size_t)p.n_items * p.wt);
   // host-position calls copy src then rcv here
-  p.off_pos = align_up(p.off_marg + sizeof(float) * (size_t)p.n_items * p.wt);
+  p.off_pos = align_up(p.off_wc + (p.gen ? sizeof(float) * WC_STRIDE * (size_t)p.wt : 0));
   p.ws_bytes = align_up(p.off_pos + sizeof(float) * 3 * ((size_t)n_src + (size_t)n_rcv));
   return ISM_OK;
 }
@@ -401,10 +437,12 @@ static int run_plan(const Plan &p, const float *src, const float *rcv, float *ou
   AxisEntry *tab = (AxisEntry *)(w + p.off_tab);
   float *part = p.any_split ? (float *)(w + p.off_part) : nullptr;
   float *marg = (float *)(w + p.off_marg);
+  float *wc = p.gen ? (float *)(w + p.off_wc) : nullptr;
   if (launch_tables(p.ra, src, rcv, orient, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
+  if (wc && launch_window_consts((float)p.win, p.wt, p.half, wc, s) != 0) return ISM_E_DEVICE;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, s) != hipSuccess) return ISM_E_DEVICE;
-  if (launch_accumulate(p.wt, p.half, p.lut, orient != nullptr, p.ra, p.pa, p.n_items, tab, origin, valid, out, part,
-                        marg, s) != 0)
+  if (launch_accumulate(p.wt, p.gen, p.half, p.lut, orient != nullptr, p.ra, p.pa, p.n_items, tab, origin, valid, out,
+                        part, marg, wc, s) != 0)
     return ISM_E_DEVICE;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, s) != hipSuccess) return ISM_E_DEVICE;
   // split tiles and the margins between neighbouring tiles
@@ -464,7 +502,10 @@ int ism_debug_enumerate(const ism_room *room, const float *src, int n_src, const
   int *valid = (int *)(w + p.off_valid);
   AxisOrigin *origin = (AxisOrigin *)(w + p.off_origin);
   AxisEntry *tab = (AxisEntry *)(w + p.off_tab);
-  if (launch_tables(p.ra, src, rcv, nullptr, tab, origin, valid, p.n_rir, s) != 0) return ISM_E_DEVICE;
+  if (launch_tables(p.ra, src, rcv, nullptr, tab, origin, valid, p.n_rir, s) != 0) {
+    fprintf(stderr, "ism_debug_enumerate: tables launch failed\n");
+    return ISM_E_DEVICE;
+  }
   DumpArgs d{(DumpRec *)records, count, cap};
   if (launch_dump(p.wt, p.ra, p.pa, p.n_items, tab, origin, valid, d, s) != 0) return ISM_E_DEVICE;
   return ISM_OK;
@@ -570,15 +611,16 @@ int ism_simulate_diffuse_polar(const ism_room *room, double t_diff, double t60, 
 
 namespace {
 
-constexpr int kMaxClasses = 4;
+constexpr int kMaxClasses = kMaxBatchClasses;
 
 struct BatchState {  // stored in ism_batch::opaque
   uint64_t ws;
-  uint64_t off_jobs, off_rirs, off_items, off_red, off_pos, off_valid, off_origin, off_tab, off_part, off_marg;
+  uint64_t off_jobs, off_rirs, off_items, off_red, off_pos, off_valid, off_origin, off_tab, off_part, off_marg,
+      off_queue, off_wc;
   uint32_t n_rir, n_red, n_classes, mode;  // mode: 0 FP32, 1 FP16, 2 table taps
-  uint32_t polar, pad;                      // 1: directional kernels
+  uint32_t polar, n_jobs, any_gen, pad;     // polar: directional kernels; any_gen: general-mode windows
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
-  int32_t class_wt[kMaxClasses];
+  int32_t class_wt[kMaxClasses], class_gen[kMaxClasses];
 };
 static_assert(sizeof(BatchState) <= sizeof(ism_batch), "ism_batch too small");
 
@@ -625,9 +667,9 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   // others take the pattern a = 1, b = 0, whose factor is exactly 1
   // pass 1: plans, window classes and counts
   int n_classes = 0;
-  int class_wt[kMaxClasses] = {0, 0, 0, 0};
+  int class_wt[kMaxClasses] = {}, class_gen[kMaxClasses] = {};
   std::vector<int> job_cls(n_jobs);
-  uint64_t tab_entries = 0, n_rir = 0, n_items = 0, slots = 0, n_red = 0;
+  uint64_t tab_entries = 0, n_rir = 0, n_items = 0, slots = 0, n_red = 0, marg_units = 0, wc_floats = 0;
   std::vector<uint64_t> bucket_count((size_t)kMaxClasses * kCostBuckets, 0);
   for (int j = 0; j < n_jobs; ++j) {
     Plan &p = plans[j];
@@ -635,16 +677,19 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     if (stt != ISM_OK) return stt;
     int cls = -1;
     for (int k = 0; k < n_classes; ++k)
-      if (class_wt[k] == p.wt) cls = k;
+      if (class_wt[k] == p.wt && class_gen[k] == (p.gen ? 1 : 0)) cls = k;
     if (cls < 0) {
       if (n_classes == kMaxClasses) return ISM_E_UNSUPPORTED;
       cls = n_classes++;
       class_wt[cls] = p.wt;
+      class_gen[cls] = p.gen ? 1 : 0;
     }
     job_cls[j] = cls;
+    if (p.gen) wc_floats += (uint64_t)WC_STRIDE * p.wt;
     for (int t = 0; t < p.pa.n_tiles; ++t) {
       const uint64_t C = p.pa.chunks[t];
       n_items += C * p.n_rir;
+      marg_units += C * p.n_rir * (uint64_t)(p.wt / MARG_UNIT);
       if (C > 1) slots += C * p.n_rir;
       bucket_count[(size_t)cls * kCostBuckets + cost_bucket(p.tile_taps[t] / C)] += C * p.n_rir;
     }
@@ -652,7 +697,8 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     tab_entries += (uint64_t)p.n_rir * p.ra.n_tab;
     n_rir += (uint64_t)p.n_rir;
   }
-  if (n_rir > 0x7fffffffULL || n_items > 0x7fffffffULL || slots > 0xffffffffULL || n_red > 0x7fffffffULL)
+  if (n_rir > 0x7fffffffULL || n_items > 0x7fffffffULL || slots > 0xffffffffULL || n_red > 0x7fffffffULL ||
+      marg_units > 0xffffffffULL)
     return ISM_E_TOO_LARGE;
   // item positions: classes in order, each class from its most expensive bucket down
   std::vector<uint64_t> bucket_next((size_t)kMaxClasses * kCostBuckets, 0);
@@ -665,7 +711,10 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     }
     bp.st.class_count[k] = (uint32_t)(acc - bp.st.class_first[k]);
     bp.st.class_wt[k] = class_wt[k];
+    bp.st.class_gen[k] = class_gen[k];
   }
+  bp.st.n_jobs = (uint32_t)n_jobs;
+  bp.st.any_gen = wc_floats > 0 ? 1u : 0u;
   bp.st.n_classes = (uint32_t)n_classes;
   bp.st.mode = precision == ISM_FP16 ? 1u : precision == ISM_FP32_LUT ? 2u : 0u;
   bp.st.polar = polar ? 1u : 0u;
@@ -698,7 +747,13 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   bp.st.off_part = o;
   o = align_up(o + sizeof(float) * (size_t)slots * TILE);
   bp.st.off_marg = o;
-  o = align_up(o + sizeof(float) * (size_t)n_items * MARG_STRIDE);
+  o = align_up(o + sizeof(float) * MARG_UNIT * (size_t)marg_units);
+  // work-queue counters of the persistent launches, one per window class
+  bp.st.off_queue = o;
+  o = align_up(o + sizeof(uint32_t) * kMaxClasses);
+  // general-mode window constants, one block per such job
+  bp.st.off_wc = o;
+  o = align_up(o + sizeof(float) * (size_t)wc_floats);
   bp.ws_bytes = o;
   if (!fill) return ISM_OK;
 
@@ -708,7 +763,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   bp.rirs.resize(n_rir);
   bp.items.resize(n_items);
   bp.red.resize(n_red);
-  uint64_t rir_base = 0, tab_base = 0, mslot = 0, red_i = 0;
+  uint64_t rir_base = 0, tab_base = 0, mslot = 0, red_i = 0, wc_base = 0;
   uint32_t slot = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const Plan &p = plans[j];
@@ -724,13 +779,19 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     d.orient = jb.orient;
     d.tab_base = tab_base;
     d.rir_base = (uint32_t)rir_base;
+    if (p.gen) {  // device address filled in by prepare_batch (ws base unknown here)
+      d.wc = (float *)(uintptr_t)(wc_base + 1);
+      wc_base += (uint64_t)WC_STRIDE * p.wt;
+    }
     for (int r = 0; r < p.n_rir; ++r) bp.rirs[rir_base + r] = BatchRir{(uint32_t)j, (uint32_t)r};
     const int nt = p.pa.n_tiles;
-    // first margin record of (tile t, RIR r) is mfirst_t + r * chunks[t]
+    // margin records (units of MARG_UNIT floats, wu units each): the first
+    // record of (tile t, RIR r) is mfirst_t + r * chunks[t] * wu
+    const uint64_t wu = (uint64_t)(p.wt / MARG_UNIT);
     std::vector<uint64_t> mfirst(nt);
     for (int t = 0; t < nt; ++t) {
       mfirst[t] = mslot;
-      mslot += (uint64_t)p.pa.chunks[t] * p.n_rir;
+      mslot += (uint64_t)p.pa.chunks[t] * p.n_rir * wu;
     }
     for (int t = 0; t < nt; ++t) {
       const int C = p.pa.chunks[t];
@@ -744,17 +805,17 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
         rd.chunks = (uint16_t)C;
         rd.first = C > 1 ? slot : 0xffffffffu;
         if (t > 0) {
-          rd.mprev = (uint32_t)(mfirst[t - 1] + (uint64_t)r * p.pa.chunks[t - 1]);
+          rd.mprev = (uint32_t)(mfirst[t - 1] + (uint64_t)r * p.pa.chunks[t - 1] * wu);
           rd.nprev = p.pa.chunks[t - 1];
         }
         if (t + 1 < nt) {
-          rd.mnext = (uint32_t)(mfirst[t + 1] + (uint64_t)r * p.pa.chunks[t + 1]);
+          rd.mnext = (uint32_t)(mfirst[t + 1] + (uint64_t)r * p.pa.chunks[t + 1] * wu);
           rd.nnext = p.pa.chunks[t + 1];
         }
         for (int c = 0; c < C; ++c)
           bp.items[pos++] = BatchItem{(uint32_t)j, (uint32_t)r, (uint16_t)t, (uint8_t)c, (uint8_t)C,
                                       C > 1 ? slot + (uint32_t)c : 0xffffffffu,
-                                      (uint32_t)(mfirst[t] + (uint64_t)r * C + c)};
+                                      (uint32_t)(mfirst[t] + ((uint64_t)r * C + c) * wu)};
         if (C > 1) slot += (uint32_t)C;
       }
     }
@@ -828,13 +889,17 @@ int prepare_batch(const ism_job *jobs, int n_jobs, int precision, const ism_sche
       }
     }
   }
+  for (JobDev &d : bp.jobs)  // general-mode window constants: offsets into ws
+    if (d.wc) d.wc = (float *)((char *)ws + bp.st.off_wc) + ((uintptr_t)d.wc - 1);
   std::memcpy(host + bp.st.off_jobs, bp.jobs.data(), sizeof(JobDev) * bp.jobs.size());
   std::memcpy(host + bp.st.off_rirs, bp.rirs.data(), sizeof(BatchRir) * bp.rirs.size());
   std::memcpy(host + bp.st.off_items, bp.items.data(), sizeof(BatchItem) * bp.items.size());
   if (!bp.red.empty()) std::memcpy(host + bp.st.off_red, bp.red.data(), sizeof(BatchReduce) * bp.red.size());
   hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(ws, host, bp.st.off_valid, hipMemcpyHostToDevice, s) != hipSuccess) return ISM_E_DEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return ISM_E_DEVICE;
+  hipError_t e = hipMemcpyAsync(ws, host, bp.st.off_valid, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return device_error("batch tables upload", e);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return device_error("batch tables upload (synchronize)", e);
   bp.st.ws = (uint64_t)(uintptr_t)ws;
   std::memset(batch, 0, sizeof(*batch));
   std::memcpy(batch, &bp.st, sizeof(bp.st));
@@ -867,13 +932,14 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
   std::memcpy(&b, batch, sizeof(b));
   if (!b.ws || b.n_rir == 0 || b.n_classes == 0 || b.n_classes > (uint32_t)kMaxClasses) return ISM_E_INVALID_ARG;
   char *w = (char *)(uintptr_t)b.ws;
-  const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (const BatchRir *)(w + b.off_rirs), b.n_rir,
+  const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (int)b.n_jobs, b.any_gen != 0,
+                              (const BatchRir *)(w + b.off_rirs), b.n_rir,
                               (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_wt,
-                              (int)b.n_classes, b.mode == 1, b.mode == 2, b.polar != 0,
+                              b.class_gen, (int)b.n_classes, b.mode == 1, b.mode == 2, b.polar != 0,
                               (const BatchReduce *)(w + b.off_red), b.n_red,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
                               (int *)(w + b.off_valid), (float *)(w + b.off_part), (float *)(w + b.off_marg),
-                              (hipStream_t)stream,
+                              (uint32_t *)(w + b.off_queue), (hipStream_t)stream,
                               (hipEvent_t)ev_start, (hipEvent_t)ev_stop);
   return rc == 0 ? ISM_OK : ISM_E_DEVICE;
 }
@@ -886,6 +952,8 @@ int ism_filter_trajectory(const float *x, int n_x, const float *rir, int n_pos, 
   if (!x || !rir || !y) return ISM_E_INVALID_ARG;
   if (n_x < 1 || n_pos < 1 || n_mic < 1 || n_rir < 1 || n_pos > n_x) return ISM_E_INVALID_ARG;
   if (n_mic > 65535 || (int64_t)n_x + n_rir - 1 > (int64_t)0x7fffffff) return ISM_E_TOO_LARGE;
-  if (launch_filter(x, n_x, rir, n_pos, n_mic, n_rir, y, (hipStream_t)stream) != 0) return ISM_E_DEVICE;
+  const int rc = launch_filter(x, n_x, rir, n_pos, n_mic, n_rir, y, (hipStream_t)stream);
+  if (rc == -2) return ISM_E_TOO_LARGE;
+  if (rc != 0) return ISM_E_DEVICE;
   return ISM_OK;
 }

@@ -15,8 +15,20 @@ constexpr int TILE = 256;
 constexpr int MAX_TILES = 1025;
 // Dispatch positions per block of the plan's coarse first-item table.
 constexpr int PLAN_BLK = 16;
-// Stride of one work item's margin record in batch mode (the largest window).
-constexpr int MARG_STRIDE = 128;
+// Batch margin records are addressed in units of MARG_UNIT floats (window caps
+// are multiples of it); a record of a job with window cap WT holds WT floats.
+constexpr int MARG_UNIT = 32;
+// Window caps: the kernels are built for caps WT = 32, 64, ..., 256 samples.
+// An even integer window W in {32, 64, 96, 128} runs with compile-time tap
+// constants (exact mode); any other W <= 256 runs with the next cap and
+// per-call constants, masking the taps outside |j - f| < W/2 (general mode).
+constexpr int MAX_WINDOW = 256;
+// Per-tap constants of a general-mode window, 8 floats per tap jj of the cap:
+// FP32 taps (-sigma 2^-32, sigma j, cos(2 pi j / W), sin(2 pi j / W), 0 ...),
+// FP16 taps (c0, c1, ..., c5, 0, 0) of the tap's interpolant.
+constexpr int WC_STRIDE = 8;
+// Window classes (cap, mode) one batch may hold: one persistent launch each.
+constexpr int kMaxBatchClasses = 8;
 // Work items per tile are capped so the per-tile chunk count fits a byte.
 constexpr int MAX_CHUNKS = 255;
 // Waves per SIMD the accumulate kernels are built for (their LDS and VGPR
@@ -32,14 +44,18 @@ constexpr int kAccWavesPerSimd = 7;
 struct RoomArgs {
   int perm[3];             // room axis of each table axis
   float L_hi[3], L_lo[3];  // room size
-  float beta[6];           // x0, x1, y0, y1, z0, z1
+  float beta[6];           // x0, x1, y0, y1, z0, z1 (high part of a float-float pair)
+  float beta_lo[6];        // low parts: beta = beta + beta_lo to about 48 bits
   int lo[3];               // first lattice index ceil(-N/2) per axis
   int N[3];                // lattice size per axis
   int off[3];              // offset of each axis in the per-RIR table
   int n_tab;               // Nx + Ny + Nz
   float q_hi, q_lo;        // fs / c [samples per metre]
   float kappa;             // fs / (4 pi c): A = gain * kappa / x with x in samples
-  float half_w;            // W / 2
+  float half_w;            // WT / 2, WT the window cap (layout of tiles and margins)
+  float win_hw;            // W / 2, W = t_w fs the window [samples]
+  float inv_win;           // 1 / W
+  int gen;                 // 1: general-mode window (per-call tap constants, masked taps)
   int n_samples;           // nS
   int k_end;               // nS + W/2 - 1: images with k0 >= k_end add nothing
   int n_src, n_rcv;
@@ -85,6 +101,7 @@ struct JobDev {
   const float *rcv;
   float *out;
   const float *orient;  // receiver orientations, or null (omnidirectional)
+  float *wc;            // general-mode window constants [WT][WC_STRIDE], or null
   uint64_t tab_base;    // first table entry of the job's first RIR
   uint32_t rir_base;    // batch-wide index of the job's first RIR
   uint32_t pad;
@@ -97,7 +114,7 @@ struct BatchRir {
 
 // One work item of a batch (same meaning as in single-room mode). slot is the
 // partial tile written when the tile is split (chunks > 1), else 0xffffffff;
-// mslot is its margin record (MARG_STRIDE floats).
+// mslot is the offset of its margin record in units of MARG_UNIT floats.
 struct BatchItem {
   uint32_t job, rir;
   uint16_t tile;
@@ -108,7 +125,8 @@ struct BatchItem {
 
 // One output tile of a batch RIR: its own partials (slots first ..
 // first + chunks - 1 when chunks > 1) and the margin records of the items of
-// the previous and next tile (mprev .. mprev + nprev - 1, mnext .. mnext + nnext - 1;
+// the previous and next tile (nprev records from offset mprev, nnext from
+// mnext, in units of MARG_UNIT floats, consecutive records WT floats apart;
 // counts are 0 where there is no such tile).
 struct BatchReduce {
   uint32_t job, rir;

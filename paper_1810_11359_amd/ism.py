@@ -102,6 +102,11 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(python -m paper_1810_11359_amd.build)")
+        # torch first: its HIP runtime is then the one the library binds to, so
+        # both share one runtime (devices, streams, memory). Loaded the other
+        # way round, the process can end up with two runtimes, and the
+        # library's sees no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         dp, ip, fp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p
         rp = ctypes.POINTER(_Room)

@@ -187,8 +187,11 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
 
     def footprint(self, job: Job) -> int:
+        """Device bytes the job holds while in flight: its output and its
+        share of the batch workspace (``ism_batch_workspace_size`` of the job
+        alone; the tables of a group, padded per job here, take no more)."""
         out = job.n_rirs * job.room.n_samples * 4
-        return out + self.ism.workspace_size(job.room, job.src.shape[0], job.rcv.shape[0])
+        return out + self.ism.batch_workspace_size([(job.room, job.src.shape[0], job.rcv.shape[0])])
 
     def launch(self, jobs: List[Job], slot: int):
         torch = self.torch

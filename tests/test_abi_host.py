@@ -108,9 +108,16 @@ def test_room_ok_and_workspace():
     assert e.value.status == ism.ISM_E_INVALID_ARG
 
 
-def test_unsupported_requests():
+def test_window_classes_and_unsupported_requests():
+    # any window up to 256 samples plans (general mode above the exact windows)
+    for t_w in (0.0041, 0.002, 0.0005, 0.016):  # W = 65.6, 32 (exact), 8, 256
+        assert ism.workspace_size(_room(t_w=t_w), 1, 1) > 0
+        assert ism.workspace_size(_room(t_w=t_w), 1, 1, precision="fp16") > 0
     with pytest.raises(ism.IsmError) as e:
-        ism.workspace_size(_room(t_w=0.0041), 1, 1)  # W = 65.6 samples
+        ism.workspace_size(_room(t_w=0.0161), 1, 1)  # W = 257.6 > 256
+    assert e.value.status == ism.ISM_E_TOO_LARGE
+    with pytest.raises(ism.IsmError) as e:  # table taps: exact windows only
+        ism.workspace_size(_room(t_w=0.0041), 1, 1, precision="lut")
     assert e.value.status == ism.ISM_E_UNSUPPORTED
     with pytest.raises(ism.IsmError) as e:
         ism.workspace_size(_room(), 1, 1, precision="bf16")

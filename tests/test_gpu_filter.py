@@ -65,3 +65,44 @@ def test_trajectory_end_to_end(oracle_mod):
     err = np.max(np.abs(y.cpu().numpy() - ref)) / np.max(np.abs(ref))
     print("trajectory rel err", err)
     assert err <= 1e-5
+
+
+def test_filter_96000_tap_rirs_sampled(oracle_mod):
+    """The moving-source size of a 48 kHz, T60 = 2 s room: 10 s of signal
+    (480 000 samples) through 100 trajectory points to 8 microphones with
+    RIRs of 96 000 taps (decaying noise in place of simulated RIRs). The
+    oracle computes sampled outputs one by one from the definition (the
+    segment boundaries, both ends and random samples); errors are divided by
+    the largest sampled oracle output. Tolerance: each output adds 96 000 FP32
+    products, whose rounding errors add up like a random walk: about
+    u sqrt(n) of the output's size for one running sum (u = 2^-24; 1.9e-5 at
+    n = 96 000). The kernel sums 64 products at a time and then the partial
+    sums, which cuts that to about u (8 + sqrt(n / 64)) = 2.8e-6; the bound
+    is four times the plain running sum's, 4 u sqrt(n) = 7.4e-5."""
+    import torch
+
+    n_x, n_pos, n_mic, n_rir = 480000, 100, 8, 96000
+    rng = np.random.default_rng(96)
+    x = rng.standard_normal(n_x).astype(np.float32)
+    env = np.exp(-np.arange(n_rir) / 14000.0).astype(np.float32)
+    rirs = torch.empty((n_pos, n_mic, n_rir), dtype=torch.float32, device="cuda")
+    for p in range(n_pos):  # fill point by point to keep host memory small
+        rirs[p] = torch.from_numpy((rng.standard_normal((n_mic, n_rir)).astype(np.float32) * env)).cuda()
+    host = rirs.cpu().numpy()
+    print("[case] 96000-tap filter", flush=True)
+    y = ism.filter_trajectory(torch.from_numpy(x).cuda(), rirs)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    seg = -(-n_x // n_pos)
+    n_y = n_x + n_rir - 1
+    picks = np.unique(np.concatenate([
+        [0, 1, n_x - 1, n_x, n_y - 2, n_y - 1],
+        np.arange(1, n_pos) * seg - 1, np.arange(1, n_pos) * seg,
+        rng.integers(0, n_y, 200)]))
+    err, peak = 0.0, 0.0
+    for m in (0, 3, 7):
+        ref = oracle_mod.filter_samples(x, host, m, picks)
+        err = max(err, float(np.max(np.abs(got[m, picks] - ref))))
+        peak = max(peak, float(np.max(np.abs(ref))))
+    print("96000-tap filter: max err / max sampled |y| =", err / peak, flush=True)
+    assert err <= 4.0 * 2.0 ** -24 * np.sqrt(n_rir) * peak

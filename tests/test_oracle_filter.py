@@ -54,3 +54,15 @@ def test_ragged_last_segment_and_linearity(oracle_mod):
     x = np.zeros(n_x)
     x[-1] = 1.0
     np.testing.assert_array_equal(oracle_mod.filter_trajectory(x, rirs)[:, n_x - 1:], rirs[4])
+
+
+def test_filter_samples_equal_the_whole_filter(oracle_mod):
+    """The one-by-one outputs used at sizes where the whole filter is too slow
+    agree with the overlap-add of the whole signal at every output sample."""
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(997)
+    rirs = rng.standard_normal((9, 2, 140))
+    y = oracle_mod.filter_trajectory(x, rirs)
+    n = np.arange(y.shape[1])
+    for m in range(2):
+        np.testing.assert_allclose(oracle_mod.filter_samples(x, rirs, m, n), y[m], rtol=0, atol=1e-12)
