@@ -352,6 +352,26 @@ int ism_batch_prepare_ex(const ism_job *jobs, int n_jobs, int precision, const i
  * bytes of the same jobs. Results are those of ism_batch_run. */
 int ism_simulate_batch(const ism_job *jobs, int n_jobs, int precision, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Without allocation --------------------------------------------------------- */
+
+/* Size of the device array ism_simulate_noalloc uses as its workspace: 64 MiB
+ * (the 32-receiver, 0.7 s, 16 kHz room of 4 x 5 x 3 m needs 38 MiB). */
+#define ISM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/* ism_simulate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * workspace argument; the call uses a fixed array of
+ * ISM_NOALLOC_SCRATCH_BYTES in the library's device memory instead (one per
+ * GPU, held until the process ends, looked up once per device). It calls no
+ * allocating routine. Same arguments (device positions), results and checks as
+ * ism_simulate; a call whose ism_workspace_size exceeds the array returns
+ * ISM_E_TOO_LARGE before any launch. Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other streams, other host threads)
+ * race: order them, e.g. on one stream. Nothing in the array needs clearing
+ * between calls (every byte read is written earlier in the same call). */
+int ism_simulate_noalloc(const ism_room *room, const float *src, int n_src, const float *rcv, int n_rcv,
+                         int precision, float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

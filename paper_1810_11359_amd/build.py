@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libism.so")
 SOURCES = [os.path.join(CSRC, "ism_device.hip"), os.path.join(CSRC, "ism_diffuse.hip"),
-           os.path.join(CSRC, "ism_filter.hip"), os.path.join(CSRC, "ism_host.cpp")]
+           os.path.join(CSRC, "ism_filter.hip"), os.path.join(CSRC, "ism_noalloc.hip"),
+           os.path.join(CSRC, "ism_host.cpp")]
 HEADERS = [os.path.join(CSRC, "ism_internal.h"), os.path.join(ROOT, "include", "ism.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -38,6 +38,7 @@ EXPORTS = (
     "ism_diffuse_workspace_size", "ism_simulate_diffuse", "ism_simulate_diffuse_timed",
     "ism_filter_trajectory", "ism_workspace_size_ex", "ism_simulate_ex", "ism_simulate_host",
     "ism_batch_workspace_size_ex", "ism_batch_prepare_ex", "ism_simulate_batch", "ism_debug_enumerate",
+    "ism_simulate_noalloc",
 )
 
 
@@ -179,6 +180,8 @@ def lib() -> ctypes.CDLL:
         L.ism_debug_enumerate.restype = ctypes.c_int
         L.ism_debug_enumerate.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, sp, fp, ctypes.c_uint32, fp, fp,
                                           ctypes.c_size_t, fp]
+        L.ism_simulate_noalloc.restype = ctypes.c_int
+        L.ism_simulate_noalloc.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp]
         L.ism_simulate_diffuse_timed.restype = ctypes.c_int
         L.ism_simulate_diffuse_timed.argtypes = [rp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, fp,
                                                  ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp, ctypes.c_size_t,
