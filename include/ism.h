@@ -131,6 +131,8 @@ typedef struct {
   double tail_rounds;   /* single calls: the items dispatched once less than this many
                            rounds of resident waves of work remain are cut smaller so
                            the launch ends evenly; 0 = no taper, < 0 = default (1)    */
+  double batch_waves;   /* batches: workgroups per SIMD of each persistent launch
+                           (1 .. 16; the grid is 1024 times this); 0 = tuned value */
 } ism_schedule;
 
 /* ---- GPU simulation -------------------------------------------------------------- */

@@ -1,15 +1,23 @@
-"""Work-item schedule tuner. Run it on the target GPU:
+"""Work-schedule tuner. Run it on the target GPU:
 
     python -m paper_1810_11359_amd.autotune --out paper_1810_11359_amd/csrc/ism_tuning.h
 
-For every window length W (32, 64, 96, 128 samples) and tap precision it times
-the tap-accumulation kernel (HIP events the library records around it) on
-representative workloads over a grid of (min_item_taps, balance_items) pairs,
-keeps the pair with the best geometric-mean time relative to each workload's
-fastest pair, and writes the table header the host planner compiles in.
-Rebuild the library afterwards. The candidate values reach the planner as
-the call's explicit schedule (``ism_schedule``: min_item_taps,
-balance_items).
+For every window length W (32, 64, 96, 128 samples), tap precision and RIR
+length bucket (up to 8192, 32768 and more samples) it times the
+tap-accumulation kernel (HIP events the library records around it) on
+representative single-room and batch workloads of that bucket over a grid of
+(min_item_taps, balance_items) pairs and keeps the pair with the best
+geometric-mean time relative to each workload's fastest pair. For the
+persistent batch launches of W = 64 it also picks the workgroups per SIMD of
+the grid. It writes the table header the host planner compiles in; rebuild
+the library afterwards. Candidate values reach the library as the call's
+explicit schedule (``ism_schedule``).
+
+The kernel's compile-time shape (256-sample tiles, two images per step,
+seven waves per SIMD) is not a knob here: 512-sample tiles (five waves per
+SIMD) and four images per step were built and timed on the 1024-room batch,
+the 32-receiver room, the 64-microphone 48 kHz room and a single RIR, and
+were no faster anywhere (the timings are in the design notes).
 """
 from __future__ import annotations
 
@@ -26,6 +34,8 @@ from . import ism, workloads
 
 MIN_TAPS = (6.0e4, 1.2e5, 2.4e5, 4.8e5)
 BALANCE = (24576.0, 49152.0, 98304.0, 196608.0)
+NS_BUCKETS = (8192, 32768, 2147483647)   # RIR length buckets (samples), upper bounds
+BATCH_WAVES = (4, 5, 6, 7, 8)
 
 
 class _Events:
@@ -60,20 +70,31 @@ def _feasible(room, t60):
         return False
 
 
-def class_workloads(wt: int):
-    """Representative single-room and batch workloads for one window length."""
-    base = workloads.room_32_receivers(0)
-    if wt == 32:
-        return [("room_4x5x3_32rcv_8k", [replace(base, fs=8000.0)])]
+def _room(L, t60, fs, t_w, n_rcv, seed=0):
+    rng = np.random.default_rng(seed)
+    L = np.asarray(L, dtype=float)
+    src = rng.uniform(0.5, L - 0.5, (1, 3)).astype(np.float32)
+    rcv = rng.uniform(0.5, L - 0.5, (n_rcv, 3)).astype(np.float32)
+    return workloads.Workload(f"room_{L[0]:g}x{L[1]:g}x{L[2]:g}_t60_{t60:g}_{n_rcv}rcv_{fs / 1000:g}k", L, t60, src,
+                              rcv, fs=fs, t_max=t60, t_w=t_w)
+
+
+def bucket_workloads(wt: int, ns_max: int):
+    """Representative workloads of one window length and RIR length bucket:
+    (name, [workloads]); several workloads form one batch."""
+    fs, t_w = {32: (8000.0, 0.004), 64: (16000.0, 0.004), 96: (48000.0, 0.002), 128: (32000.0, 0.004)}[wt]
+    ns_lo = {8192: 0, 32768: 8192}.get(ns_max, 32768)
+    if ns_lo > 2.5 * fs:
+        return []  # RIRs longer than 2.5 s at this rate: the previous bucket's entry is reused
+    # T60 (= T_max) in the middle of the bucket (RIRs up to 2.5 s) and the room it is run in
+    t_mid = (ns_lo + min(ns_max, 2.5 * fs)) / 2.0 / fs
+    out = [(f"room_t60_{t_mid:.2f}_{fs / 1000:g}k", [_room([4.0, 5.0, 3.0], t_mid, fs, t_w, 16 if t_mid < 1.0 else 4)])]
     if wt == 64:
-        return [("room_4x5x3_32rcv_16k", [base]),
-                ("batch_256_rooms_16k", workloads.batch_rooms(256, seed=0, feasible=_feasible))]
-    if wt == 96:
-        return [("room_6x9x3.5_uca64_48k", [workloads.large_room_uca(0)])]
-    if wt == 128:
-        w = replace(base, fs=32000.0, t60=0.5, t_max=0.5, rcv=base.rcv[:16])
-        return [("room_4x5x3_16rcv_32k", [w])]
-    raise ValueError(wt)
+        rooms = workloads.batch_rooms(256, seed=0, feasible=_feasible)
+        sel = [w for w in rooms if ns_lo < w.t_max * fs <= ns_max]
+        if sel:
+            out.append((f"batch_{len(sel)}_rooms_16k", sel))
+    return out
 
 
 def time_kernel(ws, precision: str, ev: _Events, reps: int, schedule=None) -> float:
@@ -98,48 +119,78 @@ def time_kernel(ws, precision: str, ev: _Events, reps: int, schedule=None) -> fl
     return float(np.mean(t))
 
 
+def _score(times, n_loads):
+    best_each = [min(t[i] for t in times.values()) for i in range(n_loads)]
+    return {k: math.exp(np.mean([math.log(t / b) for t, b in zip(v, best_each)])) for k, v in times.items()}
+
+
 def tune(reps: int = 3, classes=(32, 64, 96, 128), precisions=("fp32", "fp16"), log=print):
+    """Returns ({(wt, prec, ns_max): (best pair, scores, times, names)},
+    {(wt, prec): (best waves, scores)})."""
     ev = _Events()
-    results = {}
+    results, waves = {}, {}
     for wt in classes:
-        loads = class_workloads(wt)
         for prec in precisions:
-            times = {}
-            for mt in MIN_TAPS:
-                for bal in BALANCE:
-                    sc = ism.Schedule(min_item_taps=mt, balance_items=bal)
-                    times[(mt, bal)] = [time_kernel(ws, prec, ev, reps, sc) for _, ws in loads]
-                    log(f"W={wt} {prec} min_item_taps={mt:g} balance_items={bal:g}: "
-                        + ", ".join(f"{name} {t:.3f} ms" for (name, _), t in zip(loads, times[(mt, bal)])))
-            best_each = [min(t[i] for t in times.values()) for i in range(len(loads))]
-            score = {k: math.exp(np.mean([math.log(t / b) for t, b in zip(v, best_each)])) for k, v in times.items()}
-            best = min(score, key=score.get)
-            results[(wt, prec)] = (best, score, times, [n for n, _ in loads])
-            log(f"W={wt} {prec}: best min_item_taps={best[0]:g} balance_items={best[1]:g} "
-                f"(score {score[best]:.4f}; default pair {score[(1.2e5, 49152.0)]:.4f})")
-    return results
+            prev = None
+            for ns_max in NS_BUCKETS:
+                loads = bucket_workloads(wt, ns_max)
+                if not loads:
+                    results[(wt, prec, ns_max)] = prev
+                    continue
+                times = {}
+                for mt in MIN_TAPS:
+                    for bal in BALANCE:
+                        sc = ism.Schedule(min_item_taps=mt, balance_items=bal)
+                        times[(mt, bal)] = [time_kernel(ws, prec, ev, reps, sc) for _, ws in loads]
+                        log(f"W={wt} {prec} nS<={ns_max} min_item_taps={mt:g} balance_items={bal:g}: "
+                            + ", ".join(f"{name} {t:.3f} ms" for (name, _), t in zip(loads, times[(mt, bal)])))
+                score = _score(times, len(loads))
+                best = min(score, key=score.get)
+                results[(wt, prec, ns_max)] = prev = (best, score, times, [n for n, _ in loads])
+                log(f"W={wt} {prec} nS<={ns_max}: best min_item_taps={best[0]:g} balance_items={best[1]:g} "
+                    f"(score {score[best]:.4f}; default pair {score[(1.2e5, 49152.0)]:.4f})")
+            if wt == 64:
+                batch = workloads.batch_rooms(1024, seed=0, feasible=_feasible)
+                t = {k: [time_kernel(batch, prec, ev, reps, ism.Schedule(batch_waves=k))] for k in BATCH_WAVES}
+                sc = _score(t, 1)
+                waves[(wt, prec)] = (min(sc, key=sc.get), sc)
+                log(f"W={wt} {prec} batch waves per SIMD: " + ", ".join(f"{k}: {t[k][0]:.3f} ms" for k in t))
+    return results, waves
 
 
-def write_header(results, path: str, device: str) -> None:
+def write_header(results, waves, path: str, device: str) -> None:
     lines = [
-        "// Work-item schedule per window length and tap precision, read by the host",
-        "// planner. Written by paper_1810_11359_amd/autotune.py from timings on the",
-        f"// target GPU ({device}).",
+        "// Work-item schedule per window length, tap precision and RIR length, read by",
+        "// the host planner, and the grid of the persistent batch launch. Written by",
+        f"// paper_1810_11359_amd/autotune.py from timings on the target GPU ({device}).",
         "//   min_item_taps  estimated taps of the smallest work item",
         "//   balance_items  items a large call is split into (about eight per",
         "//                  resident wave), which sets the item size of large calls",
+        "//   ns_max         the entry applies to RIRs of at most this many samples",
+        "//                  (first match in table order)",
+        "//   waves          workgroups per SIMD of a persistent batch launch",
         "//",
-        "// Score: geometric mean over the class's workloads of kernel time relative",
+        "// Score: geometric mean over the bucket's workloads of kernel time relative",
         "// to the fastest pair on that workload (1.0 = fastest everywhere).",
     ]
-    for (wt, prec), (best, score, times, names) in sorted(results.items()):
-        lines.append(f"// W={wt} {prec} ({', '.join(names)}): best {best[0]:g} / {best[1]:g}, "
+    for (wt, prec, ns_max), (best, score, times, names) in sorted(results.items()):
+        lines.append(f"// W={wt} {prec} nS<={ns_max} ({', '.join(names)}): best {best[0]:g} / {best[1]:g}, "
                      f"score {score[best]:.4f}, default 1.2e5 / 49152 score {score[(1.2e5, 49152.0)]:.4f}")
+    for (wt, prec), (best, sc) in sorted(waves.items()):
+        lines.append(f"// W={wt} {prec} batch: best {best} waves per SIMD, "
+                     + ", ".join(f"{k}: {v:.4f}" for k, v in sorted(sc.items())))
     lines += ["#pragma once", "", "namespace ism {", "", "struct ItemTuning {",
-              "  int wt;        // window length in samples", "  int half;      // 1: FP16 taps, 0: FP32 taps",
-              "  double min_item_taps;", "  double balance_items;", "};", "", "constexpr ItemTuning kItemTuning[] = {"]
-    for (wt, prec), (best, _, _, _) in sorted(results.items()):
-        lines.append(f"    {{{wt}, {1 if prec == 'fp16' else 0}, {best[0]:.6g}, {best[1]:.1f}}},")
+              "  int wt;        // window cap in samples", "  int half;      // 1: FP16 taps, 0: FP32 taps",
+              "  int ns_max;    // RIR length bucket (samples)", "  double min_item_taps;", "  double balance_items;",
+              "};", "", "struct BatchTuning {", "  int wt;", "  int half;", "  int waves;", "};", "",
+              "constexpr ItemTuning kItemTuning[] = {"]
+    for (wt, prec, ns_max), (best, _, _, _) in sorted(results.items()):
+        lines.append(f"    {{{wt}, {1 if prec == 'fp16' else 0}, {ns_max}, {best[0]:.6g}, {best[1]:.1f}}},")
+    lines += ["};", "", "constexpr BatchTuning kBatchTuning[] = {"]
+    for (wt, prec), (best, _) in sorted(waves.items()):
+        lines.append(f"    {{{wt}, {1 if prec == 'fp16' else 0}, {best}}},")
+    if not waves:
+        lines.append("    {0, 0, 0},")
     lines += ["};", "", "}  // namespace ism", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))
@@ -155,8 +206,8 @@ def main(argv=None) -> int:
     if not torch.cuda.is_available():
         print("autotune needs a GPU", file=sys.stderr)
         return 2
-    results = tune(args.reps, log=lambda s: print(s, flush=True))
-    write_header(results, args.out, torch.cuda.get_device_name(0))
+    results, waves = tune(args.reps, log=lambda s: print(s, flush=True))
+    write_header(results, waves, args.out, torch.cuda.get_device_name(0))
     print(f"wrote {args.out}; rebuild the library to use it", flush=True)
     return 0
 

@@ -1466,18 +1466,14 @@ int launch_accumulate(int wt, bool gen, bool half, bool lut, bool polar, const R
   });
 }
 
-// Workgroups of a persistent batch launch: the waves resident at once
-// (256 CUs x 4 SIMDs x the waves per SIMD the kernel is built for).
-constexpr uint32_t kBatchGrid = 256u * 4u * (uint32_t)kAccWavesPerSimd;
-uint32_t batch_grid(uint32_t n_items) { return n_items < kBatchGrid ? n_items : kBatchGrid; }
-
+// grid: workgroups of the persistent launch (at most n_items; the planner
+// sizes it from the tuned workgroups per SIMD).
 template <int WT, bool HALF, bool LUT, bool POLAR, bool GEN>
-static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, uint32_t *queue,
-                              const AxisEntry *tab, const AxisOrigin *origin, const int *valid, float *part,
-                              float *marg, hipStream_t st) {
+static int launch_acc_batch_w(const JobDev *jobs, const BatchItem *items, uint32_t n_items, uint32_t grid,
+                              uint32_t *queue, const AxisEntry *tab, const AxisOrigin *origin, const int *valid,
+                              float *part, float *marg, hipStream_t st) {
   hipLaunchKernelGGL((accumulate_batch_kernel<WT, HALF, images_per_step(WT, HALF), LUT, POLAR, GEN>),
-                     dim3(batch_grid(n_items)), dim3(64), 0, st, jobs, items, n_items, queue, tab, origin, valid,
-                     part, marg);
+                     dim3(grid), dim3(64), 0, st, jobs, items, n_items, queue, tab, origin, valid, part, marg);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1489,7 +1485,7 @@ __global__ void queue_init_kernel(uint32_t *queue, uint4 a, uint4 b) {
 
 int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
                  const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
-                 const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
+                 const uint32_t *class_grid, const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
                  const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
                  float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
@@ -1500,7 +1496,7 @@ int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *r
   }
   if (queue) {
     uint32_t fp[kMaxBatchClasses] = {};
-    for (int k = 0; k < n_classes && k < kMaxBatchClasses; ++k) fp[k] = batch_grid(class_count[k]);
+    for (int k = 0; k < n_classes && k < kMaxBatchClasses; ++k) fp[k] = class_grid[k];
     hipLaunchKernelGGL(queue_init_kernel, dim3(1), dim3(64), 0, st, queue, make_uint4(fp[0], fp[1], fp[2], fp[3]),
                        make_uint4(fp[4], fp[5], fp[6], fp[7]));
     if (hipGetLastError() != hipSuccess) return -1;
@@ -1514,8 +1510,9 @@ int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *r
                                    [&](auto W, auto H, auto L, auto P, auto G) -> int {
                                      return launch_acc_batch_w<decltype(W)::value, decltype(H)::value,
                                                                decltype(L)::value, decltype(P)::value,
-                                                               decltype(G)::value>(jobs, it, class_count[k], qk, tab,
-                                                                                   origin, valid, part, marg, st);
+                                                               decltype(G)::value>(jobs, it, class_count[k],
+                                                                                   class_grid[k], qk, tab, origin,
+                                                                                   valid, part, marg, st);
                                    });
     if (rc != 0) return -1;
   }

@@ -31,7 +31,7 @@ int launch_dump(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items
                 const AxisOrigin *origin, const int *valid, DumpArgs dump, hipStream_t st);
 int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
                  const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
-                 const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
+                 const uint32_t *class_grid, const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
                  const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
                  float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
@@ -117,12 +117,13 @@ struct Plan {
 // call's schedule (ism_schedule) replaces them.
 constexpr double kMinItemTaps = 1.2e5;
 constexpr double kBalanceItems = 49152.0;
-double item_target(double total_taps, int wt, bool half, const ism_schedule *sc) {
+double item_target(double total_taps, int wt, bool half, int64_t n_samples, const ism_schedule *sc) {
   double min_taps = kMinItemTaps, balance = kBalanceItems;
   for (const ItemTuning &t : kItemTuning)
-    if (t.wt == wt && t.half == (half ? 1 : 0)) {
+    if (t.wt == wt && t.half == (half ? 1 : 0) && n_samples <= t.ns_max) {
       min_taps = t.min_item_taps;
       balance = t.balance_items;
+      break;
     }
   if (sc && sc->min_item_taps > 0.0) min_taps = std::max(1e3, sc->min_item_taps);
   if (sc && sc->balance_items > 0.0) balance = std::max(1.0, sc->balance_items);
@@ -137,10 +138,11 @@ constexpr double kTailRounds = 1.0;
 
 bool valid_schedule(const ism_schedule *sc) {
   if (!sc) return true;
-  const double v[4] = {sc->item_taps, sc->min_item_taps, sc->balance_items, sc->tail_rounds};
+  const double v[5] = {sc->item_taps, sc->min_item_taps, sc->balance_items, sc->tail_rounds, sc->batch_waves};
   for (double x : v)
     if (!std::isfinite(x)) return false;
-  return sc->item_taps >= 0.0 && sc->min_item_taps >= 0.0 && sc->balance_items >= 0.0;
+  return sc->item_taps >= 0.0 && sc->min_item_taps >= 0.0 && sc->balance_items >= 0.0 && sc->batch_waves >= 0.0 &&
+         sc->batch_waves <= 16.0;
 }
 
 // sched: the call's schedule (null = the tuned default).
@@ -216,7 +218,7 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, c
   }
   // an explicit item size is used as given
   const bool fixed = sched && sched->item_taps > 0.0;
-  const double target = fixed ? std::max(1e3, sched->item_taps) : item_target(p.total_taps, p.wt, p.half, sched);
+  const double target = fixed ? std::max(1e3, sched->item_taps) : item_target(p.total_taps, p.wt, p.half, nS, sched);
   // Tail taper: tiles are dispatched last first, and the items of a tile
   // dispatched when the work left (this tile included) is below tail_rounds
   // rounds of the resident waves are cut to that work over tail_rounds x the
@@ -619,7 +621,7 @@ struct BatchState {  // stored in ism_batch::opaque
       off_queue, off_wc;
   uint32_t n_rir, n_red, n_classes, mode;  // mode: 0 FP32, 1 FP16, 2 table taps
   uint32_t polar, n_jobs, any_gen, pad;     // polar: directional kernels; any_gen: general-mode windows
-  uint32_t class_first[kMaxClasses], class_count[kMaxClasses];
+  uint32_t class_first[kMaxClasses], class_count[kMaxClasses], class_grid[kMaxClasses];
   int32_t class_wt[kMaxClasses], class_gen[kMaxClasses];
 };
 static_assert(sizeof(BatchState) <= sizeof(ism_batch), "ism_batch too small");
@@ -712,6 +714,12 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     bp.st.class_count[k] = (uint32_t)(acc - bp.st.class_first[k]);
     bp.st.class_wt[k] = class_wt[k];
     bp.st.class_gen[k] = class_gen[k];
+    // persistent grid: the tuned workgroups per SIMD (or the schedule's)
+    int waves = kAccWavesPerSimd;
+    for (const BatchTuning &t : kBatchTuning)
+      if (t.wt == class_wt[k] && t.half == (precision == ISM_FP16 ? 1 : 0)) waves = t.waves;
+    if (sched && sched->batch_waves > 0.0) waves = std::max(1, (int)std::lround(sched->batch_waves));
+    bp.st.class_grid[k] = (uint32_t)std::min<uint64_t>(bp.st.class_count[k], 1024ull * (uint64_t)waves);
   }
   bp.st.n_jobs = (uint32_t)n_jobs;
   bp.st.any_gen = wc_floats > 0 ? 1u : 0u;
@@ -934,8 +942,8 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
   char *w = (char *)(uintptr_t)b.ws;
   const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (int)b.n_jobs, b.any_gen != 0,
                               (const BatchRir *)(w + b.off_rirs), b.n_rir,
-                              (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_wt,
-                              b.class_gen, (int)b.n_classes, b.mode == 1, b.mode == 2, b.polar != 0,
+                              (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_grid,
+                              b.class_wt, b.class_gen, (int)b.n_classes, b.mode == 1, b.mode == 2, b.polar != 0,
                               (const BatchReduce *)(w + b.off_red), b.n_red,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
                               (int *)(w + b.off_valid), (float *)(w + b.off_part), (float *)(w + b.off_marg),

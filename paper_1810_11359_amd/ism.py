@@ -66,7 +66,8 @@ class _Batch(ctypes.Structure):
 
 class _Schedule(ctypes.Structure):
     _fields_ = [("item_taps", ctypes.c_double), ("min_item_taps", ctypes.c_double),
-                ("balance_items", ctypes.c_double), ("tail_rounds", ctypes.c_double)]
+                ("balance_items", ctypes.c_double), ("tail_rounds", ctypes.c_double),
+                ("batch_waves", ctypes.c_double)]
 
 
 @dataclass
@@ -77,10 +78,11 @@ class Schedule:
     min_item_taps: float = 0.0
     balance_items: float = 0.0
     tail_rounds: float = -1.0
+    batch_waves: float = 0.0
 
     def _c(self) -> _Schedule:
         return _Schedule(float(self.item_taps), float(self.min_item_taps), float(self.balance_items),
-                         float(self.tail_rounds))
+                         float(self.tail_rounds), float(self.batch_waves))
 
 
 def _sched(schedule):

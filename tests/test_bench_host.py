@@ -1,5 +1,6 @@
 """Host-side behaviour of bench.py (no GPU): the one-GPU guard and the
 traffic figure taken from the committed counter summary."""
+import os
 import subprocess
 import sys
 
@@ -30,18 +31,34 @@ def test_traffic_only_for_the_profiled_library(monkeypatch):
 
 
 def test_tuner_header_round_trip(tmp_path):
-    """The tuner's header lists one entry per (window, precision) with the chosen pair."""
+    """The tuner's header lists one entry per (window, precision, RIR length
+    bucket) with the chosen pair, and the chosen batch grid per class."""
     from paper_1810_11359_amd import autotune
 
-    res = {}
+    res, waves = {}, {}
     for wt in (32, 64):
         for prec in ("fp32", "fp16"):
-            score = {(mt, bal): 1.0 + 0.01 * i for i, (mt, bal) in
-                     enumerate((a, b) for a in autotune.MIN_TAPS for b in autotune.BALANCE)}
-            res[(wt, prec)] = ((autotune.MIN_TAPS[0], autotune.BALANCE[0]), score, {}, ["w"])
+            for ns in autotune.NS_BUCKETS:
+                score = {(mt, bal): 1.0 + 0.01 * i for i, (mt, bal) in
+                         enumerate((a, b) for a in autotune.MIN_TAPS for b in autotune.BALANCE)}
+                res[(wt, prec, ns)] = ((autotune.MIN_TAPS[0], autotune.BALANCE[0]), score, {}, ["w"])
+    waves[(64, "fp32")] = (6, {k: 1.0 for k in autotune.BATCH_WAVES})
     p = tmp_path / "ism_tuning.h"
-    autotune.write_header(res, str(p), "test device")
+    autotune.write_header(res, waves, str(p), "test device")
     text = p.read_text()
     first = f"{autotune.MIN_TAPS[0]:.6g}, {autotune.BALANCE[0]:.1f}}}"
-    assert text.count("{32, 0, " + first) == 1 and text.count("{64, 1, " + first) == 1
-    assert "constexpr ItemTuning kItemTuning[]" in text
+    for ns in autotune.NS_BUCKETS:
+        assert text.count(f"{{32, 0, {ns}, " + first) == 1 and text.count(f"{{64, 1, {ns}, " + first) == 1
+    assert "constexpr ItemTuning kItemTuning[]" in text and "{64, 0, 6}," in text
+
+
+def test_committed_tuning_table_covers_every_exact_window():
+    """Every exact window and precision has a catch-all entry (the last
+    bucket), so every RIR length finds its schedule."""
+    import re
+
+    text = open(os.path.join(bench.ROOT, "paper_1810_11359_amd", "csrc", "ism_tuning.h")).read()
+    entries = re.findall(r"\{(\d+), ([01]), (\d+), ([0-9.e+]+), ([0-9.e+]+)\}", text)
+    for wt in (32, 64, 96, 128):
+        for half in ("0", "1"):
+            assert any(int(e[0]) == wt and e[1] == half and int(e[2]) == 2147483647 for e in entries), (wt, half)
