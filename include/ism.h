@@ -286,6 +286,40 @@ int ism_simulate_diffuse_polar(const ism_room *room, double t_diff, double t60, 
 int ism_filter_trajectory(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
                           void *stream);
 
+/* Filter methods of ism_filter_trajectory_ex. */
+enum {
+  ISM_FILTER_AUTO = 0,   /* FFT for RIRs of 2048 taps and more (when every input
+                            block of the FFT path touches at most 4 segments),
+                            direct otherwise                                   */
+  ISM_FILTER_DIRECT = 1, /* the direct sum of ism_filter_trajectory            */
+  ISM_FILTER_FFT = 2     /* partitioned FFT convolution (the paper's batched
+                            FFTs, Sec. 3.4)                                     */
+};
+
+/* Device workspace (bytes) of ism_filter_trajectory_ex for these sizes and
+ * method: 0 for the direct sum; for the FFT path the spectra of every RIR
+ * partition (about 4 times the RIR data), of the input blocks and of the
+ * output blocks. ISM_E_UNSUPPORTED for ISM_FILTER_FFT when one block of the
+ * signal would touch more than 16 segments (segments much shorter than the
+ * block); errors otherwise as for ism_filter_trajectory. */
+int ism_filter_workspace_size(int n_x, int n_pos, int n_mic, int n_rir, int method, size_t *bytes);
+
+/* ism_filter_trajectory (same x, rir, y layouts and result definition) with a
+ * choice of method. The FFT path cuts x into blocks of B samples (B = 4096
+ * for RIRs of 16384 taps and more, else a quarter of the next power of two of
+ * n_rir, at least 256), splits each block at segment boundaries, multiplies
+ * the spectra of the pieces with those of the B-tap partitions of their
+ * segment's RIR (2B-point FP32 transforms, radix-2 Stockham in LDS), adds the
+ * products of each output block in a fixed order and overlap-adds the
+ * inverse transforms: results are bitwise reproducible and agree with the
+ * direct sum to FP32 transform rounding. Its cost per output sample grows
+ * with log B and n_rir / B instead of n_rir.
+ *   ws: ism_filter_workspace_size() bytes (may be NULL for the direct sum).
+ * Errors: as for ism_filter_trajectory, ISM_E_WORKSPACE, ISM_E_UNSUPPORTED;
+ * all before any launch. Asynchronous on stream. */
+int ism_filter_trajectory_ex(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, int method,
+                             float *y, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- Batches of rooms --------------------------------------------------------- */
 
 /* One job of a batch: one room with its own sources, receivers and output. */

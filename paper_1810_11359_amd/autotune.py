@@ -70,13 +70,16 @@ def _feasible(room, t60):
         return False
 
 
-def _room(L, t60, fs, t_w, n_rcv, seed=0):
+def _room(L, t_max, fs, t_w, n_rcv, seed=0):
+    """A room simulated for t_max seconds; its T60 is t_max, or 0.2 s where
+    Sabine's formula cannot reach a shorter one in this room."""
     rng = np.random.default_rng(seed)
     L = np.asarray(L, dtype=float)
     src = rng.uniform(0.5, L - 0.5, (1, 3)).astype(np.float32)
     rcv = rng.uniform(0.5, L - 0.5, (n_rcv, 3)).astype(np.float32)
-    return workloads.Workload(f"room_{L[0]:g}x{L[1]:g}x{L[2]:g}_t60_{t60:g}_{n_rcv}rcv_{fs / 1000:g}k", L, t60, src,
-                              rcv, fs=fs, t_max=t60, t_w=t_w)
+    t60 = t_max if _feasible(L, t_max) else 0.2
+    return workloads.Workload(f"room_{L[0]:g}x{L[1]:g}x{L[2]:g}_t_{t_max:.3g}_{n_rcv}rcv_{fs / 1000:g}k", L, t60, src,
+                              rcv, fs=fs, t_max=t_max, t_w=t_w)
 
 
 def bucket_workloads(wt: int, ns_max: int):

@@ -10,9 +10,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libism.so")
 SOURCES = [os.path.join(CSRC, "ism_device.hip"), os.path.join(CSRC, "ism_diffuse.hip"),
-           os.path.join(CSRC, "ism_filter.hip"), os.path.join(CSRC, "ism_noalloc.hip"),
+           os.path.join(CSRC, "ism_filter.hip"), os.path.join(CSRC, "ism_filter_fft.hip"),
+           os.path.join(CSRC, "ism_noalloc.hip"),
            os.path.join(CSRC, "ism_host.cpp")]
-HEADERS = [os.path.join(CSRC, "ism_internal.h"), os.path.join(ROOT, "include", "ism.h")]
+HEADERS = [os.path.join(CSRC, "ism_internal.h"), os.path.join(CSRC, "ism_math.h"), os.path.join(ROOT, "include", "ism.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

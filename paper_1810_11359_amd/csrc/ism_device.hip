@@ -30,6 +30,7 @@
 
 #include "ism.h"
 #include "ism_internal.h"
+#include "ism_math.h"
 
 namespace ism {
 
@@ -242,38 +243,6 @@ constexpr ChebFit make_cheb_fit() {
   return F;
 }
 __constant__ ChebFit kChebFit = make_cheb_fit();
-
-// sin(pi x) and cos(pi x) in FP32 for |x| < 2^22, to a few ulp. x is reduced
-// exactly to r = x - n/2 with n = rint(2x) (|r| <= 1/4); sin(pi r) and
-// cos(pi r) are summed from their Taylor series to degree 9 and 10 (the first
-// omitted terms are below 2e-10 at |pi r| <= pi/4), with coefficients
-// pi^k / k! rounded to FP32, and rotated by the quadrant n mod 4.
-__device__ __forceinline__ void sincospi_acc(float x, float &s, float &c) {
-  const float n = __builtin_rintf(2.0f * x);
-  const float r = __builtin_fmaf(n, -0.5f, x);  // exact
-  const float r2 = r * r;
-  constexpr float S1 = (float)kPi, S3 = (float)(-kPi * kPi * kPi / 6.0),
-                  S5 = (float)(kPi * kPi * kPi * kPi * kPi / 120.0),
-                  S7 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi / 5040.0),
-                  S9 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 362880.0);
-  constexpr float C2 = (float)(-kPi * kPi / 2.0), C4 = (float)(kPi * kPi * kPi * kPi / 24.0),
-                  C6 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi / 720.0),
-                  C8 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 40320.0),
-                  C10 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 3628800.0);
-  float ps = __builtin_fmaf(r2, S9, S7);
-  ps = __builtin_fmaf(r2, ps, S5);
-  ps = __builtin_fmaf(r2, ps, S3);
-  ps = __builtin_fmaf(r2, ps, S1);
-  const float sr = r * ps;
-  float pc = __builtin_fmaf(r2, C10, C8);
-  pc = __builtin_fmaf(r2, pc, C6);
-  pc = __builtin_fmaf(r2, pc, C4);
-  pc = __builtin_fmaf(r2, pc, C2);
-  const float cr = __builtin_fmaf(r2, pc, 1.0f);
-  const int q = ((int)n) & 3;
-  s = q == 0 ? sr : q == 1 ? cr : q == 2 ? -sr : -cr;
-  c = q == 0 ? cr : q == 1 ? -sr : q == 2 ? -cr : sr;
-}
 
 // Constants of tap jj (j = jj + 1 - WT/2) of a general-mode window of W
 // samples under cap WT, for FP32 (half == 0) or FP16 (half == 1) taps, into

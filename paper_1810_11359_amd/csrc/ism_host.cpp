@@ -38,6 +38,9 @@ int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int 
                    double t60, uint64_t seed, hipStream_t st);
 int launch_filter(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
                   hipStream_t st);
+bool fft_plan(int n_x, int n_pos, int n_mic, int n_rir, int max_pieces, FftPlan &f);
+int launch_filter_fft(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
+                      const FftPlan &f, void *ws, hipStream_t st);
 }  // namespace ism
 
 using namespace ism;
@@ -955,6 +958,60 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
 }  // extern "C"
 
 // ---- Moving-source filtering (Sec. 3.4) --------------------------------------
+namespace {
+constexpr int kFftMaxPieces = 16;  // segments one FFT input block may touch
+constexpr int kAutoMaxPieces = 4;
+
+int filter_args(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, const float *y) {
+  if (!x || !rir || !y) return ISM_E_INVALID_ARG;
+  if (n_x < 1 || n_pos < 1 || n_mic < 1 || n_rir < 1 || n_pos > n_x) return ISM_E_INVALID_ARG;
+  if (n_mic > 65535 || (int64_t)n_x + n_rir - 1 > (int64_t)0x7fffffff) return ISM_E_TOO_LARGE;
+  return ISM_OK;
+}
+
+// Resolves the method (auto: FFT for RIRs of 2048 taps and more when an input
+// block touches at most kAutoMaxPieces segments) and the FFT plan.
+int filter_method(int n_x, int n_pos, int n_mic, int n_rir, int method, FftPlan &f, int &resolved) {
+  if (method != ISM_FILTER_AUTO && method != ISM_FILTER_DIRECT && method != ISM_FILTER_FFT) return ISM_E_INVALID_ARG;
+  resolved = ISM_FILTER_DIRECT;
+  if (method == ISM_FILTER_DIRECT) return ISM_OK;
+  const bool ok = fft_plan(n_x, n_pos, n_mic, n_rir, method == ISM_FILTER_FFT ? kFftMaxPieces : kAutoMaxPieces, f);
+  if (method == ISM_FILTER_FFT) {
+    if (!ok) return ISM_E_UNSUPPORTED;
+    resolved = ISM_FILTER_FFT;
+  } else if (ok && n_rir >= 2048) {
+    resolved = ISM_FILTER_FFT;
+  }
+  return ISM_OK;
+}
+}  // namespace
+
+int ism_filter_workspace_size(int n_x, int n_pos, int n_mic, int n_rir, int method, size_t *bytes) {
+  if (!bytes) return ISM_E_INVALID_ARG;
+  if (n_x < 1 || n_pos < 1 || n_mic < 1 || n_rir < 1 || n_pos > n_x) return ISM_E_INVALID_ARG;
+  if (n_mic > 65535 || (int64_t)n_x + n_rir - 1 > (int64_t)0x7fffffff) return ISM_E_TOO_LARGE;
+  FftPlan f;
+  int m = 0;
+  const int st = filter_method(n_x, n_pos, n_mic, n_rir, method, f, m);
+  if (st != ISM_OK) return st;
+  *bytes = m == ISM_FILTER_FFT ? f.bytes : 0;
+  return ISM_OK;
+}
+
+int ism_filter_trajectory_ex(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, int method,
+                             float *y, void *ws, size_t ws_bytes, void *stream) {
+  int st = filter_args(x, n_x, rir, n_pos, n_mic, n_rir, y);
+  if (st != ISM_OK) return st;
+  FftPlan f;
+  int m = 0;
+  st = filter_method(n_x, n_pos, n_mic, n_rir, method, f, m);
+  if (st != ISM_OK) return st;
+  if (m == ISM_FILTER_DIRECT) return ism_filter_trajectory(x, n_x, rir, n_pos, n_mic, n_rir, y, stream);
+  if (!ws || ws_bytes < f.bytes) return ISM_E_WORKSPACE;
+  if (launch_filter_fft(x, n_x, rir, n_pos, n_mic, n_rir, y, f, ws, (hipStream_t)stream) != 0) return ISM_E_DEVICE;
+  return ISM_OK;
+}
+
 int ism_filter_trajectory(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
                           void *stream) {
   if (!x || !rir || !y) return ISM_E_INVALID_ARG;

@@ -153,4 +153,12 @@ struct DumpArgs {
   uint32_t cap;
 };
 
+// Workspace layout of one FFT filter call (offsets in bytes): block size B,
+// transform size N = 2B, RIR partitions P, pieces per input block R, segment
+// length L, input and output block counts.
+struct FftPlan {
+  int B, N, P, R, n_in_blocks, n_out_blocks, L;
+  size_t off_tw, off_H, off_X, off_Y, off_z, bytes;
+};
+
 }  // namespace ism

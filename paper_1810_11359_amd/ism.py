@@ -38,7 +38,7 @@ EXPORTS = (
     "ism_diffuse_workspace_size", "ism_simulate_diffuse", "ism_simulate_diffuse_timed",
     "ism_filter_trajectory", "ism_workspace_size_ex", "ism_simulate_ex", "ism_simulate_host",
     "ism_batch_workspace_size_ex", "ism_batch_prepare_ex", "ism_simulate_batch", "ism_debug_enumerate",
-    "ism_simulate_noalloc",
+    "ism_simulate_noalloc", "ism_filter_workspace_size", "ism_filter_trajectory_ex",
 )
 
 
@@ -182,6 +182,11 @@ def lib() -> ctypes.CDLL:
         L.ism_debug_enumerate.restype = ctypes.c_int
         L.ism_debug_enumerate.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, sp, fp, ctypes.c_uint32, fp, fp,
                                           ctypes.c_size_t, fp]
+        L.ism_filter_workspace_size.restype = ctypes.c_int
+        L.ism_filter_workspace_size.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_size_t)]
+        L.ism_filter_trajectory_ex.restype = ctypes.c_int
+        L.ism_filter_trajectory_ex.argtypes = [fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, fp, fp, ctypes.c_size_t, fp]
         L.ism_simulate_noalloc.restype = ctypes.c_int
         L.ism_simulate_noalloc.argtypes = [rp, fp, ctypes.c_int, fp, ctypes.c_int, ctypes.c_int, fp, fp]
         L.ism_simulate_diffuse_timed.restype = ctypes.c_int
@@ -481,10 +486,22 @@ def simulate_diffuse_polar(room: Room, src, rcv, orient, t_diff: float, t60: flo
     return out
 
 
-def filter_trajectory(x, rirs, stream=None):
+FILTER_METHODS = {"auto": 0, "direct": 1, "fft": 2}
+
+
+def filter_workspace_size(n_x: int, n_pos: int, n_mic: int, n_rir: int, method: str = "auto") -> int:
+    out = ctypes.c_size_t()
+    _check(lib().ism_filter_workspace_size(int(n_x), int(n_pos), int(n_mic), int(n_rir), FILTER_METHODS[method],
+                                           ctypes.byref(out)), "ism_filter_workspace_size")
+    return out.value
+
+
+def filter_trajectory(x, rirs, stream=None, method: str = "auto", ws=None):
     """Moving source (Sec. 3.4): x [n_x] float32 device tensor, rirs [n_pos, n_mic,
     n_rir] float32 device tensor (ism_simulate output with the trajectory points as
-    sources). Returns y [n_mic, n_x + n_rir - 1] on the same device."""
+    sources). Returns y [n_mic, n_x + n_rir - 1] on the same device.
+    method: "direct" (direct sum), "fft" (partitioned FFT convolution) or
+    "auto"; ws: optional uint8 device tensor of at least filter_workspace_size bytes."""
     import torch
 
     if x.dtype != torch.float32 or rirs.dtype != torch.float32 or x.dim() != 1 or rirs.dim() != 3:
@@ -492,10 +509,15 @@ def filter_trajectory(x, rirs, stream=None):
     x = x.contiguous()
     rirs = rirs.contiguous()
     n_pos, n_mic, n_rir = rirs.shape
+    nbytes = filter_workspace_size(x.shape[0], n_pos, n_mic, n_rir, method)
+    if nbytes and (ws is None or ws.numel() < nbytes):
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     y = torch.empty((n_mic, x.shape[0] + n_rir - 1), dtype=torch.float32, device=x.device)
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib().ism_filter_trajectory(x.data_ptr(), int(x.shape[0]), rirs.data_ptr(), int(n_pos), int(n_mic),
-                                       int(n_rir), y.data_ptr(), st.cuda_stream), "ism_filter_trajectory")
+    _check(lib().ism_filter_trajectory_ex(x.data_ptr(), int(x.shape[0]), rirs.data_ptr(), int(n_pos), int(n_mic),
+                                          int(n_rir), FILTER_METHODS[method], y.data_ptr(),
+                                          ws.data_ptr() if nbytes else None, nbytes, st.cuda_stream),
+           "ism_filter_trajectory_ex")
     return y
 
 

@@ -21,25 +21,32 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("method", ["direct", "fft"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_filter_matches_oracle(oracle_mod, case):
+def test_filter_matches_oracle(oracle_mod, case, method):
     import torch
 
     name, n_x, n_pos, n_mic, n_rir = case
+    if method == "fft" and name == "every_sample_its_point":
+        # one segment per sample: an FFT block would touch more than 16 segments
+        with pytest.raises(ism.IsmError) as e:
+            ism.filter_workspace_size(n_x, n_pos, n_mic, n_rir, "fft")
+        assert e.value.status == ism.ISM_E_UNSUPPORTED
+        return
     rng = np.random.default_rng(zlib.crc32(name.encode()))
     x = rng.standard_normal(n_x).astype(np.float32)
     rirs = (rng.standard_normal((n_pos, n_mic, n_rir)) * np.exp(-np.arange(n_rir) / 300.0)).astype(np.float32)
-    print(f"[case] {name}", flush=True)
+    print(f"[case] {name} {method}", flush=True)
     sys.stdout.flush()
-    y = ism.filter_trajectory(torch.from_numpy(x).cuda(), torch.from_numpy(rirs).cuda())
+    y = ism.filter_trajectory(torch.from_numpy(x).cuda(), torch.from_numpy(rirs).cuda(), method=method)
     torch.cuda.synchronize()
     got = y.cpu().numpy().astype(np.float64)
     ref = oracle_mod.filter_trajectory(x, rirs)
     assert got.shape == ref.shape
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
-    print(name, "rel err", err)
+    print(name, method, "rel err", err)
     assert err <= 1e-5
-    y2 = ism.filter_trajectory(torch.from_numpy(x).cuda(), torch.from_numpy(rirs).cuda())
+    y2 = ism.filter_trajectory(torch.from_numpy(x).cuda(), torch.from_numpy(rirs).cuda(), method=method)
     torch.cuda.synchronize()
     assert torch.equal(y.cpu(), y2.cpu())  # fixed summation order
 
@@ -67,7 +74,8 @@ def test_trajectory_end_to_end(oracle_mod):
     assert err <= 1e-5
 
 
-def test_filter_96000_tap_rirs_sampled(oracle_mod):
+@pytest.mark.parametrize("method", ["direct", "fft"])
+def test_filter_96000_tap_rirs_sampled(oracle_mod, method):
     """The moving-source size of a 48 kHz, T60 = 2 s room: 10 s of signal
     (480 000 samples) through 100 trajectory points to 8 microphones with
     RIRs of 96 000 taps (decaying noise in place of simulated RIRs). The
@@ -89,8 +97,8 @@ def test_filter_96000_tap_rirs_sampled(oracle_mod):
     for p in range(n_pos):  # fill point by point to keep host memory small
         rirs[p] = torch.from_numpy((rng.standard_normal((n_mic, n_rir)).astype(np.float32) * env)).cuda()
     host = rirs.cpu().numpy()
-    print("[case] 96000-tap filter", flush=True)
-    y = ism.filter_trajectory(torch.from_numpy(x).cuda(), rirs)
+    print(f"[case] 96000-tap filter {method}", flush=True)
+    y = ism.filter_trajectory(torch.from_numpy(x).cuda(), rirs, method=method)
     torch.cuda.synchronize()
     got = y.cpu().numpy()
     seg = -(-n_x // n_pos)
@@ -104,5 +112,5 @@ def test_filter_96000_tap_rirs_sampled(oracle_mod):
         ref = oracle_mod.filter_samples(x, host, m, picks)
         err = max(err, float(np.max(np.abs(got[m, picks] - ref))))
         peak = max(peak, float(np.max(np.abs(ref))))
-    print("96000-tap filter: max err / max sampled |y| =", err / peak, flush=True)
+    print(f"96000-tap filter ({method}): max err / max sampled |y| =", err / peak, flush=True)
     assert err <= 4.0 * 2.0 ** -24 * np.sqrt(n_rir) * peak
