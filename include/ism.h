@@ -358,11 +358,13 @@ int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, 
 
 /* Simulates every job of a prepared batch on stream: kernel launches only (no
  * host-device copies, no allocation), so it can be captured in a HIP graph and
- * replayed. Each job is planned as a single call with tail_rounds = 0 (see
- * ism_schedule): its result is bitwise identical to ism_simulate_ex of that
- * job with that schedule, whatever the other jobs of the batch, and within
- * rounding (<= 1e-6 of the RIR peak) of ism_simulate, whose default schedule
- * tapers the tail of a single call. */
+ * replayed. Work items are sized from the batch's total work: each job is
+ * planned as a single call with item_taps = max(min_item_taps, batch taps /
+ * balance_items) of its class (or the schedule's item_taps when given). A
+ * job's result therefore agrees within rounding (<= 1e-6 of the RIR peak)
+ * with the job alone and with ism_simulate; it is bitwise that of
+ * ism_simulate_ex with the same item_taps, and a batch of one job is bitwise
+ * ism_simulate_ex with tail_rounds = 0. */
 int ism_batch_run(const ism_batch *batch, void *stream);
 
 /* ism_batch_run that also records the caller's HIP events ev_start before the

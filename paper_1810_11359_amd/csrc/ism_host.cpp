@@ -670,6 +670,17 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   }
   // with any directional job the batch runs the directional kernels; the
   // others take the pattern a = 1, b = 0, whose factor is exactly 1
+  // pass 0: every job's estimated work. The batch fills the device with all
+  // of it, so work items are sized from the batch's total (as a single call
+  // sizes them from its own): a job's items are those of a single call with
+  // item_taps = max(min_item_taps, batch total / balance_items) of its class.
+  double batch_taps = 0.0;
+  for (int j = 0; j < n_jobs; ++j) {
+    Plan &p = plans[j];
+    const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, sched, false);
+    if (stt != ISM_OK) return stt;
+    batch_taps += p.total_taps;
+  }
   // pass 1: plans, window classes and counts
   int n_classes = 0;
   int class_wt[kMaxClasses] = {}, class_gen[kMaxClasses] = {};
@@ -678,8 +689,13 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   std::vector<uint64_t> bucket_count((size_t)kMaxClasses * kCostBuckets, 0);
   for (int j = 0; j < n_jobs; ++j) {
     Plan &p = plans[j];
-    const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, sched, false);
-    if (stt != ISM_OK) return stt;
+    if (!(sched && sched->item_taps > 0.0)) {
+      ism_schedule js{};
+      if (sched) js = *sched;
+      js.item_taps = item_target(batch_taps, p.wt, p.half, p.ra.n_samples, sched);
+      const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, &js, false);
+      if (stt != ISM_OK) return stt;
+    }
     int cls = -1;
     for (int k = 0; k < n_classes; ++k)
       if (class_wt[k] == p.wt && class_gen[k] == (p.gen ? 1 : 0)) cls = k;

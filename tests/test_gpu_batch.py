@@ -48,8 +48,19 @@ def _mixed_jobs():
     return jobs
 
 
-# a batch plans each job like a single call without the tail taper
+# with an explicit item size every job of a batch is planned exactly as its
+# single call with the same schedule (bitwise equal results); by default a
+# batch sizes its items from its total work, so a job agrees with its single
+# call within the rounding of another split
+SHARED = ism.Schedule(item_taps=60000.0)
 UNTAPERED = ism.Schedule(tail_rounds=0.0)
+
+
+def _close(a, b, peak_of):
+    import torch
+
+    peak = torch.amax(torch.abs(peak_of), dim=-1)
+    return bool(torch.all(torch.amax(torch.abs(a - b), dim=-1) <= 1e-6 * peak))
 
 
 def test_batch_equals_single_room_calls(oracle_mod):
@@ -57,18 +68,19 @@ def test_batch_equals_single_room_calls(oracle_mod):
 
     jobs = _mixed_jobs()
     _say("mixed batch")
-    b = ism.BatchSimulator(jobs)
-    outs = [o.clone() for o in b.run()]
+    outs = [o.clone() for o in ism.BatchSimulator(jobs).run()]
+    shared = [o.clone() for o in ism.BatchSimulator(jobs, schedule=SHARED).run()]
     torch.cuda.synchronize()
-    for (room, src, rcv), o in zip(jobs, outs):
-        single = ism.simulate(room, src, rcv, schedule=UNTAPERED)
-        torch.cuda.synchronize()
-        assert torch.equal(o, single), f"batch differs from single-room call for {room.room}"
-        # the default single call tapers its tail: another split, same sums within rounding
+    for (room, src, rcv), o, sh in zip(jobs, outs, shared):
+        single = ism.simulate(room, src, rcv, schedule=SHARED)
+        alone = ism.BatchSimulator([(room, src, rcv)]).run()[0]
+        untapered = ism.simulate(room, src, rcv, schedule=UNTAPERED)
         tapered = ism.simulate(room, src, rcv)
         torch.cuda.synchronize()
-        peak = torch.amax(torch.abs(single), dim=-1)
-        assert bool(torch.all(torch.amax(torch.abs(tapered - o), dim=-1) <= 1e-6 * peak))
+        assert torch.equal(sh, single), f"batch differs from the single call with its schedule for {room.room}"
+        assert torch.equal(alone, untapered), f"a one-job batch differs from the untapered call for {room.room}"
+        # other splits (batch-sized items, the single call's tapered tail): same sums within rounding
+        assert _close(o, single, single) and _close(tapered, o, single) and _close(alone, o, single)
     # oracle on two of the jobs
     for k in (0, 1):
         room, src, rcv = jobs[k]
@@ -85,21 +97,21 @@ def test_batch_table_taps_equal_single_calls():
 
     jobs = _mixed_jobs()
     _say("mixed batch, table taps")
-    b = ism.BatchSimulator(jobs, precision="lut")
+    b = ism.BatchSimulator(jobs, precision="lut", schedule=SHARED)
     outs = [o.clone() for o in b.run()]
     torch.cuda.synchronize()
     for (room, src, rcv), o in zip(jobs, outs):
-        single = ism.simulate(room, src, rcv, precision="lut", schedule=UNTAPERED)
+        single = ism.simulate(room, src, rcv, precision="lut", schedule=SHARED)
         torch.cuda.synchronize()
         assert torch.equal(o, single), f"batch differs from single-room call for {room.room}"
 
 
 def test_batch_directional_jobs_equal_single_calls():
-    """A batch mixing directional and omnidirectional jobs: every job bitwise
-    equal to itself alone in a batch, omnidirectional jobs bitwise equal to
-    their single call with the batch's schedule (their pattern factor is
-    exactly 1), directional jobs within rounding of ism_simulate_polar (whose
-    default schedule tapers the tail)."""
+    """A batch mixing directional and omnidirectional jobs (one shared item
+    size): every job bitwise equal to itself alone in a batch, omnidirectional
+    jobs bitwise equal to their single call (their pattern factor is exactly
+    1), directional jobs within rounding of ism_simulate_polar (whose default
+    schedule tapers the tail)."""
     import torch
 
     jobs = _mixed_jobs()
@@ -112,20 +124,19 @@ def test_batch_directional_jobs_equal_single_calls():
         else:
             batch_jobs.append((room, src, rcv, rng.standard_normal((len(rcv), 3)).astype(np.float32), pat))
     _say("mixed batch, directional jobs")
-    b = ism.BatchSimulator(batch_jobs)
+    b = ism.BatchSimulator(batch_jobs, schedule=SHARED)
     outs = [o.clone() for o in b.run()]
     torch.cuda.synchronize()
     for job, o in zip(batch_jobs, outs):
-        alone = ism.BatchSimulator([job]).run()[0]
+        alone = ism.BatchSimulator([job], schedule=SHARED).run()[0]
         torch.cuda.synchronize()
         assert torch.equal(o, alone), f"batch job differs from the job alone for {job[0].room}"
         if len(job) == 5:
             single = ism.simulate_polar(job[0], job[1], job[2], job[3], job[4])
             torch.cuda.synchronize()
-            peak = torch.amax(torch.abs(single), dim=-1)
-            assert bool(torch.all(torch.amax(torch.abs(single - o), dim=-1) <= 1e-6 * peak))
+            assert _close(single, o, single)
         else:
-            single = ism.simulate(job[0], job[1], job[2], schedule=UNTAPERED)
+            single = ism.simulate(job[0], job[1], job[2], schedule=SHARED)
             torch.cuda.synchronize()
             assert torch.equal(o, single), f"batch differs from single-room call for {job[0].room}"
 

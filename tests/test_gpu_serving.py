@@ -1,4 +1,5 @@
-"""The serving loop on the GPU: every job's result in the mix equals the job alone."""
+"""The serving loop on the GPU: every job's result in the mix equals the job
+alone within rounding."""
 import sys
 
 import numpy as np
@@ -39,7 +40,11 @@ def test_mixed_stream_equals_jobs_alone():
     assert st.n_jobs == len(jobs)
     assert max(sch.batch_sizes) > 1  # jobs were actually batched together
     for j in sorted(sch.done, key=lambda j: j.jid):
-        # batches plan each job like a single call without the tail taper
-        alone = ism.simulate(j.room, j.src, j.rcv, schedule=ism.Schedule(tail_rounds=0.0))
+        # a batch sizes work items from its total work: alone and in the mix,
+        # a job's sums are split differently, equal within rounding (1e-6 of
+        # the peak, 10x inside the FP32 parity tolerance)
+        alone = ism.simulate(j.room, j.src, j.rcv)
         torch.cuda.synchronize()
-        assert torch.equal(alone, j.out), f"job {j.jid} differs alone vs in the mix"
+        peak = torch.amax(torch.abs(alone), dim=-1)
+        err = torch.amax(torch.abs(alone - j.out), dim=-1)
+        assert bool(torch.all(err <= 1e-6 * peak)), f"job {j.jid} differs alone vs in the mix"

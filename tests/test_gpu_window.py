@@ -103,9 +103,9 @@ def test_general_window_polar(oracle_mod):
 
 
 def test_general_windows_in_one_batch(oracle_mod):
-    """Jobs of four windows (two exact, two general; three caps) in one batch:
-    each bitwise equal to its untapered single call, one checked against the
-    oracle."""
+    """Jobs of four windows (two exact, two general; three caps) in one batch
+    with a shared item size: each bitwise equal to its single call with that
+    schedule, one checked against the oracle."""
     import torch
 
     jobs = []
@@ -113,10 +113,11 @@ def test_general_windows_in_one_batch(oracle_mod):
                                           (22050.0, 0.004, 0.1)]):
         jobs.append(_case(fs, t_w, t_max, n_rcv=2, seed=10 + k))
     _say("batch of windows 64, 176.4, 96, 88.2")
-    outs = [o.clone() for o in ism.BatchSimulator(jobs).run()]
+    sched = ism.Schedule(item_taps=50000.0)
+    outs = [o.clone() for o in ism.BatchSimulator(jobs, schedule=sched).run()]
     torch.cuda.synchronize()
     for (room, src, rcv), o in zip(jobs, outs):
-        single = ism.simulate(room, src, rcv, schedule=ism.Schedule(tail_rounds=0.0))
+        single = ism.simulate(room, src, rcv, schedule=sched)
         torch.cuda.synchronize()
         assert torch.equal(o, single), f"batch differs from single call at W = {room.fs * room.t_w:g}"
     room, src, rcv = jobs[1]
