@@ -211,8 +211,26 @@ def cpu_baseline(ws, n_rcv_sample: int, gpu_outs=None, lut_q: int = 0, one_core_
     return out, errs
 
 
-def _time_runs(sim, steps: int, warmup: int):
-    """Warm-up, then ``steps`` timed runs: (ms per whole step, per-run kernel ms list)."""
+# Untimed seconds of back-to-back steps after the warm-up steps: the GPU's
+# clocks take longer than a few short steps to reach their level under load
+# (the 32-receiver room measured 0.53 ms per kernel after 3 warm-up steps,
+# 0.45 ms after a second of steps), so short steps are timed only from then.
+PREWARM_S = 1.0
+
+
+def _prewarm(step, seconds: float) -> None:
+    """Runs ``step`` back to back (synchronising after each) for ``seconds``."""
+    import torch
+
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        step()
+        torch.cuda.synchronize()
+
+
+def _time_runs(sim, steps: int, warmup: int, prewarm_s: float = PREWARM_S):
+    """Warm-up steps, ``prewarm_s`` seconds of untimed steps, then ``steps``
+    timed runs: (ms per whole step, per-run kernel ms list)."""
     import torch
 
     hip = _HipEvents()
@@ -221,6 +239,7 @@ def _time_runs(sim, steps: int, warmup: int):
     for _ in range(warmup):
         sim.run()
     torch.cuda.synchronize()
+    _prewarm(sim.run, prewarm_s)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -331,6 +350,7 @@ def bench_moving_source(args) -> int:
     for _ in range(args.warmup):
         ism.filter_trajectory(x, rirs, method=method, ws=ws)
     torch.cuda.synchronize()
+    _prewarm(lambda: ism.filter_trajectory(x, rirs, method=method, ws=ws), args.prewarm_s)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     e0.record()
@@ -345,7 +365,7 @@ def bench_moving_source(args) -> int:
     # an equivalent rate); roofline only for the direct sum
     out = {"metric": "moving-source filter multiply-adds/s (G/s)", "value": macs / (ms_step / 1e3) / 1e9,
            "unit": "G MAC/s (direct-sum equivalent)", "filter_method": resolved,
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "prewarm_s": args.prewarm_s, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": f"{args.workload}_{fs / 1000:g}k_100pts_8mics_{n_rir}_taps",
                       "n_x": int(x.shape[0]), "n_pos": n_pos, "n_mic": n_mic, "n_rir": n_rir, "macs_per_step": macs,
@@ -404,7 +424,7 @@ def bench_batch(args) -> int:
     precisions = [args.precision] + (["fp16"] if args.precision == "fp32" and not args.no_fp16 else [])
     for prec in precisions:
         sim = ism.BatchSimulator(jobs, precision=prec)
-        ms_step, kern_ms = _time_runs(sim, args.steps, args.warmup)
+        ms_step, kern_ms = _time_runs(sim, args.steps, args.warmup, args.prewarm_s)
         legs[prec] = {"ms_per_step": ms_step, "kern_ms": kern_ms, "n_rir": sim.n_rirs,
                       "outs": [o.cpu().numpy() for o in sim.outs[:n_rooms_sample]]}
         del sim
@@ -417,7 +437,8 @@ def bench_batch(args) -> int:
               "parallelism": "single GPU"}
     ms_step = head["ms_per_step"]
     out = {"metric": METRIC, "value": taps / (ms_step / 1e3) / 1e9, "unit": "G taps/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "steps": args.steps, "warmup": args.warmup, "prewarm_s": args.prewarm_s, "ms_per_step": ms_step,
+           "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic", "config": config,
            "rirs_per_s": n_rir / (ms_step / 1e3),
            "roofline": _roofline(taps, head["kern_ms"], "batch_rooms", args.precision, "accumulate_batch_kernel")}
@@ -463,9 +484,10 @@ def bench_single(args) -> int:
               "n_img": list(room.n_img), "taps_per_step": int(taps), "parallelism": "single GPU"}
     if w.t_diff > 0.0:
         config["t_diff_s"] = w.t_diff
-    ms_step, kern_ms = _time_runs(sim, args.steps, args.warmup)
+    ms_step, kern_ms = _time_runs(sim, args.steps, args.warmup, args.prewarm_s)
     out = {"metric": METRIC, "value": taps / (ms_step / 1e3) / 1e9, "unit": "G taps/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "steps": args.steps, "warmup": args.warmup, "prewarm_s": args.prewarm_s, "ms_per_step": ms_step,
+           "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic", "config": config,
            "rirs_per_s": n_rir / (ms_step / 1e3),
            "roofline": _roofline(taps, kern_ms, args.workload, args.precision, "accumulate_kernel")}
@@ -483,6 +505,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prewarm-s", type=float, default=PREWARM_S,
+                    help="untimed seconds of steps after the warm-up steps, so the clocks settle (0: none)")
     ap.add_argument("--workload", default="batch_rooms",
                     choices=["batch_rooms", "room_32_receivers", "single_rir", "large_room_uca",
                              "paper_room_128rir", "paper_room_diffuse_1024rir", "moving_source_10s",

@@ -8,8 +8,9 @@ tap-accumulation kernel (HIP events the library records around it) on
 representative single-room and batch workloads of that bucket over a grid of
 (min_item_taps, balance_items) pairs and keeps the pair with the best
 geometric-mean time relative to each workload's fastest pair. For the
-persistent batch launches of W = 64 it also picks the workgroups per SIMD of
-the grid. It writes the table header the host planner compiles in; rebuild
+persistent batch launches of W = 64 it also picks, on the 1024-room batch, the
+workgroups per SIMD of the grid and the largest item of a batch job. It writes
+the table header the host planner compiles in; rebuild
 the library afterwards. Candidate values reach the library as the call's
 explicit schedule (``ism_schedule``).
 
@@ -36,6 +37,7 @@ MIN_TAPS = (6.0e4, 1.2e5, 2.4e5, 4.8e5)
 BALANCE = (24576.0, 49152.0, 98304.0, 196608.0)
 NS_BUCKETS = (8192, 32768, 2147483647)   # RIR length buckets (samples), upper bounds
 BATCH_WAVES = (4, 5, 6, 7, 8)
+BATCH_ITEM_TAPS = (1.2e5, 2.5e5, 5.0e5)
 
 
 class _Events:
@@ -129,7 +131,7 @@ def _score(times, n_loads):
 
 def tune(reps: int = 3, classes=(32, 64, 96, 128), precisions=("fp32", "fp16"), log=print):
     """Returns ({(wt, prec, ns_max): (best pair, scores, times, names)},
-    {(wt, prec): (best waves, scores)})."""
+    {(wt, prec): ((best waves, best batch item taps), scores)})."""
     ev = _Events()
     results, waves = {}, {}
     for wt in classes:
@@ -154,10 +156,12 @@ def tune(reps: int = 3, classes=(32, 64, 96, 128), precisions=("fp32", "fp16"), 
                     f"(score {score[best]:.4f}; default pair {score[(1.2e5, 49152.0)]:.4f})")
             if wt == 64:
                 batch = workloads.batch_rooms(1024, seed=0, feasible=_feasible)
-                t = {k: [time_kernel(batch, prec, ev, reps, ism.Schedule(batch_waves=k))] for k in BATCH_WAVES}
+                t = {(k, it): [time_kernel(batch, prec, ev, reps, ism.Schedule(batch_waves=k, item_taps=it))]
+                     for k in BATCH_WAVES for it in BATCH_ITEM_TAPS}
                 sc = _score(t, 1)
                 waves[(wt, prec)] = (min(sc, key=sc.get), sc)
-                log(f"W={wt} {prec} batch waves per SIMD: " + ", ".join(f"{k}: {t[k][0]:.3f} ms" for k in t))
+                log(f"W={wt} {prec} batch (waves per SIMD, item taps): "
+                    + ", ".join(f"({k}, {it:g}) {t[(k, it)][0]:.3f} ms" for k, it in t))
     return results, waves
 
 
@@ -172,6 +176,7 @@ def write_header(results, waves, path: str, device: str) -> None:
         "//   ns_max         the entry applies to RIRs of at most this many samples",
         "//                  (first match in table order)",
         "//   waves          workgroups per SIMD of a persistent batch launch",
+        "//   item_taps      largest work item of a batch job (estimated taps)",
         "//",
         "// Score: geometric mean over the bucket's workloads of kernel time relative",
         "// to the fastest pair on that workload (1.0 = fastest everywhere).",
@@ -180,20 +185,21 @@ def write_header(results, waves, path: str, device: str) -> None:
         lines.append(f"// W={wt} {prec} nS<={ns_max} ({', '.join(names)}): best {best[0]:g} / {best[1]:g}, "
                      f"score {score[best]:.4f}, default 1.2e5 / 49152 score {score[(1.2e5, 49152.0)]:.4f}")
     for (wt, prec), (best, sc) in sorted(waves.items()):
-        lines.append(f"// W={wt} {prec} batch: best {best} waves per SIMD, "
-                     + ", ".join(f"{k}: {v:.4f}" for k, v in sorted(sc.items())))
+        lines.append(f"// W={wt} {prec} batch: best {best[0]} waves per SIMD, items <= {best[1]:g} taps; "
+                     + ", ".join(f"({k}, {it:g}): {v:.4f}" for (k, it), v in sorted(sc.items())))
     lines += ["#pragma once", "", "namespace ism {", "", "struct ItemTuning {",
               "  int wt;        // window cap in samples", "  int half;      // 1: FP16 taps, 0: FP32 taps",
               "  int ns_max;    // RIR length bucket (samples)", "  double min_item_taps;", "  double balance_items;",
-              "};", "", "struct BatchTuning {", "  int wt;", "  int half;", "  int waves;", "};", "",
+              "};", "", "struct BatchTuning {", "  int wt;", "  int half;", "  int waves;", "  double item_taps;", "};",
+              "",
               "constexpr ItemTuning kItemTuning[] = {"]
     for (wt, prec, ns_max), (best, _, _, _) in sorted(results.items()):
         lines.append(f"    {{{wt}, {1 if prec == 'fp16' else 0}, {ns_max}, {best[0]:.6g}, {best[1]:.1f}}},")
     lines += ["};", "", "constexpr BatchTuning kBatchTuning[] = {"]
     for (wt, prec), (best, _) in sorted(waves.items()):
-        lines.append(f"    {{{wt}, {1 if prec == 'fp16' else 0}, {best}}},")
+        lines.append(f"    {{{wt}, {1 if prec == 'fp16' else 0}, {best[0]}, {best[1]:.6g}}},")
     if not waves:
-        lines.append("    {0, 0, 0},")
+        lines.append("    {0, 0, 0, 0.0},")
     lines += ["};", "", "}  // namespace ism", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))

@@ -133,6 +133,15 @@ double item_target(double total_taps, int wt, bool half, int64_t n_samples, cons
   return std::max(min_taps, total_taps / balance);
 }
 
+// Largest work item of a batch job (the tuned value of its window class and
+// precision; classes the tuner has no batch workload for take kBatchItemTaps).
+constexpr double kBatchItemTaps = 2.5e5;
+double batch_item_taps(int wt, bool half) {
+  for (const BatchTuning &t : kBatchTuning)
+    if (t.wt == wt && t.half == (half ? 1 : 0)) return t.item_taps;
+  return kBatchItemTaps;
+}
+
 // Waves of the accumulate kernel resident on the device at once (256 CUs x
 // 4 SIMDs x the waves per SIMD the kernel is built for), and the default
 // rounds of them over which a single call tapers its tail.
@@ -655,10 +664,10 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
                bool fill) {
   if (!jobs || n_jobs < 1) return ISM_E_INVALID_ARG;
   std::memset(&bp.st, 0, sizeof(bp.st));
-  // Each job is planned as a single call would plan it without the tail
-  // taper (items sized from the job's own work), so a job's result does not
-  // depend on the batch; tapering every job would only fragment small jobs,
-  // and the batch's own tail is the largest-first order over all its items.
+  // Each job is planned as a single call without the tail taper (tapering
+  // every job would only fragment small jobs; the batch's own tail is the
+  // largest-first order over all its items), with an item size taken from
+  // the whole batch (pass 0).
   std::vector<Plan> plans(n_jobs);
   bool polar = false;
   for (int j = 0; j < n_jobs; ++j) {
@@ -671,9 +680,10 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   // with any directional job the batch runs the directional kernels; the
   // others take the pattern a = 1, b = 0, whose factor is exactly 1
   // pass 0: every job's estimated work. The batch fills the device with all
-  // of it, so work items are sized from the batch's total (as a single call
-  // sizes them from its own): a job's items are those of a single call with
-  // item_taps = max(min_item_taps, batch total / balance_items) of its class.
+  // of it, so its items are sized from the batch's total as a single call
+  // sizes them from its own (max(min_item_taps, total / balance_items) of
+  // the job's class), capped at the tuned batch item size: many small items
+  // cost margin and partial writes, a few large ones leave an uneven tail.
   double batch_taps = 0.0;
   for (int j = 0; j < n_jobs; ++j) {
     Plan &p = plans[j];
@@ -692,7 +702,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     if (!(sched && sched->item_taps > 0.0)) {
       ism_schedule js{};
       if (sched) js = *sched;
-      js.item_taps = item_target(batch_taps, p.wt, p.half, p.ra.n_samples, sched);
+      js.item_taps = std::min(batch_item_taps(p.wt, p.half), item_target(batch_taps, p.wt, p.half, p.ra.n_samples, sched));
       const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, &js, false);
       if (stt != ISM_OK) return stt;
     }

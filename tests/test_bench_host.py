@@ -42,14 +42,15 @@ def test_tuner_header_round_trip(tmp_path):
                 score = {(mt, bal): 1.0 + 0.01 * i for i, (mt, bal) in
                          enumerate((a, b) for a in autotune.MIN_TAPS for b in autotune.BALANCE)}
                 res[(wt, prec, ns)] = ((autotune.MIN_TAPS[0], autotune.BALANCE[0]), score, {}, ["w"])
-    waves[(64, "fp32")] = (6, {k: 1.0 for k in autotune.BATCH_WAVES})
+    waves[(64, "fp32")] = ((6, 2.5e5), {(k, it): 1.0 for k in autotune.BATCH_WAVES
+                                         for it in autotune.BATCH_ITEM_TAPS})
     p = tmp_path / "ism_tuning.h"
     autotune.write_header(res, waves, str(p), "test device")
     text = p.read_text()
     first = f"{autotune.MIN_TAPS[0]:.6g}, {autotune.BALANCE[0]:.1f}}}"
     for ns in autotune.NS_BUCKETS:
         assert text.count(f"{{32, 0, {ns}, " + first) == 1 and text.count(f"{{64, 1, {ns}, " + first) == 1
-    assert "constexpr ItemTuning kItemTuning[]" in text and "{64, 0, 6}," in text
+    assert "constexpr ItemTuning kItemTuning[]" in text and "{64, 0, 6, 250000}," in text
 
 
 def test_committed_tuning_table_covers_every_exact_window():
