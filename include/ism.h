@@ -288,7 +288,7 @@ int ism_filter_trajectory(const float *x, int n_x, const float *rir, int n_pos, 
 
 /* Filter methods of ism_filter_trajectory_ex. */
 enum {
-  ISM_FILTER_AUTO = 0,   /* FFT for RIRs of 2048 taps and more (when every input
+  ISM_FILTER_AUTO = 0,   /* FFT for RIRs of 1024 taps and more (when every input
                             block of the FFT path touches at most 4 segments),
                             direct otherwise                                   */
   ISM_FILTER_DIRECT = 1, /* the direct sum of ism_filter_trajectory            */
@@ -298,7 +298,7 @@ enum {
 
 /* Device workspace (bytes) of ism_filter_trajectory_ex for these sizes and
  * method: 0 for the direct sum; for the FFT path the spectra of every RIR
- * partition (about 4 times the RIR data), of the input blocks and of the
+ * partition (about twice the RIR data), of the input blocks and of the
  * output blocks. ISM_E_UNSUPPORTED for ISM_FILTER_FFT when one block of the
  * signal would touch more than 16 segments (segments much shorter than the
  * block); errors otherwise as for ism_filter_trajectory. */
@@ -309,7 +309,8 @@ int ism_filter_workspace_size(int n_x, int n_pos, int n_mic, int n_rir, int meth
  * for RIRs of 16384 taps and more, else a quarter of the next power of two of
  * n_rir, at least 256), splits each block at segment boundaries, multiplies
  * the spectra of the pieces with those of the B-tap partitions of their
- * segment's RIR (2B-point FP32 transforms, radix-2 Stockham in LDS), adds the
+ * segment's RIR (2B-point real FP32 transforms, computed as B-point complex
+ * Stockham transforms in LDS), adds the
  * products of each output block in a fixed order and overlap-adds the
  * inverse transforms: results are bitwise reproducible and agree with the
  * direct sum to FP32 transform rounding. Its cost per output sample grows

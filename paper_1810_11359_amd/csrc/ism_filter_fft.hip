@@ -1,6 +1,7 @@
 // Moving-source filtering (Sec. 3.4) by partitioned FFT convolution: the
 // paper filters the signal through the trajectory's RIRs with batched FFTs;
-// this is that path, written for gfx950 (radix-2 Stockham transforms in LDS).
+// this is that path, written for gfx950 (real transforms through half-size
+// complex Stockham transforms in LDS).
 //
 // The signal x is cut into segments of L = ceil(n_x / n_pos) samples and
 // segment p goes through RIR p (y_m[n] = sum_k x[n - k] h_{p(n-k), m}[k]).
@@ -26,62 +27,194 @@
 
 namespace ism {
 
-constexpr int FFT_MAX = 8192;   // largest transform (points)
+// Transforms: the real N-point transform of each block (N = 2B, the second
+// half zero) is taken as an M = N/2-point complex transform of the packed
+// sequence z[n] = x[2n] + i x[2n+1], then split into the spectrum of x: with
+// W = exp(-2 pi i / N),
+//   X[k] = (Z[k] + conj Z[M-k]) / 2 + W^k (Z[k] - conj Z[M-k]) / (2i), 0 < k < M,
+//   X[0] = Re Z[0] + Im Z[0], X[M] = Re Z[0] - Im Z[0] (both real),
+// stored as M complex bins, bin 0 holding (X[0], X[M]). The inverse runs the
+// same steps backwards (Z[k] = E[k] + i O[k] from Y[k] and conj Y[M-k], then
+// an inverse M-point transform scaled by 1/M gives y[2n] + i y[2n+1]).
+// The complex transforms are Stockham passes of radix 8 (then one of radix 4
+// or 2), each thread holding its butterflies' points in registers between
+// two barriers; the data stay in LDS (M complex per transform).
 constexpr int FFT_THREADS = 256;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// a times -i (forward) or +i (inverse)
+__device__ __forceinline__ float2 rot_i(float2 a, bool inv) {
+  return inv ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
 
-// tw[t] = exp(-2 pi i t / N), t < N/2
+// T[n] = exp(-2 pi i n / N), n < N
 __global__ __launch_bounds__(256) void fft_twiddle_kernel(float2 *__restrict__ tw, int N) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N / 2; t += gridDim.x * blockDim.x) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N; t += gridDim.x * blockDim.x) {
     float s, c;
     sincospi_acc(-2.0f * (float)t / (float)N, s, c);
     tw[t] = make_float2(c, s);
   }
 }
 
-// N-point transform (N a power of two, <= FFT_MAX) of a[0 .. N) in LDS, with
-// b[0 .. N) as scratch, by radix-2 Stockham stages: stage of span Ns reads
-// a[j], a[j + N/2] and writes the butterfly of twiddle exp(-+2 pi i k /
-// (2 Ns)), k = j mod Ns, to positions 2 (j - k) + k and + Ns; after log2 N
-// stages the result is in natural order. inverse: conjugate twiddles (no
-// 1/N). Returns the buffer that holds the result.
-__device__ float2 *lds_fft(float2 *a, float2 *b, int N, const float2 *__restrict__ tw, bool inverse) {
-  for (int Ns = 1; Ns < N; Ns <<= 1) {
-    __syncthreads();
-    const int step = N / (2 * Ns);
-    for (int j = threadIdx.x; j < N / 2; j += blockDim.x) {
-      const int k = j & (Ns - 1);
-      float2 w = tw[k * step];
-      if (inverse) w.y = -w.y;
-      const float2 u = a[j], v = cmul(a[j + N / 2], w);
-      const int o = 2 * (j - k) + k;
-      b[o] = make_float2(u.x + v.x, u.y + v.y);
-      b[o + Ns] = make_float2(u.x - v.x, u.y - v.y);
-    }
-    float2 *t = a;
-    a = b;
-    b = t;
+// R-point DFT of v in place (R = 2, 4, 8), kernel exp(-+2 pi i t s / R).
+template <int R>
+__device__ __forceinline__ void dft_small(float2 *v, bool inv) {
+  if constexpr (R == 2) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]), t2 = cadd(v[1], v[3]),
+                 t3 = rot_i(csub(v[1], v[3]), inv);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  } else {
+    // DFTs of the even and odd points, combined with exp(-+2 pi i s / 8)
+    float2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft_small<4>(e, inv);
+    dft_small<4>(o, inv);
+    constexpr float h = 0.70710678118654752f;  // 1 / sqrt(2)
+    const float2 o1 = inv ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+                          : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+    const float2 o2 = rot_i(o[2], inv);
+    const float2 o3 = inv ? make_float2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+                          : make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
   }
-  __syncthreads();
-  return a;
 }
 
-// Spectra of the RIR partitions: block (p * n_mic + m) * P + q.
-__global__ __launch_bounds__(FFT_THREADS) void fft_rir_kernel(const float *__restrict__ rir, int n_rir, int B,
-                                                            int N, int P, const float2 *__restrict__ tw,
+// Threads per transform and transforms per block for M-point transforms.
+template <int M> struct FftShape {
+  static constexpr int TPF = M / 8 < FFT_THREADS ? M / 8 : FFT_THREADS;
+  static constexpr int FPB = FFT_THREADS / TPF;
+};
+
+// One Stockham pass of radix R and span Ns over the M points at a (LDS): the
+// butterfly j (k = j mod Ns) takes a[j + t M/R], t < R, twiddles point t by
+// exp(-+2 pi i t k / (R Ns)) (table T of the N = 2M-point roots: index 2 t k
+// M / (R Ns)), and writes its DFT to a[(j - k) R + k + s Ns]. All reads of the
+// pass happen before the first barrier, all writes after it.
+template <int M, int R>
+__device__ __forceinline__ void fft_pass(float2 *a, int tid, const float2 *__restrict__ T, int Ns, bool inv) {
+  constexpr int TPF = FftShape<M>::TPF;
+  constexpr int NB = M / R / TPF;  // butterflies per thread
+  static_assert(NB >= 1 && NB * R * TPF == M, "pass shape");
+  float2 v[NB][R];
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[u][t] = a[tid + u * TPF + t * (M / R)];
+  __syncthreads();
+  const int step2 = 2 * (M / (R * Ns));
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int j = tid + u * TPF;
+    const int k = j & (Ns - 1);
+    if (Ns > 1) {
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        float2 w = T[t * k * step2];
+        if (inv) w.y = -w.y;
+        v[u][t] = cmul(v[u][t], w);
+      }
+    }
+    dft_small<R>(v[u], inv);
+    const int o = (j - k) * R + k;
+#pragma unroll
+    for (int s = 0; s < R; ++s) a[o + s * Ns] = v[u][s];
+  }
+  __syncthreads();
+}
+
+// M-point complex transform of a (LDS), natural order in and out.
+template <int M>
+__device__ __forceinline__ void fft_m(float2 *a, int tid, const float2 *__restrict__ T, bool inv) {
+  constexpr int LOG = __builtin_ctz(M);
+  int Ns = 1;
+#pragma unroll
+  for (int p = 0; p < LOG / 3; ++p) {
+    fft_pass<M, 8>(a, tid, T, Ns, inv);
+    Ns *= 8;
+  }
+  if constexpr (LOG % 3 == 1) fft_pass<M, 2>(a, tid, T, Ns, inv);
+  if constexpr (LOG % 3 == 2) fft_pass<M, 4>(a, tid, T, Ns, inv);
+}
+
+// Spectrum bins k < M of the real sequence packed in a (after fft_m) to o.
+template <int M>
+__device__ __forceinline__ void real_split(const float2 *a, int tid, const float2 *__restrict__ T,
+                                           float2 *__restrict__ o) {
+  constexpr int TPF = FftShape<M>::TPF;
+  for (int k = tid; k < M; k += TPF) {
+    if (k == 0) {
+      o[0] = make_float2(a[0].x + a[0].y, a[0].x - a[0].y);
+      continue;
+    }
+    const float2 zk = a[k], zm = make_float2(a[M - k].x, -a[M - k].y);  // conj Z[M-k]
+    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+    const float2 d = csub(zk, zm);
+    const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
+    o[k] = cadd(e, cmul(T[k], od));
+  }
+}
+
+// Packed spectrum Y (M bins) to the packed sequence Z in a (before the inverse fft_m).
+template <int M>
+__device__ __forceinline__ void real_merge(const float2 *__restrict__ Y, int tid, const float2 *__restrict__ T,
+                                           float2 *a) {
+  constexpr int TPF = FftShape<M>::TPF;
+  for (int k = tid; k < M; k += TPF) {
+    if (k == 0) {
+      const float2 y0 = Y[0];
+      a[0] = make_float2(0.5f * (y0.x + y0.y), 0.5f * (y0.x - y0.y));
+      continue;
+    }
+    const float2 yk = Y[k], ym = make_float2(Y[M - k].x, -Y[M - k].y);  // conj Y[M-k]
+    const float2 e = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y + ym.y));
+    const float2 w = make_float2(T[k].x, -T[k].y);  // exp(+2 pi i k / N)
+    const float2 d = csub(yk, ym);
+    const float2 od = cmul(make_float2(0.5f * d.x, 0.5f * d.y), w);
+    a[k] = make_float2(e.x - od.y, e.y + od.x);  // e + i od
+  }
+}
+
+// Spectra of the RIR partitions: transform row = (p * n_mic + m) * P + q.
+template <int M>
+__global__ __launch_bounds__(FFT_THREADS) void fft_rir_kernel(const float *__restrict__ rir, int n_rir, int P,
+                                                            int n_rows, const float2 *__restrict__ T,
                                                             float2 *__restrict__ H) {
-  __shared__ float2 buf[2][FFT_MAX];
-  const int row = blockIdx.x;
-  const int q = row % P;
-  const float *h = rir + (size_t)(row / P) * n_rir + (size_t)q * B;
-  const int len = min(B, n_rir - q * B);
-  for (int t = threadIdx.x; t < N; t += blockDim.x) buf[0][t] = make_float2(t < len ? h[t] : 0.0f, 0.0f);
-  const float2 *r = lds_fft(buf[0], buf[1], N, tw, false);
-  float2 *o = H + (size_t)row * N;
-  for (int t = threadIdx.x; t < N; t += blockDim.x) o[t] = r[t];
+  constexpr int TPF = FftShape<M>::TPF, FPB = FftShape<M>::FPB;
+  __shared__ float2 buf[FPB][M];
+  const int f = threadIdx.x / TPF, tid = threadIdx.x % TPF;
+  const int row = blockIdx.x * FPB + f;
+  float2 *a = buf[f];
+  if (row < n_rows) {
+    const int q = row % P;
+    const float *h = rir + (size_t)(row / P) * n_rir + (size_t)q * M;  // B = M samples per partition
+    const int len = min(M, n_rir - q * M);
+    for (int n = tid; n < M; n += TPF) {
+      const int i0 = 2 * n, i1 = 2 * n + 1;
+      a[n] = make_float2(i0 < len ? h[i0] : 0.0f, i1 < len ? h[i1] : 0.0f);
+    }
+  } else {
+    for (int n = tid; n < M; n += TPF) a[n] = make_float2(0.0f, 0.0f);
+  }
+  __syncthreads();
+  fft_m<M>(a, tid, T, false);
+  if (row < n_rows) real_split<M>(a, tid, T, H + (size_t)row * M);
 }
 
 // Segment of input block i's piece r, or -1 when the piece is empty.
@@ -92,30 +225,36 @@ __device__ __forceinline__ int piece_segment(int i, int r, int B, int L, int n_x
   return p;
 }
 
-// Spectra of the input pieces: block i * R + r.
+// Spectra of the input pieces: transform i * R + r (empty pieces are skipped:
+// their spectra are never read).
+template <int M>
 __global__ __launch_bounds__(FFT_THREADS) void fft_input_kernel(const float *__restrict__ x, int n_x, int n_pos,
-                                                              int L, int B, int N, int R,
-                                                              const float2 *__restrict__ tw, float2 *__restrict__ X) {
-  __shared__ float2 buf[2][FFT_MAX];
-  const int i = blockIdx.x / R, r = blockIdx.x % R;
-  const int p = piece_segment(i, r, B, L, n_x, n_pos);
-  float2 *o = X + (size_t)blockIdx.x * N;
-  if (p < 0) {  // uniform over the block; the spectrum is never read
-    return;
-  }
+                                                              int L, int R, int n_rows, const float2 *__restrict__ T,
+                                                              float2 *__restrict__ X) {
+  constexpr int TPF = FftShape<M>::TPF, FPB = FftShape<M>::FPB;
+  __shared__ float2 buf[FPB][M];
+  const int f = threadIdx.x / TPF, tid = threadIdx.x % TPF;
+  const int row = blockIdx.x * FPB + f;
+  float2 *a = buf[f];
+  const int i = row / R, r = row % R;
+  const int p = row < n_rows ? piece_segment(i, r, M, L, n_x, n_pos) : -1;
   const int s0 = p * L, s1 = min(s0 + L, n_x);
-  for (int t = threadIdx.x; t < N; t += blockDim.x) {
-    const int n = i * B + t;
-    buf[0][t] = make_float2((t < B && n >= s0 && n < s1) ? x[n] : 0.0f, 0.0f);
+  for (int n = tid; n < M; n += TPF) {
+    const int t0 = 2 * n, t1 = 2 * n + 1;  // sample offsets in the block (B = M)
+    const int g0 = i * M + t0, g1 = i * M + t1;
+    const bool ok0 = p >= 0 && t0 < M && g0 >= s0 && g0 < s1, ok1 = p >= 0 && t1 < M && g1 >= s0 && g1 < s1;
+    a[n] = make_float2(ok0 ? x[g0] : 0.0f, ok1 ? x[g1] : 0.0f);
   }
-  const float2 *res = lds_fft(buf[0], buf[1], N, tw, false);
-  for (int t = threadIdx.x; t < N; t += blockDim.x) o[t] = res[t];
+  __syncthreads();
+  fft_m<M>(a, tid, T, false);
+  if (p >= 0) real_split<M>(a, tid, T, X + (size_t)row * M);
 }
 
-// Y[m][b][k] = sum over q, then r of X[b - q][r][k] H[p][m][q][k].
-// grid = (N / 256, n_out_blocks, n_mic).
+// Y[m][b][k] = sum over q, then r of X[b - q][r][k] H[p][m][q][k], k < M
+// (bin 0 holds the two real bins 0 and M: their products are taken apart).
+// grid = (M / 256, n_out_blocks, n_mic).
 __global__ __launch_bounds__(256) void spectrum_mac_kernel(const float2 *__restrict__ X, const float2 *__restrict__ H,
-                                                           int n_x, int n_pos, int n_mic, int L, int B, int N, int P,
+                                                           int n_x, int n_pos, int n_mic, int L, int B, int M, int P,
                                                            int R, int n_in_blocks, float2 *__restrict__ Y) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, m = blockIdx.z;
@@ -127,27 +266,41 @@ __global__ __launch_bounds__(256) void spectrum_mac_kernel(const float2 *__restr
     for (int r = 0; r < R; ++r) {
       const int p = piece_segment(i, r, B, L, n_x, n_pos);
       if (p < 0) continue;  // uniform over the block
-      const float2 xv = X[((size_t)i * R + r) * N + k];
-      const float2 hv = H[(((size_t)p * n_mic + m) * P + q) * N + k];
-      acc.x = __builtin_fmaf(xv.x, hv.x, acc.x);
-      acc.x = __builtin_fmaf(-xv.y, hv.y, acc.x);
-      acc.y = __builtin_fmaf(xv.x, hv.y, acc.y);
-      acc.y = __builtin_fmaf(xv.y, hv.x, acc.y);
+      const float2 xv = X[((size_t)i * R + r) * M + k];
+      const float2 hv = H[(((size_t)p * n_mic + m) * P + q) * M + k];
+      if (k == 0) {
+        acc.x = __builtin_fmaf(xv.x, hv.x, acc.x);
+        acc.y = __builtin_fmaf(xv.y, hv.y, acc.y);
+      } else {
+        acc.x = __builtin_fmaf(xv.x, hv.x, acc.x);
+        acc.x = __builtin_fmaf(-xv.y, hv.y, acc.x);
+        acc.y = __builtin_fmaf(xv.x, hv.y, acc.y);
+        acc.y = __builtin_fmaf(xv.y, hv.x, acc.y);
+      }
     }
   }
-  Y[((size_t)m * gridDim.y + b) * N + k] = acc;
+  Y[((size_t)m * gridDim.y + b) * M + k] = acc;
 }
 
-// z[m][b] = real part of IFFT(Y[m][b]) / N; block m * n_out_blocks + b.
-__global__ __launch_bounds__(FFT_THREADS) void ifft_block_kernel(const float2 *__restrict__ Y, int N,
-                                                               const float2 *__restrict__ tw, float *__restrict__ z) {
-  __shared__ float2 buf[2][FFT_MAX];
-  const float2 *in = Y + (size_t)blockIdx.x * N;
-  for (int t = threadIdx.x; t < N; t += blockDim.x) buf[0][t] = in[t];
-  const float2 *res = lds_fft(buf[0], buf[1], N, tw, true);
-  const float inv_n = 1.0f / (float)N;
-  float *o = z + (size_t)blockIdx.x * N;
-  for (int t = threadIdx.x; t < N; t += blockDim.x) o[t] = res[t].x * inv_n;
+// z[m][b] = IFFT(Y[m][b]) (N real samples); transform row = m * n_out_blocks + b.
+template <int M>
+__global__ __launch_bounds__(FFT_THREADS) void ifft_block_kernel(const float2 *__restrict__ Y, int n_rows,
+                                                               const float2 *__restrict__ T, float *__restrict__ z) {
+  constexpr int TPF = FftShape<M>::TPF, FPB = FftShape<M>::FPB;
+  __shared__ float2 buf[FPB][M];
+  const int f = threadIdx.x / TPF, tid = threadIdx.x % TPF;
+  const int row = blockIdx.x * FPB + f;
+  float2 *a = buf[f];
+  if (row < n_rows) real_merge<M>(Y + (size_t)row * M, tid, T, a);
+  else
+    for (int n = tid; n < M; n += TPF) a[n] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+  fft_m<M>(a, tid, T, true);
+  if (row < n_rows) {
+    constexpr float inv_m = 1.0f / (float)M;
+    float2 *o = reinterpret_cast<float2 *>(z + (size_t)row * 2 * M);
+    for (int n = tid; n < M; n += TPF) o[n] = make_float2(a[n].x * inv_m, a[n].y * inv_m);
+  }
 }
 
 // y[m][bB + t] = z[m][b][t] + z[m][b - 1][B + t]; grid = (ceil(n_y / 256), n_mic).
@@ -184,38 +337,55 @@ bool fft_plan(int n_x, int n_pos, int n_mic, int n_rir, int max_pieces, FftPlan 
   f.n_out_blocks = (int)((n_y + f.B - 1) / f.B);
   size_t o = 0;
   f.off_tw = o;
-  o = fft_align(o + sizeof(float2) * (size_t)(f.N / 2));
+  o = fft_align(o + sizeof(float2) * (size_t)f.N);
   f.off_H = o;
-  o = fft_align(o + sizeof(float2) * (size_t)n_pos * n_mic * f.P * f.N);
+  o = fft_align(o + sizeof(float2) * (size_t)n_pos * n_mic * f.P * f.B);
   f.off_X = o;
-  o = fft_align(o + sizeof(float2) * (size_t)f.n_in_blocks * f.R * f.N);
+  o = fft_align(o + sizeof(float2) * (size_t)f.n_in_blocks * f.R * f.B);
   f.off_Y = o;
-  o = fft_align(o + sizeof(float2) * (size_t)n_mic * f.n_out_blocks * f.N);
+  o = fft_align(o + sizeof(float2) * (size_t)n_mic * f.n_out_blocks * f.B);
   f.off_z = o;
   o = fft_align(o + sizeof(float) * (size_t)n_mic * f.n_out_blocks * f.N);
   f.bytes = o;
   return true;
 }
 
-int launch_filter_fft(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
-                      const FftPlan &f, void *ws, hipStream_t st) {
-  char *w = (char *)ws;
-  float2 *tw = (float2 *)(w + f.off_tw), *H = (float2 *)(w + f.off_H), *X = (float2 *)(w + f.off_X),
+template <int M>
+static int launch_fft_m(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
+                        const FftPlan &f, char *w, hipStream_t st) {
+  constexpr int FPB = FftShape<M>::FPB;
+  float2 *T = (float2 *)(w + f.off_tw), *H = (float2 *)(w + f.off_H), *X = (float2 *)(w + f.off_X),
          *Y = (float2 *)(w + f.off_Y);
   float *z = (float *)(w + f.off_z);
-  hipLaunchKernelGGL(fft_twiddle_kernel, dim3((f.N / 2 + 255) / 256), dim3(256), 0, st, tw, f.N);
-  hipLaunchKernelGGL(fft_rir_kernel, dim3((unsigned)((size_t)n_pos * n_mic * f.P)), dim3(FFT_THREADS), 0, st, rir,
-                     n_rir, f.B, f.N, f.P, tw, H);
-  hipLaunchKernelGGL(fft_input_kernel, dim3((unsigned)(f.n_in_blocks * f.R)), dim3(FFT_THREADS), 0, st, x, n_x,
-                     n_pos, f.L, f.B, f.N, f.R, tw, X);
-  hipLaunchKernelGGL(spectrum_mac_kernel, dim3(f.N / 256, f.n_out_blocks, n_mic), dim3(256), 0, st, X, H, n_x, n_pos,
-                     n_mic, f.L, f.B, f.N, f.P, f.R, f.n_in_blocks, Y);
-  hipLaunchKernelGGL(ifft_block_kernel, dim3((unsigned)(n_mic * f.n_out_blocks)), dim3(FFT_THREADS), 0, st, Y, f.N,
-                     tw, z);
+  hipLaunchKernelGGL(fft_twiddle_kernel, dim3((f.N + 255) / 256), dim3(256), 0, st, T, f.N);
+  const int rir_rows = n_pos * n_mic * f.P;
+  hipLaunchKernelGGL(fft_rir_kernel<M>, dim3((rir_rows + FPB - 1) / FPB), dim3(FFT_THREADS), 0, st, rir, n_rir, f.P,
+                     rir_rows, T, H);
+  const int in_rows = f.n_in_blocks * f.R;
+  hipLaunchKernelGGL(fft_input_kernel<M>, dim3((in_rows + FPB - 1) / FPB), dim3(FFT_THREADS), 0, st, x, n_x, n_pos,
+                     f.L, f.R, in_rows, T, X);
+  hipLaunchKernelGGL(spectrum_mac_kernel, dim3(M / 256, f.n_out_blocks, n_mic), dim3(256), 0, st, X, H, n_x, n_pos,
+                     n_mic, f.L, f.B, M, f.P, f.R, f.n_in_blocks, Y);
+  const int out_rows = n_mic * f.n_out_blocks;
+  hipLaunchKernelGGL(ifft_block_kernel<M>, dim3((out_rows + FPB - 1) / FPB), dim3(FFT_THREADS), 0, st, Y, out_rows,
+                     T, z);
   const int n_y = n_x + n_rir - 1;
   hipLaunchKernelGGL(overlap_add_kernel, dim3((n_y + 255) / 256, n_mic), dim3(256), 0, st, z, f.B, f.N,
                      f.n_out_blocks, y, n_y);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_filter_fft(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
+                      const FftPlan &f, void *ws, hipStream_t st) {
+  char *w = (char *)ws;
+  switch (f.B) {  // M = B complex points per transform
+    case 256: return launch_fft_m<256>(x, n_x, rir, n_pos, n_mic, n_rir, y, f, w, st);
+    case 512: return launch_fft_m<512>(x, n_x, rir, n_pos, n_mic, n_rir, y, f, w, st);
+    case 1024: return launch_fft_m<1024>(x, n_x, rir, n_pos, n_mic, n_rir, y, f, w, st);
+    case 2048: return launch_fft_m<2048>(x, n_x, rir, n_pos, n_mic, n_rir, y, f, w, st);
+    case 4096: return launch_fft_m<4096>(x, n_x, rir, n_pos, n_mic, n_rir, y, f, w, st);
+    default: return -1;
+  }
 }
 
 }  // namespace ism

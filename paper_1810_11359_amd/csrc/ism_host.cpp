@@ -995,7 +995,7 @@ int filter_args(const float *x, int n_x, const float *rir, int n_pos, int n_mic,
   return ISM_OK;
 }
 
-// Resolves the method (auto: FFT for RIRs of 2048 taps and more when an input
+// Resolves the method (auto: FFT for RIRs of 1024 taps and more when an input
 // block touches at most kAutoMaxPieces segments) and the FFT plan.
 int filter_method(int n_x, int n_pos, int n_mic, int n_rir, int method, FftPlan &f, int &resolved) {
   if (method != ISM_FILTER_AUTO && method != ISM_FILTER_DIRECT && method != ISM_FILTER_FFT) return ISM_E_INVALID_ARG;
@@ -1005,7 +1005,7 @@ int filter_method(int n_x, int n_pos, int n_mic, int n_rir, int method, FftPlan 
   if (method == ISM_FILTER_FFT) {
     if (!ok) return ISM_E_UNSUPPORTED;
     resolved = ISM_FILTER_FFT;
-  } else if (ok && n_rir >= 2048) {
+  } else if (ok && n_rir >= 1024) {
     resolved = ISM_FILTER_FFT;
   }
   return ISM_OK;
