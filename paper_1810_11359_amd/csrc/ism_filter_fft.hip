@@ -105,32 +105,34 @@ template <int M> struct FftShape {
 // One Stockham pass of radix R and span Ns over the M points at a (LDS): the
 // butterfly j (k = j mod Ns) takes a[j + t M/R], t < R, twiddles point t by
 // exp(-+2 pi i t k / (R Ns)) (table T of the N = 2M-point roots: index 2 t k
-// M / (R Ns)), and writes its DFT to a[(j - k) R + k + s Ns]. All reads of the
-// pass happen before the first barrier, all writes after it.
+// M / (R Ns)), and writes its DFT to a[(j - k) R + k + s Ns]. The twiddles
+// are fetched first, all LDS reads of the pass happen before the first
+// barrier and all writes after it.
 template <int M, int R>
 __device__ __forceinline__ void fft_pass(float2 *a, int tid, const float2 *__restrict__ T, int Ns, bool inv) {
   constexpr int TPF = FftShape<M>::TPF;
   constexpr int NB = M / R / TPF;  // butterflies per thread
   static_assert(NB >= 1 && NB * R * TPF == M, "pass shape");
+  const int step2 = 2 * (M / (R * Ns));
+  float2 w[NB][R];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int k = (tid + u * TPF) & (Ns - 1);
+#pragma unroll
+    for (int t = 1; t < R; ++t) w[u][t] = T[t * k * step2];
+  }
   float2 v[NB][R];
 #pragma unroll
   for (int u = 0; u < NB; ++u)
 #pragma unroll
     for (int t = 0; t < R; ++t) v[u][t] = a[tid + u * TPF + t * (M / R)];
   __syncthreads();
-  const int step2 = 2 * (M / (R * Ns));
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int j = tid + u * TPF;
     const int k = j & (Ns - 1);
-    if (Ns > 1) {
 #pragma unroll
-      for (int t = 1; t < R; ++t) {
-        float2 w = T[t * k * step2];
-        if (inv) w.y = -w.y;
-        v[u][t] = cmul(v[u][t], w);
-      }
-    }
+    for (int t = 1; t < R; ++t) v[u][t] = cmul(v[u][t], inv ? make_float2(w[u][t].x, -w[u][t].y) : w[u][t]);
     dft_small<R>(v[u], inv);
     const int o = (j - k) * R + k;
 #pragma unroll
@@ -139,13 +141,33 @@ __device__ __forceinline__ void fft_pass(float2 *a, int tid, const float2 *__res
   __syncthreads();
 }
 
-// M-point complex transform of a (LDS), natural order in and out.
-template <int M>
-__device__ __forceinline__ void fft_m(float2 *a, int tid, const float2 *__restrict__ T, bool inv) {
+// M-point complex transform into a (LDS), natural order in and out; point n
+// of the input is load(n). The first pass (radix 8, span 1: no twiddles)
+// reads its points through load and writes a; the later passes work in a.
+template <int M, class Load>
+__device__ __forceinline__ void fft_m(Load &&load, float2 *a, int tid, const float2 *__restrict__ T, bool inv) {
   constexpr int LOG = __builtin_ctz(M);
-  int Ns = 1;
+  static_assert(LOG >= 6, "at least two radix-8 passes");
+  constexpr int TPF = FftShape<M>::TPF;
+  constexpr int NB = M / 8 / TPF;
+  {
+    float2 v[NB][8];
 #pragma unroll
-  for (int p = 0; p < LOG / 3; ++p) {
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[u][t] = load(tid + u * TPF + t * (M / 8));
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      dft_small<8>(v[u], inv);
+      const int j = tid + u * TPF;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) a[8 * j + s] = v[u][s];
+    }
+    __syncthreads();
+  }
+  int Ns = 8;
+#pragma unroll
+  for (int p = 1; p < LOG / 3; ++p) {
     fft_pass<M, 8>(a, tid, T, Ns, inv);
     Ns *= 8;
   }
@@ -171,24 +193,20 @@ __device__ __forceinline__ void real_split(const float2 *a, int tid, const float
   }
 }
 
-// Packed spectrum Y (M bins) to the packed sequence Z in a (before the inverse fft_m).
+// Point k of the packed sequence Z whose inverse transform gives a real
+// block, from its packed spectrum Y (M bins, bin 0 holding bins 0 and M).
 template <int M>
-__device__ __forceinline__ void real_merge(const float2 *__restrict__ Y, int tid, const float2 *__restrict__ T,
-                                           float2 *a) {
-  constexpr int TPF = FftShape<M>::TPF;
-  for (int k = tid; k < M; k += TPF) {
-    if (k == 0) {
-      const float2 y0 = Y[0];
-      a[0] = make_float2(0.5f * (y0.x + y0.y), 0.5f * (y0.x - y0.y));
-      continue;
-    }
-    const float2 yk = Y[k], ym = make_float2(Y[M - k].x, -Y[M - k].y);  // conj Y[M-k]
-    const float2 e = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y + ym.y));
-    const float2 w = make_float2(T[k].x, -T[k].y);  // exp(+2 pi i k / N)
-    const float2 d = csub(yk, ym);
-    const float2 od = cmul(make_float2(0.5f * d.x, 0.5f * d.y), w);
-    a[k] = make_float2(e.x - od.y, e.y + od.x);  // e + i od
+__device__ __forceinline__ float2 real_merge(const float2 *__restrict__ Y, int k, const float2 *__restrict__ T) {
+  if (k == 0) {
+    const float2 y0 = Y[0];
+    return make_float2(0.5f * (y0.x + y0.y), 0.5f * (y0.x - y0.y));
   }
+  const float2 yk = Y[k], ym = make_float2(Y[M - k].x, -Y[M - k].y);  // conj Y[M-k]
+  const float2 e = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y + ym.y));
+  const float2 w = make_float2(T[k].x, -T[k].y);  // exp(+2 pi i k / N)
+  const float2 d = csub(yk, ym);
+  const float2 od = cmul(make_float2(0.5f * d.x, 0.5f * d.y), w);
+  return make_float2(e.x - od.y, e.y + od.x);  // e + i od
 }
 
 // Spectra of the RIR partitions: transform row = (p * n_mic + m) * P + q.
@@ -200,21 +218,14 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_rir_kernel(const float *__res
   __shared__ float2 buf[FPB][M];
   const int f = threadIdx.x / TPF, tid = threadIdx.x % TPF;
   const int row = blockIdx.x * FPB + f;
-  float2 *a = buf[f];
-  if (row < n_rows) {
-    const int q = row % P;
-    const float *h = rir + (size_t)(row / P) * n_rir + (size_t)q * M;  // B = M samples per partition
-    const int len = min(M, n_rir - q * M);
-    for (int n = tid; n < M; n += TPF) {
-      const int i0 = 2 * n, i1 = 2 * n + 1;
-      a[n] = make_float2(i0 < len ? h[i0] : 0.0f, i1 < len ? h[i1] : 0.0f);
-    }
-  } else {
-    for (int n = tid; n < M; n += TPF) a[n] = make_float2(0.0f, 0.0f);
-  }
-  __syncthreads();
-  fft_m<M>(a, tid, T, false);
-  if (row < n_rows) real_split<M>(a, tid, T, H + (size_t)row * M);
+  const int q = row % P;
+  const float *h = rir + (size_t)(row / P) * n_rir + (size_t)q * M;  // B = M samples per partition
+  const int len = row < n_rows ? min(M, n_rir - q * M) : 0;
+  fft_m<M>([&](int n) {
+    const int i0 = 2 * n, i1 = 2 * n + 1;
+    return make_float2(i0 < len ? h[i0] : 0.0f, i1 < len ? h[i1] : 0.0f);
+  }, buf[f], tid, T, false);
+  if (row < n_rows) real_split<M>(buf[f], tid, T, H + (size_t)row * M);
 }
 
 // Segment of input block i's piece r, or -1 when the piece is empty.
@@ -235,19 +246,17 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_input_kernel(const float *__r
   __shared__ float2 buf[FPB][M];
   const int f = threadIdx.x / TPF, tid = threadIdx.x % TPF;
   const int row = blockIdx.x * FPB + f;
-  float2 *a = buf[f];
   const int i = row / R, r = row % R;
   const int p = row < n_rows ? piece_segment(i, r, M, L, n_x, n_pos) : -1;
-  const int s0 = p * L, s1 = min(s0 + L, n_x);
-  for (int n = tid; n < M; n += TPF) {
-    const int t0 = 2 * n, t1 = 2 * n + 1;  // sample offsets in the block (B = M)
-    const int g0 = i * M + t0, g1 = i * M + t1;
-    const bool ok0 = p >= 0 && t0 < M && g0 >= s0 && g0 < s1, ok1 = p >= 0 && t1 < M && g1 >= s0 && g1 < s1;
-    a[n] = make_float2(ok0 ? x[g0] : 0.0f, ok1 ? x[g1] : 0.0f);
-  }
-  __syncthreads();
-  fft_m<M>(a, tid, T, false);
-  if (p >= 0) real_split<M>(a, tid, T, X + (size_t)row * M);
+  // samples of the block (B = M) inside segment p: [lo, hi) relative to the block
+  const int lo = p >= 0 ? max(p * L - i * M, 0) : 0;
+  const int hi = p >= 0 ? min(min(p * L + L, n_x) - i * M, M) : 0;
+  const float *xb = x + (size_t)i * M;
+  fft_m<M>([&](int n) {
+    const int t0 = 2 * n, t1 = 2 * n + 1;
+    return make_float2(t0 >= lo && t0 < hi ? xb[t0] : 0.0f, t1 >= lo && t1 < hi ? xb[t1] : 0.0f);
+  }, buf[f], tid, T, false);
+  if (p >= 0) real_split<M>(buf[f], tid, T, X + (size_t)row * M);
 }
 
 // Y[m][b][k] = sum over q, then r of X[b - q][r][k] H[p][m][q][k], k < M
@@ -258,16 +267,21 @@ __global__ __launch_bounds__(256) void spectrum_mac_kernel(const float2 *__restr
                                                            int R, int n_in_blocks, float2 *__restrict__ Y) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, m = blockIdx.z;
+  const float2 *__restrict__ Xk = X + k;
+  const float2 *__restrict__ Hk = H + (size_t)m * P * M + k;
   float2 acc = make_float2(0.0f, 0.0f);
-  for (int q = 0; q < P; ++q) {
+  // input blocks i = b - q that exist: q in [q0, q1]; the pieces of block i
+  // are the segments p0(i), p0(i) + 1, ... up to the first empty one
+  const int q0 = max(0, b - (n_in_blocks - 1)), q1 = min(P - 1, b);
+  for (int q = q0; q <= q1; ++q) {
     const int i = b - q;
-    if (i < 0) break;
-    if (i >= n_in_blocks) continue;
+    const int lo = i * B, hi = min(lo + B, n_x);
+    const int p0 = lo / L;
     for (int r = 0; r < R; ++r) {
-      const int p = piece_segment(i, r, B, L, n_x, n_pos);
-      if (p < 0) continue;  // uniform over the block
-      const float2 xv = X[((size_t)i * R + r) * M + k];
-      const float2 hv = H[(((size_t)p * n_mic + m) * P + q) * M + k];
+      const int p = p0 + r;
+      if (p >= n_pos || p * L >= hi) break;  // uniform over the block
+      const float2 xv = Xk[((size_t)i * R + r) * M];
+      const float2 hv = Hk[((size_t)p * n_mic * P + q) * M];
       if (k == 0) {
         acc.x = __builtin_fmaf(xv.x, hv.x, acc.x);
         acc.y = __builtin_fmaf(xv.y, hv.y, acc.y);
@@ -290,14 +304,12 @@ __global__ __launch_bounds__(FFT_THREADS) void ifft_block_kernel(const float2 *_
   __shared__ float2 buf[FPB][M];
   const int f = threadIdx.x / TPF, tid = threadIdx.x % TPF;
   const int row = blockIdx.x * FPB + f;
-  float2 *a = buf[f];
-  if (row < n_rows) real_merge<M>(Y + (size_t)row * M, tid, T, a);
-  else
-    for (int n = tid; n < M; n += TPF) a[n] = make_float2(0.0f, 0.0f);
-  __syncthreads();
-  fft_m<M>(a, tid, T, true);
-  if (row < n_rows) {
+  const bool live = row < n_rows;
+  const float2 *Yr = Y + (size_t)(live ? row : 0) * M;
+  fft_m<M>([&](int n) { return live ? real_merge<M>(Yr, n, T) : make_float2(0.0f, 0.0f); }, buf[f], tid, T, true);
+  if (live) {
     constexpr float inv_m = 1.0f / (float)M;
+    const float2 *a = buf[f];
     float2 *o = reinterpret_cast<float2 *>(z + (size_t)row * 2 * M);
     for (int n = tid; n < M; n += TPF) o[n] = make_float2(a[n].x * inv_m, a[n].y * inv_m);
   }
