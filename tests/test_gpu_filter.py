@@ -18,6 +18,9 @@ CASES = [
     ("short_segments", 2500, 100, 2, 600),         # many segments per staged window
     ("every_sample_its_point", 300, 300, 1, 257),
     ("short_signal", 50, 3, 4, 2000),              # signal shorter than a block and than the RIR
+    ("blocks_1024", 7000, 5, 2, 3001),             # FFT blocks of 1024 samples (odd RIR length)
+    ("blocks_2048", 9000, 4, 2, 6000),             # FFT blocks of 2048 samples
+    ("blocks_4096_two_parts", 12000, 3, 1, 16500), # FFT blocks of 4096 samples, a partial last partition
 ]
 
 
