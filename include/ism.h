@@ -365,8 +365,9 @@ int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, 
  * class (or the schedule's item_taps when given). A
  * job's result therefore agrees within rounding (<= 1e-6 of the RIR peak)
  * with the job alone and with ism_simulate; it is bitwise that of
- * ism_simulate_ex with the same item_taps, and a batch of one job is bitwise
- * ism_simulate_ex with tail_rounds = 0. */
+ * ism_simulate_ex with the same item_taps, and a batch of one job (of fewer
+ * than B x balance_items estimated taps) is bitwise ism_simulate_ex with
+ * tail_rounds = 0. */
 int ism_batch_run(const ism_batch *batch, void *stream);
 
 /* ism_batch_run that also records the caller's HIP events ev_start before the
