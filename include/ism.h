@@ -360,9 +360,11 @@ int ism_batch_prepare(const ism_job *jobs, int n_jobs, int precision, void *ws, 
 /* Simulates every job of a prepared batch on stream: kernel launches only (no
  * host-device copies, no allocation), so it can be captured in a HIP graph and
  * replayed. Work items are sized from the batch's total work: each job is
- * planned as a single call with item_taps = min(B, max(min_item_taps, batch
- * taps / balance_items)) of its class, B the tuned largest batch item of the
- * class (or the schedule's item_taps when given). A
+ * planned as a single call with item_taps = t = min(B, max(min_item_taps,
+ * batch taps / balance_items)) of its class, B the tuned largest batch item
+ * of the class, or, for a batch of less than t taps per resident wave, with
+ * its taps over the resident waves (at least 1e4); the schedule's item_taps
+ * replaces both when given. A
  * job's result therefore agrees within rounding (<= 1e-6 of the RIR peak)
  * with the job alone and with ism_simulate; it is bitwise that of
  * ism_simulate_ex with the same item_taps, and a batch of one job (of fewer

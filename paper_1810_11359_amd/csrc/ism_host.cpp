@@ -148,6 +148,15 @@ double batch_item_taps(int wt, bool half) {
 constexpr double kResidentWaves = 256.0 * 4.0 * kAccWavesPerSimd;
 constexpr double kTailRounds = 1.0;
 
+// Small calls: a call whose work does not give every resident wave an item
+// of the tuned size is spread over them instead, total / resident waves per
+// item but at least kSmallItemTaps, which is also the taper's lowest item (a
+// single 4800-sample RIR, 1e7 taps, measured 27 us per accumulate launch with
+// 1e4-tap items against 35 us with the earlier floor of an eighth of 1.2e5
+// and 103 us with 1.2e5-tap items).
+constexpr double kSmallItemTaps = 1e4;
+double small_call_floor(double total_taps) { return std::max(kSmallItemTaps, total_taps / kResidentWaves); }
+
 bool valid_schedule(const ism_schedule *sc) {
   if (!sc) return true;
   const double v[5] = {sc->item_taps, sc->min_item_taps, sc->balance_items, sc->tail_rounds, sc->batch_waves};
@@ -230,21 +239,24 @@ int make_plan(const ism_room *r, int n_src, int n_rcv, int precision, Plan &p, c
   }
   // an explicit item size is used as given
   const bool fixed = sched && sched->item_taps > 0.0;
-  const double target = fixed ? std::max(1e3, sched->item_taps) : item_target(p.total_taps, p.wt, p.half, nS, sched);
+  double target = fixed ? std::max(1e3, sched->item_taps) : item_target(p.total_taps, p.wt, p.half, nS, sched);
+  if (!fixed && p.total_taps < kResidentWaves * target) target = std::min(target, small_call_floor(p.total_taps));
   // Tail taper: tiles are dispatched last first, and the items of a tile
   // dispatched when the work left (this tile included) is below tail_rounds
   // rounds of the resident waves are cut to that work over tail_rounds x the
-  // resident waves, down to target / 8, so the last waves of a launch finish
-  // close together instead of one full-size item after another.
+  // resident waves, down to target / 8 but not below kSmallItemTaps, so the
+  // last waves of a launch finish close together instead of one full-size
+  // item after another.
   const double tail_rounds =
       (fixed || !taper) ? 0.0 : (sched && sched->tail_rounds >= 0.0 ? sched->tail_rounds : kTailRounds);
+  const double floor_taps = std::min(target, std::max(kSmallItemTaps, target / 8.0));
   p.any_split = false;
   double rem = p.total_taps;
   for (int pos = 0; pos < pa.n_tiles; ++pos) {
     const int t = pa.n_tiles - 1 - pos;
     const double taps = p.tile_taps[t];
     double tt = target;
-    if (tail_rounds > 0.0) tt = std::max(target / 8.0, std::min(target, rem / (tail_rounds * kResidentWaves)));
+    if (tail_rounds > 0.0) tt = std::max(floor_taps, std::min(target, rem / (tail_rounds * kResidentWaves)));
     int ch = (int)std::ceil(taps / tt);
     ch = std::max(1, std::min(ch, MAX_CHUNKS));
     pa.chunks[t] = (uint8_t)ch;
@@ -683,7 +695,9 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   // of it, so its items are sized from the batch's total as a single call
   // sizes them from its own (max(min_item_taps, total / balance_items) of
   // the job's class), capped at the tuned batch item size: many small items
-  // cost margin and partial writes, a few large ones leave an uneven tail.
+  // cost margin and partial writes, a few large ones leave an uneven tail;
+  // a batch with less work than that per resident wave gets items of its
+  // work over the resident waves (at least kSmallItemTaps).
   double batch_taps = 0.0;
   for (int j = 0; j < n_jobs; ++j) {
     Plan &p = plans[j];
@@ -702,7 +716,10 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     if (!(sched && sched->item_taps > 0.0)) {
       ism_schedule js{};
       if (sched) js = *sched;
-      js.item_taps = std::min(batch_item_taps(p.wt, p.half), item_target(batch_taps, p.wt, p.half, p.ra.n_samples, sched));
+      const double t = std::min(batch_item_taps(p.wt, p.half), item_target(batch_taps, p.wt, p.half, p.ra.n_samples, sched));
+      // a batch too small to give every resident wave an item of that size is
+      // spread over them instead (the small-call rule of single calls)
+      js.item_taps = batch_taps < kResidentWaves * t ? std::min(t, small_call_floor(batch_taps)) : t;
       const int stt = make_plan(&jobs[j].room, jobs[j].n_src, jobs[j].n_rcv, precision, p, &js, false);
       if (stt != ISM_OK) return stt;
     }
