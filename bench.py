@@ -45,7 +45,10 @@ CPU_THREADS_MAX = 16
 # valid while the library bench.py loads hashes to the value recorded beside
 # it (the build is deterministic: edits that leave the code unchanged keep it)
 TRAFFIC_PROFILES = {"room_32_receivers": "profiles/accumulate_kernel_room_4x5x3_32rcv.md",
-                    "batch_rooms": "profiles/accumulate_batch_kernel_1024_rooms.md"}
+                    "batch_rooms": "profiles/accumulate_batch_kernel_1024_rooms.md",
+                    "moving_source_10s": "profiles/filter_moving_source_16k_8000_taps.md",
+                    "moving_source_48k_96000": "profiles/filter_moving_source_48k_96000_taps.md"}
+HBM_PEAK = 8000.0  # GB/s, MI355X HBM3E
 
 
 class _HipEvents:
@@ -88,24 +91,25 @@ def library_sha256() -> str:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(workload: str, precision: str):
-    """HBM bytes per launch of the accumulate kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
-    none for this workload or the library changed since it was taken."""
+def measured_traffic(workload: str, precision: str, key: str = "traffic_bytes_per_launch"):
+    """HBM bytes per launch of the timed kernel (or per call, for the keys of a
+    whole call) from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), or None when there is none for this workload or the
+    library changed since it was taken."""
     rel = TRAFFIC_PROFILES.get(workload) if precision == "fp32" else None
     if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
         return None
     vals = {}
     with open(os.path.join(ROOT, rel)) as fh:
         for line in fh:
-            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "library_sha256"):
+            if ":" in line and line.split(":", 1)[0] in (key, "library_sha256"):
                 k, v = line.split(":", 1)
                 vals[k] = v.strip()
-    if "traffic_bytes_per_launch" not in vals or not os.path.exists(ism_lib_path()):
+    if key not in vals or not os.path.exists(ism_lib_path()):
         return None
     if vals.get("library_sha256") != library_sha256():
         return None
-    return int(vals["traffic_bytes_per_launch"])
+    return int(vals[key])
 
 
 def host_cpu():
@@ -362,7 +366,25 @@ def bench_moving_source(args) -> int:
     achieved = 2.0 * macs / (ms_step / 1e3) / 1e12
     # value: the direct sum's multiply-adds per second of filtering (the FFT path
     # does far fewer operations for the same output; its rate in these units is
-    # an equivalent rate); roofline only for the direct sum
+    # an equivalent rate). Roofline: the direct sum against the FP32 vector
+    # peak (2 FLOP per multiply-add); the FFT path against HBM with the
+    # filter's algorithmic bytes (RIRs and signal read once, output written
+    # once) over the whole call
+    alg_bytes = 4 * (n_pos * n_mic * n_rir + int(x.shape[0]) + n_mic * (int(x.shape[0]) + n_rir - 1))
+    if resolved == "fft":
+        gbs = alg_bytes / (ms_step / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": gbs / HBM_PEAK,
+                    "traffic": measured_traffic(args.workload, "fp32", "traffic_bytes_per_call_fft"),
+                    "traffic_unit": "B per call, all kernels (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "kernel": "partitioned FFT path (whole call)", "kernel_ms_mean": ms_step,
+                    "algorithmic_bytes": alg_bytes}
+    else:
+        roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_VECTOR_PEAK,
+                    "traffic": measured_traffic(args.workload, "fp32", "traffic_bytes_per_launch_direct"),
+                    "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "kernel": "filter_kernel (whole call)", "kernel_ms_mean": ms_step, "flop_per_mac": 2,
+                    "algorithmic_bytes": alg_bytes}
     out = {"metric": "moving-source filter multiply-adds/s (G/s)", "value": macs / (ms_step / 1e3) / 1e9,
            "unit": "G MAC/s (direct-sum equivalent)", "filter_method": resolved,
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "prewarm_s": args.prewarm_s, "ms_per_step": ms_step,
@@ -372,10 +394,7 @@ def bench_moving_source(args) -> int:
                       "parallelism": "single GPU"},
            "simulate_rirs_ms": sim_ms,
            "wall_s_timed": time.perf_counter() - wall0,
-           "roofline": None if resolved == "fft" else
-           {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
-            "frac": achieved / FP32_VECTOR_PEAK, "traffic": None, "kernel": "filter_kernel (whole call)",
-            "kernel_ms_mean": ms_step, "flop_per_mac": 2}}
+           "roofline": roofline}
     print(json.dumps(out), flush=True)
     return 0
 

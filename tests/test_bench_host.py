@@ -30,6 +30,10 @@ def test_traffic_only_for_the_profiled_library(monkeypatch):
     assert t is None or (isinstance(t, int) and t > 180_828_612)
     assert bench.measured_traffic("room_32_receivers", "fp16") is None
     assert bench.measured_traffic("single_rir", "fp32") is None
+    # moving-source filter: the RIRs (307.2 MB) at least, direct and FFT
+    for key in ("traffic_bytes_per_launch_direct", "traffic_bytes_per_call_fft"):
+        t = bench.measured_traffic("moving_source_48k_96000", "fp32", key)
+        assert t is None or (isinstance(t, int) and t > 307_200_000)
     monkeypatch.setattr(bench, "library_sha256", lambda: "0" * 64)
     assert bench.measured_traffic("room_32_receivers", "fp32") is None
     assert bench.measured_traffic("batch_rooms", "fp32") is None
