@@ -7,7 +7,10 @@ length bucket (up to 8192, 32768 and more samples) it times the
 tap-accumulation kernel (HIP events the library records around it) on
 representative single-room and batch workloads of that bucket over a grid of
 (min_item_taps, balance_items) pairs and keeps the pair with the best
-geometric-mean time relative to each workload's fastest pair. For the
+geometric-mean time relative to each workload's fastest pair. Every
+candidate of a grid is prepared first and the candidates are timed in
+interleaved rounds once the clocks have settled, since neighbouring
+candidates differ by less than a box drifts over a minute. For the
 persistent batch launches of W = 64 it also picks, on the 1024-room batch, the
 workgroups per SIMD of the grid and the largest item of a batch job. It writes
 the table header the host planner compiles in; rebuild
@@ -102,26 +105,60 @@ def bucket_workloads(wt: int, ns_max: int):
     return out
 
 
-def time_kernel(ws, precision: str, ev: _Events, reps: int, schedule=None) -> float:
-    """Mean accumulate-kernel time (ms) of one call over the workload(s)."""
+def _interleaved(sims, ev: _Events, reps: int, rounds: int):
+    """Mean kernel ms of every simulator, timed in interleaved rounds
+    (alternating order) after the clocks have settled."""
+    import time
+
     import torch
 
+    keys = list(sims)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 1.5:
+        sims[keys[0]].run()
+        torch.cuda.synchronize()
+    acc = {k: [] for k in keys}
+    for rnd in range(rounds):
+        for k in (keys if rnd % 2 == 0 else keys[::-1]):
+            evs = [ev.pair() for _ in range(reps)]
+            for a, b in evs:
+                sims[k].run(ev_start=a, ev_stop=b)
+            torch.cuda.synchronize()
+            acc[k] += [ev.ms(a, b) for a, b in evs]
+            for a, b in evs:
+                ev.free(a, b)
+    return {k: float(np.mean(v)) for k, v in acc.items()}
+
+
+def _simulator(ws, precision: str, schedule):
     if len(ws) == 1:
         w = ws[0]
-        sim = ism.Simulator(ism.room_for(w), w.src, w.rcv, precision=precision, schedule=schedule)
-    else:
-        sim = ism.BatchSimulator([(ism.room_for(w), w.src, w.rcv) for w in ws], precision=precision,
-                                 schedule=schedule)
-    sim.run()
-    torch.cuda.synchronize()
-    pairs = [ev.pair() for _ in range(reps)]
-    for a, b in pairs:
-        sim.run(ev_start=a, ev_stop=b)
-    torch.cuda.synchronize()
-    t = [ev.ms(a, b) for a, b in pairs]
-    for a, b in pairs:
-        ev.free(a, b)
-    return float(np.mean(t))
+        return ism.Simulator(ism.room_for(w), w.src, w.rcv, precision=precision, schedule=schedule)
+    return ism.BatchSimulator([(ism.room_for(w), w.src, w.rcv) for w in ws], precision=precision, schedule=schedule)
+
+
+def time_item_grid(loads, precision: str, ev: _Events, reps: int, rounds: int = 3):
+    """{(min_item_taps, balance_items): [mean kernel ms per workload]} over the
+    grid, every pair and workload prepared first and timed in interleaved
+    rounds (neighbouring pairs differ by about a percent, the drift of a box
+    over a minute)."""
+    pairs = [(mt, bal) for mt in MIN_TAPS for bal in BALANCE]
+    sims = {(pr, i): _simulator(ws, precision, ism.Schedule(min_item_taps=pr[0], balance_items=pr[1]))
+            for pr in pairs for i, (_, ws) in enumerate(loads)}
+    t = _interleaved(sims, ev, reps, rounds)
+    return {pr: [t[(pr, i)] for i in range(len(loads))] for pr in pairs}
+
+
+def time_batch_grid(batch, precision: str, ev: _Events, reps: int, rounds: int = 4):
+    """Mean accumulate-kernel time (ms) of the batch for every (waves per SIMD,
+    item cap) pair, as {pair: [ms]}. The pairs differ by a few tenths of a
+    percent, less than the drift of one box over a minute, so every pair is
+    prepared first and the pairs are timed in interleaved rounds."""
+    jobs = [(ism.room_for(w), w.src, w.rcv) for w in batch]
+    pairs = [(k, it) for k in BATCH_WAVES for it in BATCH_ITEM_TAPS]
+    sims = {pr: ism.BatchSimulator(jobs, precision=precision, schedule=ism.Schedule(batch_waves=pr[0], item_taps=pr[1]))
+            for pr in pairs}
+    return {pr: [t] for pr, t in _interleaved(sims, ev, reps, rounds).items()}
 
 
 def _score(times, n_loads):
@@ -142,13 +179,10 @@ def tune(reps: int = 3, classes=(32, 64, 96, 128), precisions=("fp32", "fp16"), 
                 if not loads:
                     results[(wt, prec, ns_max)] = prev
                     continue
-                times = {}
-                for mt in MIN_TAPS:
-                    for bal in BALANCE:
-                        sc = ism.Schedule(min_item_taps=mt, balance_items=bal)
-                        times[(mt, bal)] = [time_kernel(ws, prec, ev, reps, sc) for _, ws in loads]
-                        log(f"W={wt} {prec} nS<={ns_max} min_item_taps={mt:g} balance_items={bal:g}: "
-                            + ", ".join(f"{name} {t:.3f} ms" for (name, _), t in zip(loads, times[(mt, bal)])))
+                times = time_item_grid(loads, prec, ev, reps)
+                for (mt, bal), tl in times.items():
+                    log(f"W={wt} {prec} nS<={ns_max} min_item_taps={mt:g} balance_items={bal:g}: "
+                        + ", ".join(f"{name} {t:.3f} ms" for (name, _), t in zip(loads, tl)))
                 score = _score(times, len(loads))
                 best = min(score, key=score.get)
                 results[(wt, prec, ns_max)] = prev = (best, score, times, [n for n, _ in loads])
@@ -156,8 +190,7 @@ def tune(reps: int = 3, classes=(32, 64, 96, 128), precisions=("fp32", "fp16"), 
                     f"(score {score[best]:.4f}; default pair {score[(1.2e5, 49152.0)]:.4f})")
             if wt == 64:
                 batch = workloads.batch_rooms(1024, seed=0, feasible=_feasible)
-                t = {(k, it): [time_kernel(batch, prec, ev, reps, ism.Schedule(batch_waves=k, item_taps=it))]
-                     for k in BATCH_WAVES for it in BATCH_ITEM_TAPS}
+                t = time_batch_grid(batch, prec, ev, reps)
                 sc = _score(t, 1)
                 waves[(wt, prec)] = (min(sc, key=sc.get), sc)
                 log(f"W={wt} {prec} batch (waves per SIMD, item taps): "
