@@ -37,7 +37,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "image-source sinc taps/s (G/s) + RIRs/s, FP32 vs FP16; p50/p99 serving latency"
-FLOP_PER_TAP = 18          # frozen accounting of one windowed-sinc tap
+# frozen accounting of one windowed-sinc tap: 1 sub, 1 mul, 1 mul, 5 FMA,
+# 1 mul, 1 reciprocal, 2 mul, 1 add, an FMA counting 2
+FLOP_PER_TAP = 18
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 FLOP/clk)
 # Host threads the oracle may use: the machine's CPU share for one GPU.
 CPU_THREADS_MAX = 16
