@@ -45,7 +45,7 @@ FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz
 CPU_THREADS_MAX = 16
 # rocprofv3 summaries holding the calibrated HBM traffic of the timed kernel,
 # valid while the library bench.py loads hashes to the value recorded beside
-# it (the build is deterministic: edits that leave the code unchanged keep it)
+# it (compiling is deterministic: edits that leave the code unchanged keep it)
 TRAFFIC_PROFILES = {"room_32_receivers": "profiles/accumulate_kernel_room_4x5x3_32rcv.md",
                     "batch_rooms": "profiles/accumulate_batch_kernel_1024_rooms.md",
                     "moving_source_10s": "profiles/filter_moving_source_16k_8000_taps.md",

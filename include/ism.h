@@ -38,7 +38,7 @@ enum {
   ISM_E_WORKSPACE = -4,      /* workspace missing or smaller than required         */
   ISM_E_DEVICE = -5,         /* HIP launch or runtime error                        */
   ISM_E_TOO_LARGE = -6,      /* problem exceeds a documented limit (see below)     */
-  ISM_E_UNSUPPORTED = -7     /* valid request this build does not implement        */
+  ISM_E_UNSUPPORTED = -7     /* valid request the library does not implement       */
 };
 
 /* Arithmetic used for the windowed-sinc taps. Geometry, delays and the
@@ -64,7 +64,7 @@ typedef struct {
                       cut-off frequency fs/2                                        */
 } ism_room;
 
-/* Limits of this build (ISM_E_TOO_LARGE beyond them). */
+/* Limits of the library (ISM_E_TOO_LARGE beyond them). */
 #define ISM_MAX_SAMPLES (256 * 1024) /* nS per RIR                                     */
 #define ISM_MAX_N_IMG 2048           /* N_a per axis                                   */
 #define ISM_MAX_PAIRS (1 << 22)      /* n_src * n_rcv per call                         */

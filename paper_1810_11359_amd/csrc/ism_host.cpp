@@ -298,7 +298,7 @@ const char *ism_status_string(int status) {
     case ISM_E_WORKSPACE: return "workspace missing or too small";
     case ISM_E_DEVICE: return "HIP device error";
     case ISM_E_TOO_LARGE: return "problem exceeds a library limit";
-    case ISM_E_UNSUPPORTED: return "request not supported by this build";
+    case ISM_E_UNSUPPORTED: return "request not supported by the library";
     default: return "unknown status";
   }
 }
