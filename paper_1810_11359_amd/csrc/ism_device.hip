@@ -39,7 +39,7 @@ namespace ism {
 constexpr int kBaseBits = (TILE <= 256) ? 8 : 9;
 constexpr uint32_t kBaseMask = (1u << kBaseBits) - 1u;
 static_assert(TILE <= (1 << kBaseBits), "tile-local bases must fit the record");
-// The delay fraction of the FP32 and table-tap records, in units of 2^-kFracBits.
+// The delay fraction of the table-tap record, in units of 2^-kFracBits.
 constexpr int kFracBits = 32 - kBaseBits;
 
 // ---------------------------------------------------------------------------
@@ -255,7 +255,7 @@ __device__ void window_const_entry(float W, int WT, int half, int jj, float *e) 
   if (!half) {
     float sn, cs;
     sincospi_acc(2.0f * (float)j / W, sn, cs);
-    e[0] = -sg * 0x1p-32f;
+    e[0] = -sg;
     e[1] = sg * (float)j;
     e[2] = cs;
     e[3] = sn;
@@ -658,13 +658,17 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // tile does not own the image. base = k0 - T0 is the tile-local LDS index of its
 // tap j = 1 - W/2 (the LDS tile starts at sample T0 + 1 - W/2). rec is the
 // staged record of the taps, which also carries the base:
-//   FP32: (F, CP, CQ, C/2) with F = fq 2^8 + base (bits of a uint32), fq the
-//         fraction in units of 2^-24; the taps use f = float(F) 2^-32, and
-//         C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W), CQ = C/2 sin(2 pi f/W)
-//         follow from that same f;
+//   FP32: (f, CP, CQ', C/2) with f the fraction in [2^-24, 1 - 2^-24],
+//         C = A sin(pi f)/pi, CP = C/2 cos(2 pi f/W), and CQ' the value
+//         CQ = C/2 sin(2 pi f/W) with the base in its 8 low mantissa bits.
+//         That changes CQ by less than 2^-15 of itself; CQ enters tap j as
+//         CQ sin(2 pi j/W) / (j - f) and |CQ| <= C/2 sin(2 pi/W) (W >= 4), so
+//         a tap moves by less than 2^-15 sin(2 pi/W) A/(2 pi): 4.8e-7 A at
+//         W = 64, 9.5e-7 A at W = 32;
 //   FP16: (t, A') with t = f - 1/2 in FP32 and A' the amplitude with the
 //         base in its 8 low mantissa bits (relative change < 2^-15);
-//   LUT:  (F, A) with F = fq 2^8 + base as for FP32 and A in FP32.
+//   LUT:  (F, A) with F = fq 2^8 + base (bits of a uint32), fq the fraction
+//         in units of 2^-24, and A in FP32.
 // The column gain cgain carries the constant factor of A: fs / (4 pi c)
 // for FP16 and LUT, and fs / (4 pi c) / (2 pi) for FP32, whose record holds C/2.
 template <bool HALF> struct StageRec { typedef f4v type; };
@@ -717,18 +721,17 @@ __device__ __forceinline__ ImageParams<HALF || LUT> image_params(const RoomArgs 
     const uint32_t fq = min((uint32_t)__builtin_rintf(fr * (float)(1u << kFracBits)), (1u << kFracBits) - 1u);
     p.rec = float2v{__uint_as_float((fq << kBaseBits) | ((uint32_t)p.base & kBaseMask)), A};
   } else {
-    // 24-bit fraction fq in [1, 2^24 - 2] (rounding moves the delay by at
-    // most 3e-8 samples) and the base in the low byte; float(F) rounds F to
-    // 24 bits, so f = float(F) 2^-32 lies in [2^-24, 1 - 2^-24].
-    const uint32_t fq = min(max((uint32_t)__builtin_rintf(fr * (float)(1u << kFracBits)), 1u), (1u << kFracBits) - 2u);
-    const uint32_t F = (fq << kBaseBits) | ((uint32_t)p.base & kBaseMask);
-    const float f = (float)F * 0x1p-32f;
+    // f at least 2^-24 (fr is at most 1 - 2^-24 already): no tap sits on the
+    // image itself, where the sinc's numerator and denominator both vanish.
+    const float f = fmaxf(fr, 0x1p-24f);
     // The hardware sine and cosine take the angle in turns; their relative
     // error (< 1e-6, also for the tiny angles of f near 0 or 1) enters each
     // tap of the image once. sin(pi f) is taken as sin(pi min(f, 1 - f)).
     const float C2 = A * __builtin_amdgcn_sinf(0.5f * fminf(f, 1.0f - f));
     const float turn = f * (GEN ? ra.inv_win : 1.0f / (float)WT);  // phi = 2 pi f / W in turns
-    p.rec = f4v{__uint_as_float(F), C2 * __builtin_amdgcn_cosf(turn), C2 * __builtin_amdgcn_sinf(turn), C2};
+    const float CQ = C2 * __builtin_amdgcn_sinf(turn);
+    const uint32_t Qb = (__float_as_uint(CQ) & ~kBaseMask) | ((uint32_t)p.base & kBaseMask);
+    p.rec = f4v{f, C2 * __builtin_amdgcn_cosf(turn), __uint_as_float(Qb), C2};
   }
   return p;
 }
@@ -900,7 +903,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     const TapConsts<WT> &K = tap_table<WT>();
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
-      nsg[m] = -K.sig[l + LPG * m] * 0x1p-32f;  // times float(F) = f 2^32
+      nsg[m] = -K.sig[l + LPG * m];
       sgj[m] = K.sig_j[l + LPG * m];
       cth[m] = K.cth[l + LPG * m];
       sth[m] = K.sth[l + LPG * m];
@@ -927,7 +930,10 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   // FP16) issued ahead.
   auto step = [&](const Rec P) {
     __asm__ volatile("" ::"v"(P));
-    const int b = (int)(__float_as_uint(HALF ? P.y : P.x) & kBaseMask);
+    uint32_t bw;  // record word that carries the base
+    if constexpr (NARROW) bw = __float_as_uint(HALF ? P.y : P.x);
+    else bw = __float_as_uint(P.z);
+    const int b = (int)(bw & kBaseMask);
     float *t = th + b;
     if constexpr (HALF) {
       // tap = A (c0 + t q(t)), q in packed FP16 two taps at a time, the
@@ -959,7 +965,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     } else if constexpr (GEN) {
       // general window: no half-period symmetry between the lane's taps; a
       // tap outside |j - f| < W/2 gets a zero reciprocal
-      const float fs = (float)__float_as_uint(P.x);  // f 2^32
+      const float fs = P.x;  // f
 #pragma unroll
       for (int m = 0; m < TPL; ++m) {
         float w = __builtin_fmaf(cth[m], P.y, P.w);
@@ -981,7 +987,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
           w[m] = __builtin_fmaf(sth[m], P.z, w[m]);
         }
       }
-      const float fs = (float)__float_as_uint(P.x);  // f 2^32
+      const float fs = P.x;  // f
 #pragma unroll
       for (int m = 0; m < TPL; ++m) {
         const float u = __builtin_fmaf(nsg[m], fs, sgj[m]);

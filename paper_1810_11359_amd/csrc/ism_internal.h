@@ -24,7 +24,7 @@ constexpr int MARG_UNIT = 32;
 // per-call constants, masking the taps outside |j - f| < W/2 (general mode).
 constexpr int MAX_WINDOW = 256;
 // Per-tap constants of a general-mode window, 8 floats per tap jj of the cap:
-// FP32 taps (-sigma 2^-32, sigma j, cos(2 pi j / W), sin(2 pi j / W), 0 ...),
+// FP32 taps (-sigma, sigma j, cos(2 pi j / W), sin(2 pi j / W), 0 ...),
 // FP16 taps (c0, c1, ..., c5, 0, 0) of the tap's interpolant.
 constexpr int WC_STRIDE = 8;
 // Window classes (cap, mode) one batch may hold: one persistent launch each.
