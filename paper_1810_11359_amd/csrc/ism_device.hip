@@ -39,8 +39,13 @@ namespace ism {
 constexpr int kBaseBits = (TILE <= 256) ? 8 : 9;
 constexpr uint32_t kBaseMask = (1u << kBaseBits) - 1u;
 static_assert(TILE <= (1 << kBaseBits), "tile-local bases must fit the record");
-// The delay fraction of the table-tap record, in units of 2^-kFracBits.
+// The delay fraction of the table-tap record (and of the FP32 record where
+// cq_base is false), in units of 2^-kFracBits.
 constexpr int kFracBits = 32 - kBaseBits;
+// Whether the FP32 record of window cap wt carries the base in CQ's low
+// mantissa bits (else beside the fraction): all but general windows of the
+// 32-sample cap.
+constexpr bool cq_base(int wt, bool gen) { return !(gen && wt == 32); }
 
 // ---------------------------------------------------------------------------
 // Float-float building blocks (Dekker / Knuth error-free transformations).
@@ -255,7 +260,7 @@ __device__ void window_const_entry(float W, int WT, int half, int jj, float *e) 
   if (!half) {
     float sn, cs;
     sincospi_acc(2.0f * (float)j / W, sn, cs);
-    e[0] = -sg;
+    e[0] = cq_base(WT, true) ? -sg : -sg * 0x1p-32f;  // times f, or times float(F) = f 2^32
     e[1] = sg * (float)j;
     e[2] = cs;
     e[3] = sn;
@@ -664,7 +669,11 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 //         That changes CQ by less than 2^-15 of itself; CQ enters tap j as
 //         CQ sin(2 pi j/W) / (j - f) and |CQ| <= C/2 sin(2 pi/W) (W >= 4), so
 //         a tap moves by less than 2^-15 sin(2 pi/W) A/(2 pi): 4.8e-7 A at
-//         W = 64, 9.5e-7 A at W = 32;
+//         W = 64, 9.5e-7 A at W = 32. General windows of the 32-sample cap
+//         (any W < 32, where that bound grows towards 4.9e-6 A) keep the
+//         fraction and the base in one word instead (cq_base false):
+//         (F, CP, CQ, C/2) with F = fq 2^8 + base, fq the fraction rounded
+//         to 24 bits, and f = float(F) 2^-32 for the taps and the factors;
 //   FP16: (t, A') with t = f - 1/2 in FP32 and A' the amplitude with the
 //         base in its 8 low mantissa bits (relative change < 2^-15);
 //   LUT:  (F, A) with F = fq 2^8 + base (bits of a uint32), fq the fraction
@@ -723,15 +732,31 @@ __device__ __forceinline__ ImageParams<HALF || LUT> image_params(const RoomArgs 
   } else {
     // f at least 2^-24 (fr is at most 1 - 2^-24 already): no tap sits on the
     // image itself, where the sinc's numerator and denominator both vanish.
-    const float f = fmaxf(fr, 0x1p-24f);
+    // Packed beside the base, f is rounded to 24 bits (the delay moves by at
+    // most 3e-8 samples) and float(F) 2^-32 stays in [2^-24, 1 - 2^-24].
+    constexpr bool CQB = cq_base(WT, GEN);
+    uint32_t F = 0;
+    float f;
+    if constexpr (CQB) {
+      f = fmaxf(fr, 0x1p-24f);
+    } else {
+      const uint32_t fq = min(max((uint32_t)__builtin_rintf(fr * (float)(1u << kFracBits)), 1u), (1u << kFracBits) - 2u);
+      F = (fq << kBaseBits) | ((uint32_t)p.base & kBaseMask);
+      f = (float)F * 0x1p-32f;
+    }
     // The hardware sine and cosine take the angle in turns; their relative
     // error (< 1e-6, also for the tiny angles of f near 0 or 1) enters each
     // tap of the image once. sin(pi f) is taken as sin(pi min(f, 1 - f)).
     const float C2 = A * __builtin_amdgcn_sinf(0.5f * fminf(f, 1.0f - f));
     const float turn = f * (GEN ? ra.inv_win : 1.0f / (float)WT);  // phi = 2 pi f / W in turns
     const float CQ = C2 * __builtin_amdgcn_sinf(turn);
-    const uint32_t Qb = (__float_as_uint(CQ) & ~kBaseMask) | ((uint32_t)p.base & kBaseMask);
-    p.rec = f4v{f, C2 * __builtin_amdgcn_cosf(turn), __uint_as_float(Qb), C2};
+    const float CP = C2 * __builtin_amdgcn_cosf(turn);
+    if constexpr (CQB) {
+      const uint32_t Qb = (__float_as_uint(CQ) & ~kBaseMask) | ((uint32_t)p.base & kBaseMask);
+      p.rec = f4v{f, CP, __uint_as_float(Qb), C2};
+    } else {
+      p.rec = f4v{__uint_as_float(F), CP, CQ, C2};
+    }
   }
   return p;
 }
@@ -931,7 +956,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
   auto step = [&](const Rec P) {
     __asm__ volatile("" ::"v"(P));
     uint32_t bw;  // record word that carries the base
-    if constexpr (NARROW) bw = __float_as_uint(HALF ? P.y : P.x);
+    if constexpr (NARROW || !cq_base(WT, GEN)) bw = __float_as_uint(HALF ? P.y : P.x);
     else bw = __float_as_uint(P.z);
     const int b = (int)(bw & kBaseMask);
     float *t = th + b;
@@ -965,7 +990,7 @@ __device__ __forceinline__ void accumulate_item(const RoomArgs &ra, const int ti
     } else if constexpr (GEN) {
       // general window: no half-period symmetry between the lane's taps; a
       // tap outside |j - f| < W/2 gets a zero reciprocal
-      const float fs = P.x;  // f
+      const float fs = cq_base(WT, GEN) ? P.x : (float)__float_as_uint(P.x);  // f, or f 2^32
 #pragma unroll
       for (int m = 0; m < TPL; ++m) {
         float w = __builtin_fmaf(cth[m], P.y, P.w);

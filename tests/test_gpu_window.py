@@ -4,8 +4,9 @@ parity of the general-mode kernels with the FP64 oracle, which takes any W.
 Each case is a small room the oracle finishes in seconds, at sampling rates
 and window lengths whose W is not one of the exact-mode windows {32, 64, 96,
 128}: 44.1 kHz x 4 ms (W = 176.4), 22.05 kHz x 4 ms (88.2), 48 kHz x 4 ms
-(192), 16 kHz x 2.5 ms (40), an odd W = 33 and a short W = 16.5. Tolerance:
-max|err| / oracle peak <= 1e-5 (FP32 taps), <= 2e-3 (FP16 taps).
+(192), 16 kHz x 2.5 ms (40), an odd W = 33, a short W = 16.5 and very short
+W = 6.4 and 4.4 (few taps per image, each with a large window-phase term).
+Tolerance: max|err| / oracle peak <= 1e-5 (FP32 taps), <= 2e-3 (FP16 taps).
 """
 import sys
 
@@ -29,6 +30,8 @@ WINDOWS = [
     ("16k_2.5ms_W40", 16000.0, 0.0025, 0.15),
     ("11k_3ms_W33", 11000.0, 0.003, 0.15),
     ("5.5k_3ms_W16.5", 5500.0, 0.003, 0.2),
+    ("8k_0.8ms_W6.4", 8000.0, 0.0008, 0.2),
+    ("11k_0.4ms_W4.4", 11000.0, 0.0004, 0.15),
 ]
 
 
