@@ -1272,17 +1272,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAccWavesPer
 // grid = (rir, dispatch position of the tile, 256-sample segment)
 // ---------------------------------------------------------------------------
 // v + x[0] + x[stride] + ... + x[(n - 1) stride], added in that order; the
-// loads of a group of eight are issued together (the order of the additions,
-// and so the result, does not depend on the grouping).
+// loads of a group of 32 (then 8) are issued together, so a tile split into
+// many items costs few memory round trips (the order of the additions, and
+// so the result, does not depend on the grouping).
+template <int B>
+__device__ __forceinline__ float ordered_block(float v, const float *__restrict__ x, size_t stride) {
+  float t[B];
+#pragma unroll
+  for (int u = 0; u < B; ++u) t[u] = x[(size_t)u * stride];
+#pragma unroll
+  for (int u = 0; u < B; ++u) v += t[u];
+  return v;
+}
 __device__ __forceinline__ float ordered_sum(float v, const float *__restrict__ x, size_t stride, int n) {
   int cc = 0;
-  for (; cc + 8 <= n; cc += 8) {
-    float t[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = x[(size_t)(cc + u) * stride];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v += t[u];
-  }
+  for (; cc + 32 <= n; cc += 32) v = ordered_block<32>(v, x + (size_t)cc * stride, stride);
+  for (; cc + 8 <= n; cc += 8) v = ordered_block<8>(v, x + (size_t)cc * stride, stride);
   for (; cc < n; ++cc) v += x[(size_t)cc * stride];
   return v;
 }
