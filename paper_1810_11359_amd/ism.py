@@ -25,6 +25,10 @@ ISM_E_WORKSPACE = -4
 ISM_E_DEVICE = -5
 ISM_E_TOO_LARGE = -6
 ISM_E_UNSUPPORTED = -7
+# Limits of the library (ISM_E_TOO_LARGE beyond them), as in include/ism.h.
+ISM_MAX_SAMPLES = 256 * 1024
+ISM_MAX_N_IMG = 2048
+ISM_MAX_PAIRS = 1 << 22
 
 PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "lut": 3}
 

@@ -99,6 +99,28 @@ def test_room_checks(kw, status):
     assert e.value.status == status
 
 
+def test_limits_at_their_edges():
+    # nS = ISM_MAX_SAMPLES and N = ISM_MAX_N_IMG plan; one more of either is refused
+    fs = 16000.0
+    at = _room(t_max=ism.ISM_MAX_SAMPLES / fs)
+    assert at.n_samples == ism.ISM_MAX_SAMPLES
+    assert ism.workspace_size(at, 1, 1) > 0
+    over = _room(t_max=(ism.ISM_MAX_SAMPLES + 1) / fs)
+    assert over.n_samples == ism.ISM_MAX_SAMPLES + 1
+    with pytest.raises(ism.IsmError) as e:
+        ism.workspace_size(over, 1, 1)
+    assert e.value.status == ism.ISM_E_TOO_LARGE
+    assert ism.workspace_size(_room(n_img=(ism.ISM_MAX_N_IMG, 1, 1)), 1, 1) > 0
+    with pytest.raises(ism.IsmError) as e:
+        ism.workspace_size(_room(n_img=(ism.ISM_MAX_N_IMG + 1, 1, 1)), 1, 1)
+    assert e.value.status == ism.ISM_E_TOO_LARGE
+    # source x receiver pairs per call
+    assert ism.workspace_size(_room(), 1, ism.ISM_MAX_PAIRS) > 0
+    with pytest.raises(ism.IsmError) as e:
+        ism.workspace_size(_room(), 2, ism.ISM_MAX_PAIRS // 2 + 1)
+    assert e.value.status == ism.ISM_E_TOO_LARGE
+
+
 def test_room_ok_and_workspace():
     r = _room()
     assert ism.lib().ism_check_room(ctypes.byref(r._c())) == ism.ISM_OK

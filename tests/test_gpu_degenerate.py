@@ -8,7 +8,9 @@
   arrives, so no image reaches the output; every sample must still be
   written (a NaN-filled output must come back as exact zeros);
 - one source with many receivers at the same point as another receiver
-  (identical pairs give identical RIRs, bit for bit).
+  (identical pairs give identical RIRs, bit for bit);
+- the limits: nS = ISM_MAX_SAMPLES exactly, and ISM_MAX_N_IMG lattice
+  indices along one axis.
 Tolerance as for the other FP32 cases: max|err| / oracle peak <= 1e-5.
 """
 import sys
@@ -91,3 +93,33 @@ def test_identical_pairs_identical_rirs():
     torch.cuda.synchronize()
     assert torch.equal(got[0, 0], got[0, 2]) and torch.equal(got[0, 0], got[0, 3])
     assert not torch.equal(got[0, 0], got[0, 1])
+
+
+def test_maximum_samples_sparse_lattice(oracle_mod):
+    """nS = ISM_MAX_SAMPLES exactly (1025 tiles, most without an image): a
+    3 x 3 x 3 lattice whose taps sit at the start of a 16.4 s RIR."""
+    fs = 16000.0
+    room = ism.Room([3.0, 4.0, 2.5], [0.9] * 6, (3, 3, 3), 343.0, fs, ism.ISM_MAX_SAMPLES / fs, 0.004)
+    assert room.n_samples == ism.ISM_MAX_SAMPLES
+    src, rcv = [[1.0, 1.5, 1.0]], [[2.2, 3.1, 1.7]]
+    _say(f"maximum nS = {room.n_samples}")
+    got = _host(room, src, rcv)
+    ref = _oracle(oracle_mod, room, src, rcv)
+    assert np.all(np.isfinite(got))
+    err = rel_err(got, ref)
+    print("rel err", err.ravel(), flush=True)
+    assert np.all(err <= TOL_FP32)
+
+
+def test_maximum_images_per_axis(oracle_mod):
+    """N = ISM_MAX_N_IMG images along one axis (2048 lattice indices, delays up
+    to ~95 000 samples), one along the others."""
+    room = ism.Room([1.0, 4.0, 3.0], [0.999] * 6, (ism.ISM_MAX_N_IMG, 1, 1), 343.0, 16000.0, 6.25, 0.004)
+    src, rcv = [[0.3, 2.0, 1.5]], [[0.8, 2.5, 1.2]]
+    _say(f"N = {room.n_img}, nS = {room.n_samples}")
+    got = _host(room, src, rcv)
+    ref = _oracle(oracle_mod, room, src, rcv)
+    assert np.all(np.isfinite(got))
+    err = rel_err(got, ref)
+    print("rel err", err.ravel(), flush=True)
+    assert np.all(err <= TOL_FP32)
