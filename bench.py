@@ -41,7 +41,7 @@ METRIC = "image-source sinc taps/s (G/s) + RIRs/s, FP32 vs FP16; p50/p99 serving
 # 1 mul, 1 reciprocal, 2 mul, 1 add, an FMA counting 2
 FLOP_PER_TAP = 18
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 FLOP/clk)
-# Host threads the oracle may use: the machine's CPU share for one GPU.
+# Host threads the oracle may use: the host CPU share of one GPU on a shared node.
 CPU_THREADS_MAX = 16
 # rocprofv3 summaries holding the calibrated HBM traffic of the timed kernel,
 # valid while the library bench.py loads hashes to the value recorded beside
