@@ -1288,7 +1288,16 @@ __device__ __forceinline__ float ordered_sum(float v, const float *__restrict__ 
   int cc = 0;
   for (; cc + 32 <= n; cc += 32) v = ordered_block<32>(v, x + (size_t)cc * stride, stride);
   for (; cc + 8 <= n; cc += 8) v = ordered_block<8>(v, x + (size_t)cc * stride, stride);
-  for (; cc < n; ++cc) v += x[(size_t)cc * stride];
+  if (cc < n) {  // the last (fewer than 8) terms, loaded together
+    const int m = n - cc;
+    float t[7];
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (u < m) t[u] = x[(size_t)(cc + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (u < m) v += t[u];
+  }
   return v;
 }
 
