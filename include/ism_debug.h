@@ -20,7 +20,7 @@ typedef struct {
   int32_t rir;     /* source * n_rcv + receiver                                      */
   int32_t n[3];    /* lattice index per room axis (x, y, z), Sec. 2.1               */
   int32_t k0;      /* floor(x), x = d fs / c the delay in samples (Eq. (3))          */
-  uint32_t fq;     /* x - k0 in units of 2^-24 (the rounded fraction the taps use)   */
+  uint32_t fq;     /* x - k0 rounded to units of 2^-24 (as the table taps use it)    */
   float amp;       /* Eq. (4) amplitude beta_n / (4 pi d_n), FP32                   */
   uint32_t pad;
 } ism_image_record;
