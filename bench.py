@@ -485,6 +485,43 @@ def bench_batch(args) -> int:
     return 0
 
 
+# The full-ISM cases of the paper's Table 4 (1, 16 and 128 RIRs at T60 0.7 s)
+# and Table 5 (128 RIRs at T60 0.3, 0.7 and 1.1 s): (T60 [s], RIRs)
+PAPER_TABLE_CASES = [(0.7, 1), (0.7, 16), (0.7, 128), (0.3, 128), (1.1, 128)]
+
+
+def bench_paper_tables(args) -> int:
+    """The room of the paper's Tables 4 and 5 (3 x 4 x 2.5 m, 16 kHz and 4 ms
+    assumed): one ism_simulate call per case and precision (FP32 and packed
+    FP16 taps), timed as the other single-room workloads. One JSON line with a
+    row per case; value = RIRs/s of the 128-RIR FP32 case at T60 0.7 s."""
+    from paper_1810_11359_amd import ism, workloads
+
+    rows = []
+    for t60, n_rcv in PAPER_TABLE_CASES:
+        w = workloads.paper_table_room(t60, n_rcv, 0)
+        room = ism.room_for(w)
+        taps = ism.count_taps(room, w.src, w.rcv)
+        row = {"t60_s": t60, "n_rirs": n_rcv, "n_samples": room.n_samples, "n_img": list(room.n_img),
+               "taps_per_call": int(taps)}
+        for prec in ("fp32", "fp16"):
+            sim = ism.Simulator(room, w.src, w.rcv, precision=prec)
+            ms, kern = _time_runs(sim, args.steps, args.warmup, args.prewarm_s)
+            row[prec] = {"ms_per_call": ms, "rirs_per_s": n_rcv / (ms / 1e3), "taps_per_s": taps / (ms / 1e3),
+                         "kernel_ms_mean": float(np.mean(kern))}
+        rows.append(row)
+    head = next(r for r in rows if r["t60_s"] == 0.7 and r["n_rirs"] == 128)
+    out = {"metric": "RIRs/s of the paper's full-ISM table cases", "value": head["fp32"]["rirs_per_s"],
+           "unit": "RIRs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "prewarm_s": args.prewarm_s,
+           "ms_per_step": head["fp32"]["ms_per_call"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": "paper_tables_room_3x4x2.5", "fs": 16000.0, "t_w_s": 0.004,
+                      "parallelism": "single GPU"},
+           "cases": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_single(args) -> int:
     """A single-room workload: one ism_simulate (or ism_simulate_diffuse) per step."""
     from paper_1810_11359_amd import ism, workloads
@@ -531,7 +568,7 @@ def main() -> int:
     ap.add_argument("--workload", default="batch_rooms",
                     choices=["batch_rooms", "room_32_receivers", "single_rir", "large_room_uca",
                              "paper_room_128rir", "paper_room_diffuse_1024rir", "moving_source_10s",
-                             "moving_source_48k_96000"])
+                             "moving_source_48k_96000", "paper_tables"])
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="RIRs the CPU oracle baseline computes (default 64 for the batch, 16 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -568,6 +605,8 @@ def main() -> int:
         return bench_moving_source(args)
     if args.workload == "batch_rooms":
         return bench_batch(args)
+    if args.workload == "paper_tables":
+        return bench_paper_tables(args)
     return bench_single(args)
 
 

@@ -101,6 +101,14 @@ def paper_room_128rir(seed: int = 0) -> Workload:
                     _uniform_positions(rng, room, 128), t_max=0.7)
 
 
+def paper_table_room(t60: float, n_rcv: int, seed: int = 0) -> Workload:
+    """The full-ISM cases of the paper's Tables 4 and 5: the 3 x 4 x 2.5 m room
+    at T60 = T_max = t60 with 1 source and n_rcv receivers (the first n_rcv of
+    the 128 positions of paper_room_128rir, so the cases are nested)."""
+    w = paper_room_128rir(seed)
+    return Workload(f"room_3x4x2.5_t60_{t60:g}_{n_rcv}rcv", w.room, t60, w.src, w.rcv[:n_rcv], t_max=t60)
+
+
 def paper_room_diffuse_1024rir(seed: int = 0) -> Workload:
     """The diffuse-model case of the paper's Table 4 (1024 RIRs, T60 0.7 s, same
     room): ISM up to the 13 dB attenuation time (T60 13/60, the switch the paper

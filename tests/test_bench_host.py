@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 import bench
 
 
@@ -72,3 +74,14 @@ def test_committed_tuning_table_covers_every_exact_window():
     for wt in (32, 64, 96, 128):
         for half in ("0", "1"):
             assert any(int(e[0]) == wt and e[1] == half and int(e[2]) == 2147483647 for e in entries), (wt, half)
+
+
+def test_paper_table_cases_are_nested():
+    from paper_1810_11359_amd import workloads
+
+    full = workloads.paper_room_128rir(0)
+    for t60, n_rcv in bench.PAPER_TABLE_CASES:
+        w = workloads.paper_table_room(t60, n_rcv, 0)
+        assert w.t60 == t60 and w.t_max == t60
+        np.testing.assert_array_equal(w.src, full.src)
+        np.testing.assert_array_equal(w.rcv, full.rcv[:n_rcv])
