@@ -1269,7 +1269,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAccWavesPer
 // where the own sum is the ordered sum of the tile's partials when it was
 // split and the value already in the output otherwise. Every term is added in
 // a fixed order, so results do not depend on scheduling.
-// grid = (rir, dispatch position of the tile, 256-sample segment)
+// grid = (rir, dispatch position of the tile, segment of the tile)
 // ---------------------------------------------------------------------------
 // v + x[0] + x[stride] + ... + x[(n - 1) stride], added in that order; the
 // loads of a group of 32 (then 8) are issued together, so a tile split into
@@ -1301,67 +1301,117 @@ __device__ __forceinline__ float ordered_sum(float v, const float *__restrict__ 
   return v;
 }
 
+// A run of n terms added to v in the fixed order of the reduce (the run
+// length alone decides it): fewer than RED_SLICE_MIN terms one by one, more as
+// RED_SLICES consecutive slices, each summed in order from its first term,
+// whose sums are then added to v in slice order. Launches with a long run
+// take RED_SLICES threads per sample (a block covers RED_SAMPLES samples):
+// each thread sums one slice and the sample's first thread adds the slice
+// sums; the others take one thread per sample and add term by term (all
+// their runs are short). n is uniform over the block (its barriers are);
+// active: this thread's sample takes the run.
+constexpr int RED_SAMPLES = 256 / RED_SLICES;
+static_assert(TILE % RED_SAMPLES == 0, "reduce blocks tile the tile");
+__device__ __forceinline__ float run_sum(float v, const float *__restrict__ x, size_t stride, int n, bool active,
+                                         int slice, int ks, float (*red)[RED_SAMPLES]) {
+  if (n < RED_SLICE_MIN) {
+    if (active && slice == 0) v = ordered_sum(v, x, stride, n);
+    return v;
+  }
+  const int m = (n + RED_SLICES - 1) / RED_SLICES;
+  const int a = slice * m, len = min(m, n - a);
+  red[slice][ks] = active ? ordered_sum(0.0f, x + (size_t)a * stride, stride, len) : 0.0f;
+  __syncthreads();
+  if (active && slice == 0) {
+#pragma unroll
+    for (int i = 0; i < RED_SLICES; ++i) v += red[i][ks];
+  }
+  __syncthreads();
+  return v;
+}
+
+template <bool SLICED>
 __global__ __launch_bounds__(256) void reduce_kernel(RoomArgs ra, PlanArgs pa, const float *__restrict__ part,
                                                      const float *__restrict__ marg, float *__restrict__ out) {
+  constexpr int SPB = SLICED ? RED_SAMPLES : 256;  // samples per block
+  __shared__ float red[SLICED ? RED_SLICES : 1][SLICED ? RED_SAMPLES : 1];
   const int pos = blockIdx.y;
   const int tile_id = pa.n_tiles - 1 - pos;
   const int C = pa.chunks[tile_id];
   const int rir = blockIdx.x;
   const int T0 = tile_id * TILE;
-  const int k = blockIdx.z * 256 + threadIdx.x;
-  if (k >= ra.n_samples - T0 || k >= TILE) return;
+  const int ks = (int)threadIdx.x % SPB, slice = (int)threadIdx.x / SPB;
+  const int k0 = blockIdx.z * SPB, k = k0 + ks;
   const int W = (int)(2.0f * ra.half_w);
   const int LM = W / 2 - 1;
-  const bool zl = tile_id > 0 && k < W / 2;                  // right margin of tile t-1
-  const bool zr = tile_id + 1 < pa.n_tiles && k >= TILE - LM;  // left margin of tile t+1
-  if (C <= 1 && !zl && !zr) return;
+  // block-uniform: which runs exist for some sample of this block
+  const bool has_l = tile_id > 0 && k0 < W / 2;                    // right margin of tile t-1
+  const bool has_r = tile_id + 1 < pa.n_tiles && k0 + SPB > TILE - LM;  // left margin of tile t+1
+  if (C <= 1 && !has_l && !has_r) return;
+  const bool in = k < ra.n_samples - T0 && k < TILE;
+  const bool zl = in && has_l && k < W / 2;
+  const bool zr = in && has_r && k >= TILE - LM;
+  auto add = [&](float v, const float *x, size_t stride, int n, bool active) {
+    if constexpr (SLICED) return run_sum(v, x, stride, n, active, slice, ks, red);
+    else return active ? ordered_sum(v, x, stride, n) : v;  // n < RED_SLICE_MIN
+  };
   float *o = out + (size_t)rir * ra.n_samples + T0 + k;
-  float v;
+  float v = 0.0f;
   if (C > 1) {
     const size_t first = (size_t)plan_first_item(pa, pos) + (size_t)rir * C;
-    v = ordered_sum(0.0f, part + first * TILE + k, TILE, C);
-  } else {
+    v = add(0.0f, part + first * TILE + k, TILE, C, in);
+  } else if (in && slice == 0 && (zl || zr)) {
     v = *o;
   }
-  if (zl) {  // tile t-1 is dispatched at pos + 1
+  if (has_l) {  // tile t-1 is dispatched at pos + 1
     const int Cp = pa.chunks[tile_id - 1];
     const size_t first = (size_t)plan_first_item(pa, pos + 1) + (size_t)rir * Cp;
-    v = ordered_sum(v, marg + first * W + LM + k, W, Cp);
+    v = add(v, marg + first * W + LM + k, W, Cp, zl);
   }
-  if (zr) {  // tile t+1 is dispatched at pos - 1
+  if (has_r) {  // tile t+1 is dispatched at pos - 1
     const int Cn = pa.chunks[tile_id + 1];
     const size_t first = (size_t)plan_first_item(pa, pos - 1) + (size_t)rir * Cn;
-    v = ordered_sum(v, marg + first * W + (k - (TILE - LM)), W, Cn);
+    v = add(v, marg + first * W + (k - (TILE - LM)), W, Cn, zr);
   }
-  *o = v;
+  if (in && slice == 0 && (C > 1 || zl || zr)) *o = v;
 }
 
-// Batch mode: grid = (output tile of a batch RIR, 256-sample segment).
+// Batch mode: grid = (output tile of a batch RIR, segment of the tile).
+template <bool SLICED>
 __global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restrict__ jobs,
-                                                           const BatchReduce *__restrict__ red,
+                                                           const BatchReduce *__restrict__ red_tab,
                                                            const float *__restrict__ part,
                                                            const float *__restrict__ marg) {
-  const BatchReduce br = red[blockIdx.x];
+  constexpr int SPB = SLICED ? RED_SAMPLES : 256;
+  __shared__ float red[SLICED ? RED_SLICES : 1][SLICED ? RED_SAMPLES : 1];
+  const BatchReduce br = red_tab[blockIdx.x];
   const JobDev &jb = jobs[br.job];
   const int n_samples = jb.ra.n_samples;
   const int T0 = (int)br.tile * TILE;
-  const int k = blockIdx.y * 256 + threadIdx.x;
-  if (k >= n_samples - T0 || k >= TILE) return;
+  const int ks = (int)threadIdx.x % SPB, slice = (int)threadIdx.x / SPB;
+  const int k0 = blockIdx.y * SPB, k = k0 + ks;
   const int W = (int)(2.0f * jb.ra.half_w);
   const int LM = W / 2 - 1;
-  const bool zl = br.nprev > 0 && k < W / 2;
-  const bool zr = br.nnext > 0 && k >= TILE - LM;
-  if (br.chunks <= 1 && !zl && !zr) return;
+  const bool has_l = br.nprev > 0 && k0 < W / 2;
+  const bool has_r = br.nnext > 0 && k0 + SPB > TILE - LM;
+  if (br.chunks <= 1 && !has_l && !has_r) return;
+  const bool in = k < n_samples - T0 && k < TILE;
+  const bool zl = in && has_l && k < W / 2;
+  const bool zr = in && has_r && k >= TILE - LM;
+  auto add = [&](float v, const float *x, size_t stride, int n, bool active) {
+    if constexpr (SLICED) return run_sum(v, x, stride, n, active, slice, ks, red);
+    else return active ? ordered_sum(v, x, stride, n) : v;  // n < RED_SLICE_MIN
+  };
   float *o = jb.out + (size_t)br.rir * n_samples + T0 + k;
-  float v;
+  float v = 0.0f;
   if (br.chunks > 1) {
-    v = ordered_sum(0.0f, part + (size_t)br.first * TILE + k, TILE, br.chunks);
-  } else {
+    v = add(0.0f, part + (size_t)br.first * TILE + k, TILE, br.chunks, in);
+  } else if (in && slice == 0 && (zl || zr)) {
     v = *o;
   }
-  if (zl) v = ordered_sum(v, marg + (size_t)br.mprev * MARG_UNIT + LM + k, W, br.nprev);
-  if (zr) v = ordered_sum(v, marg + (size_t)br.mnext * MARG_UNIT + (k - (TILE - LM)), W, br.nnext);
-  *o = v;
+  if (has_l) v = add(v, marg + (size_t)br.mprev * MARG_UNIT + LM + k, W, br.nprev, zl);
+  if (has_r) v = add(v, marg + (size_t)br.mnext * MARG_UNIT + (k - (TILE - LM)), W, br.nnext, zr);
+  if (in && slice == 0 && (br.chunks > 1 || zl || zr)) *o = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1500,8 +1550,9 @@ __global__ void queue_init_kernel(uint32_t *queue, uint4 a, uint4 b) {
 int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
                  const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
                  const uint32_t *class_grid, const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
-                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
-                 float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                 const BatchReduce *red, uint32_t n_red, bool long_runs, AxisEntry *tab, AxisOrigin *origin,
+                 int *valid, float *part, float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start,
+                 hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
   if (hipGetLastError() != hipSuccess) return -1;
   if (any_gen) {
@@ -1532,7 +1583,12 @@ int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *r
   }
   if (ev_stop && hipEventRecord(ev_stop, st) != hipSuccess) return -1;
   if (n_red > 0) {
-    hipLaunchKernelGGL(reduce_batch_kernel, dim3(n_red, TILE / 256), dim3(256), 0, st, jobs, red, part, marg);
+    // runs of RED_SLICE_MIN terms or more: RED_SLICES threads per sample
+    if (long_runs)
+      hipLaunchKernelGGL(reduce_batch_kernel<true>, dim3(n_red, TILE / RED_SAMPLES), dim3(256), 0, st, jobs, red, part,
+                         marg);
+    else
+      hipLaunchKernelGGL(reduce_batch_kernel<false>, dim3(n_red, TILE / 256), dim3(256), 0, st, jobs, red, part, marg);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;
@@ -1540,8 +1596,14 @@ int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *r
 
 int launch_reduce(const RoomArgs &ra, const PlanArgs &pa, int n_rir, const float *part, const float *marg,
                   float *out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)n_rir, (unsigned)pa.n_tiles, TILE / 256), dim3(256), 0, st, ra,
-                     pa, part, marg, out);
+  int max_c = 0;  // longest run: the most items of any tile (its own, or a neighbour's margins)
+  for (int t = 0; t < pa.n_tiles; ++t) max_c = max(max_c, (int)pa.chunks[t]);
+  if (max_c >= RED_SLICE_MIN)
+    hipLaunchKernelGGL(reduce_kernel<true>, dim3((unsigned)n_rir, (unsigned)pa.n_tiles, TILE / RED_SAMPLES), dim3(256),
+                       0, st, ra, pa, part, marg, out);
+  else
+    hipLaunchKernelGGL(reduce_kernel<false>, dim3((unsigned)n_rir, (unsigned)pa.n_tiles, TILE / 256), dim3(256), 0, st,
+                       ra, pa, part, marg, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -32,8 +32,9 @@ int launch_dump(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items
 int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
                  const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
                  const uint32_t *class_grid, const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
-                 const BatchReduce *red, uint32_t n_red, AxisEntry *tab, AxisOrigin *origin, int *valid, float *part,
-                 float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
+                 const BatchReduce *red, uint32_t n_red, bool long_runs, AxisEntry *tab, AxisOrigin *origin,
+                 int *valid, float *part, float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start,
+                 hipEvent_t ev_stop);
 int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
                    double t60, uint64_t seed, hipStream_t st);
 int launch_filter(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
@@ -644,7 +645,8 @@ struct BatchState {  // stored in ism_batch::opaque
   uint64_t off_jobs, off_rirs, off_items, off_red, off_pos, off_valid, off_origin, off_tab, off_part, off_marg,
       off_queue, off_wc;
   uint32_t n_rir, n_red, n_classes, mode;  // mode: 0 FP32, 1 FP16, 2 table taps
-  uint32_t polar, n_jobs, any_gen, pad;     // polar: directional kernels; any_gen: general-mode windows
+  uint32_t polar, n_jobs, any_gen, long_runs;  // polar: directional kernels; any_gen: general-mode windows;
+                                               // long_runs: a tile of RED_SLICE_MIN items or more
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses], class_grid[kMaxClasses];
   int32_t class_wt[kMaxClasses], class_gen[kMaxClasses];
 };
@@ -709,7 +711,8 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   int n_classes = 0;
   int class_wt[kMaxClasses] = {}, class_gen[kMaxClasses] = {};
   std::vector<int> job_cls(n_jobs);
-  uint64_t tab_entries = 0, n_rir = 0, n_items = 0, slots = 0, n_red = 0, marg_units = 0, wc_floats = 0;
+  uint64_t tab_entries = 0, n_rir = 0, n_items = 0, slots = 0, n_red = 0, marg_units = 0, wc_floats = 0,
+           max_chunks = 0;
   std::vector<uint64_t> bucket_count((size_t)kMaxClasses * kCostBuckets, 0);
   for (int j = 0; j < n_jobs; ++j) {
     Plan &p = plans[j];
@@ -736,6 +739,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     if (p.gen) wc_floats += (uint64_t)WC_STRIDE * p.wt;
     for (int t = 0; t < p.pa.n_tiles; ++t) {
       const uint64_t C = p.pa.chunks[t];
+      max_chunks = std::max(max_chunks, C);
       n_items += C * p.n_rir;
       marg_units += C * p.n_rir * (uint64_t)(p.wt / MARG_UNIT);
       if (C > 1) slots += C * p.n_rir;
@@ -769,6 +773,7 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
   }
   bp.st.n_jobs = (uint32_t)n_jobs;
   bp.st.any_gen = wc_floats > 0 ? 1u : 0u;
+  bp.st.long_runs = max_chunks >= (uint64_t)RED_SLICE_MIN ? 1u : 0u;
   bp.st.n_classes = (uint32_t)n_classes;
   bp.st.mode = precision == ISM_FP16 ? 1u : precision == ISM_FP32_LUT ? 2u : 0u;
   bp.st.polar = polar ? 1u : 0u;
@@ -990,7 +995,7 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
                               (const BatchRir *)(w + b.off_rirs), b.n_rir,
                               (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_grid,
                               b.class_wt, b.class_gen, (int)b.n_classes, b.mode == 1, b.mode == 2, b.polar != 0,
-                              (const BatchReduce *)(w + b.off_red), b.n_red,
+                              (const BatchReduce *)(w + b.off_red), b.n_red, b.long_runs != 0,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
                               (int *)(w + b.off_valid), (float *)(w + b.off_part), (float *)(w + b.off_marg),
                               (uint32_t *)(w + b.off_queue), (hipStream_t)stream,

@@ -27,6 +27,13 @@ constexpr int MAX_WINDOW = 256;
 // FP32 taps (-sigma, sigma j, cos(2 pi j / W), sin(2 pi j / W), 0 ...),
 // FP16 taps (c0, c1, ..., c5, 0, 0) of the tap's interpolant.
 constexpr int WC_STRIDE = 8;
+// Reduce kernels: a run of at least RED_SLICE_MIN partials or margins of one
+// sample is summed as RED_SLICES consecutive slices (each in order from its
+// first term, then the slice sums in order); shorter runs term by term. The
+// order depends on the run length only; launches whose runs are all shorter
+// use one thread per sample, others RED_SLICES threads per sample.
+constexpr int RED_SLICES = 4;
+constexpr int RED_SLICE_MIN = 64;
 // Window classes (cap, mode) one batch may hold: one persistent launch each.
 constexpr int kMaxBatchClasses = 8;
 // Work items per tile are capped so the per-tile chunk count fits a byte.

@@ -237,3 +237,26 @@ def test_batch_graph_replay():
         torch.cuda.synchronize()
         for e, o in zip(eager, b.outs):
             assert torch.equal(e, o), f"replay {rep} differs from the eager run"
+
+
+def test_long_runs_reduce(oracle_mod):
+    """Tiles split into 64 items or more (a fine fixed split) take the reduce
+    that sums long runs in slices on several threads: the single call agrees
+    with the oracle, and a one-job batch with the same split (which sums the
+    same runs in the same order) is bitwise equal to it. The last tiles of
+    this 4800-sample RIR hold about 1e6 estimated taps each, so 2000-tap items
+    split them into the cap of 255."""
+    import torch
+
+    w = workloads.single_rir(0)
+    room = ism.room_for(w)
+    fine = ism.Schedule(item_taps=2000.0)
+    _say("long reduce runs (items of 2000 taps)")
+    single = ism.simulate(room, w.src, w.rcv, schedule=fine)
+    alone = ism.BatchSimulator([(room, w.src, w.rcv)], schedule=fine).run()[0]
+    torch.cuda.synchronize()
+    assert torch.equal(single, alone), "one-job batch differs from the single call with the same split"
+    ref = oracle_mod.rir(room.room, room.beta, room.n_img, room.c, room.fs, room.t_max, room.t_w, w.src, w.rcv)
+    err = rel_err(single.cpu().numpy(), ref)
+    print("rel err", err.ravel(), flush=True)
+    assert np.all(err <= TOL_FP32)
