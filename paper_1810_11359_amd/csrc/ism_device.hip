@@ -1414,6 +1414,42 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const JobDev *__restr
   if (in && slice == 0 && (br.chunks > 1 || zl || zr)) *o = v;
 }
 
+// The fixed order of run_sum on one thread: the slices of a long run summed
+// one after the other (each from its first term), then added in order.
+__device__ __forceinline__ float run_sum_serial(float v, const float *__restrict__ x, size_t stride, int n) {
+  if (n < RED_SLICE_MIN) return ordered_sum(v, x, stride, n);
+  const int m = (n + RED_SLICES - 1) / RED_SLICES;
+  for (int i = 0; i < RED_SLICES; ++i) v += ordered_sum(0.0f, x + (size_t)(i * m) * stride, stride, min(m, n - i * m));
+  return v;
+}
+
+// Batch mode, tiles that were not split: their own samples are final, and
+// only the W - 1 margin samples (the first W/2 and the last W/2 - 1) take the
+// neighbours' margins, in the order of reduce_batch_kernel. One 64-lane block
+// per reduce entry.
+__global__ __launch_bounds__(64) void reduce_margins_kernel(const JobDev *__restrict__ jobs,
+                                                            const BatchReduce *__restrict__ red_tab,
+                                                            const float *__restrict__ marg) {
+  const BatchReduce br = red_tab[blockIdx.x];
+  const JobDev &jb = jobs[br.job];
+  const int n_samples = jb.ra.n_samples;
+  const int T0 = (int)br.tile * TILE;
+  const int W = (int)(2.0f * jb.ra.half_w);
+  const int LM = W / 2 - 1;
+  for (int i = (int)threadIdx.x; i < W - 1; i += 64) {
+    const int k = i < W / 2 ? i : TILE - LM + (i - W / 2);
+    if (k >= n_samples - T0) continue;
+    const bool zl = br.nprev > 0 && k < W / 2;
+    const bool zr = br.nnext > 0 && k >= TILE - LM;
+    if (!zl && !zr) continue;
+    float *o = jb.out + (size_t)br.rir * n_samples + T0 + k;
+    float v = *o;
+    if (zl) v = run_sum_serial(v, marg + (size_t)br.mprev * MARG_UNIT + LM + k, W, br.nprev);
+    if (zr) v = run_sum_serial(v, marg + (size_t)br.mnext * MARG_UNIT + (k - (TILE - LM)), W, br.nnext);
+    *o = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (called from ism_host.cpp).
 // ---------------------------------------------------------------------------
@@ -1550,9 +1586,9 @@ __global__ void queue_init_kernel(uint32_t *queue, uint4 a, uint4 b) {
 int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
                  const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
                  const uint32_t *class_grid, const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
-                 const BatchReduce *red, uint32_t n_red, bool long_runs, AxisEntry *tab, AxisOrigin *origin,
-                 int *valid, float *part, float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start,
-                 hipEvent_t ev_stop) {
+                 const BatchReduce *red, uint32_t n_red, uint32_t n_red_split, bool long_runs, AxisEntry *tab,
+                 AxisOrigin *origin, int *valid, float *part, float *marg, uint32_t *queue, hipStream_t st,
+                 hipEvent_t ev_start, hipEvent_t ev_stop) {
   hipLaunchKernelGGL(tables_batch_kernel, dim3(n_rir), dim3(256), 0, st, jobs, rirs, tab, origin, valid);
   if (hipGetLastError() != hipSuccess) return -1;
   if (any_gen) {
@@ -1582,13 +1618,19 @@ int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *r
     if (rc != 0) return -1;
   }
   if (ev_stop && hipEventRecord(ev_stop, st) != hipSuccess) return -1;
-  if (n_red > 0) {
-    // runs of RED_SLICE_MIN terms or more: RED_SLICES threads per sample
+  if (n_red_split > 0) {
+    // split tiles, whole tiles; runs of RED_SLICE_MIN terms or more: RED_SLICES threads per sample
     if (long_runs)
-      hipLaunchKernelGGL(reduce_batch_kernel<true>, dim3(n_red, TILE / RED_SAMPLES), dim3(256), 0, st, jobs, red, part,
-                         marg);
+      hipLaunchKernelGGL(reduce_batch_kernel<true>, dim3(n_red_split, TILE / RED_SAMPLES), dim3(256), 0, st, jobs, red,
+                         part, marg);
     else
-      hipLaunchKernelGGL(reduce_batch_kernel<false>, dim3(n_red, TILE / 256), dim3(256), 0, st, jobs, red, part, marg);
+      hipLaunchKernelGGL(reduce_batch_kernel<false>, dim3(n_red_split, TILE / 256), dim3(256), 0, st, jobs, red, part,
+                         marg);
+    if (hipGetLastError() != hipSuccess) return -1;
+  }
+  if (n_red > n_red_split) {  // the other tiles: their margin samples only
+    hipLaunchKernelGGL(reduce_margins_kernel, dim3(n_red - n_red_split), dim3(64), 0, st, jobs, red + n_red_split,
+                       marg);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;

@@ -32,9 +32,9 @@ int launch_dump(int wt, const RoomArgs &ra, const PlanArgs &pa, uint32_t n_items
 int launch_batch(const JobDev *jobs, int n_jobs, bool any_gen, const BatchRir *rirs, uint32_t n_rir,
                  const BatchItem *items, const uint32_t *class_first, const uint32_t *class_count,
                  const uint32_t *class_grid, const int *class_wt, const int *class_gen, int n_classes, bool half, bool lut, bool polar,
-                 const BatchReduce *red, uint32_t n_red, bool long_runs, AxisEntry *tab, AxisOrigin *origin,
-                 int *valid, float *part, float *marg, uint32_t *queue, hipStream_t st, hipEvent_t ev_start,
-                 hipEvent_t ev_stop);
+                 const BatchReduce *red, uint32_t n_red, uint32_t n_red_split, bool long_runs, AxisEntry *tab,
+                 AxisOrigin *origin, int *valid, float *part, float *marg, uint32_t *queue, hipStream_t st,
+                 hipEvent_t ev_start, hipEvent_t ev_stop);
 int launch_diffuse(const float *ism, int k_diff, float *out, int n_samples, int n_rir, double fs, double t_diff,
                    double t60, uint64_t seed, hipStream_t st);
 int launch_filter(const float *x, int n_x, const float *rir, int n_pos, int n_mic, int n_rir, float *y,
@@ -647,6 +647,7 @@ struct BatchState {  // stored in ism_batch::opaque
   uint32_t n_rir, n_red, n_classes, mode;  // mode: 0 FP32, 1 FP16, 2 table taps
   uint32_t polar, n_jobs, any_gen, long_runs;  // polar: directional kernels; any_gen: general-mode windows;
                                                // long_runs: a tile of RED_SLICE_MIN items or more
+  uint32_t n_red_split, pad;                    // reduce entries of split tiles (they come first)
   uint32_t class_first[kMaxClasses], class_count[kMaxClasses], class_grid[kMaxClasses];
   int32_t class_wt[kMaxClasses], class_gen[kMaxClasses];
 };
@@ -882,6 +883,11 @@ int plan_batch(const ism_job *jobs, int n_jobs, int precision, const ism_schedul
     rir_base += (uint64_t)p.n_rir;
   }
   if (mslot > 0xffffffffULL) return ISM_E_TOO_LARGE;
+  // split tiles first (their whole tile is summed), then the tiles whose own
+  // samples are already final (only their margin samples change)
+  const auto mid = std::stable_partition(bp.red.begin(), bp.red.end(),
+                                         [](const BatchReduce &r) { return r.chunks > 1; });
+  bp.st.n_red_split = (uint32_t)(mid - bp.red.begin());
   return ISM_OK;
 }
 
@@ -995,7 +1001,7 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
                               (const BatchRir *)(w + b.off_rirs), b.n_rir,
                               (const BatchItem *)(w + b.off_items), b.class_first, b.class_count, b.class_grid,
                               b.class_wt, b.class_gen, (int)b.n_classes, b.mode == 1, b.mode == 2, b.polar != 0,
-                              (const BatchReduce *)(w + b.off_red), b.n_red, b.long_runs != 0,
+                              (const BatchReduce *)(w + b.off_red), b.n_red, b.n_red_split, b.long_runs != 0,
                               (AxisEntry *)(w + b.off_tab), (AxisOrigin *)(w + b.off_origin),
                               (int *)(w + b.off_valid), (float *)(w + b.off_part), (float *)(w + b.off_marg),
                               (uint32_t *)(w + b.off_queue), (hipStream_t)stream,
