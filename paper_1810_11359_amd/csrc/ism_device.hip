@@ -1302,8 +1302,8 @@ __device__ __forceinline__ float ordered_sum(float v, const float *__restrict__ 
 }
 
 // A run of n terms added to v in the fixed order of the reduce (the run
-// length alone decides it): fewer than RED_SLICE_MIN terms one by one, more as
-// RED_SLICES consecutive slices, each summed in order from its first term,
+// length alone decides it): fewer than RED_SLICE_MIN terms one by one, longer
+// runs as RED_SLICES consecutive slices, each summed in order from its first term,
 // whose sums are then added to v in slice order. Launches with a long run
 // take RED_SLICES threads per sample (a block covers RED_SAMPLES samples):
 // each thread sums one slice and the sample's first thread adds the slice
