@@ -995,7 +995,8 @@ int ism_batch_run_timed(const ism_batch *batch, void *stream, void *ev_start, vo
   if (!batch) return ISM_E_INVALID_ARG;
   BatchState b;
   std::memcpy(&b, batch, sizeof(b));
-  if (!b.ws || b.n_rir == 0 || b.n_classes == 0 || b.n_classes > (uint32_t)kMaxClasses) return ISM_E_INVALID_ARG;
+  if (!b.ws || b.n_rir == 0 || b.n_classes == 0 || b.n_classes > (uint32_t)kMaxClasses || b.n_red_split > b.n_red)
+    return ISM_E_INVALID_ARG;
   char *w = (char *)(uintptr_t)b.ws;
   const int rc = launch_batch((const JobDev *)(w + b.off_jobs), (int)b.n_jobs, b.any_gen != 0,
                               (const BatchRir *)(w + b.off_rirs), b.n_rir,
